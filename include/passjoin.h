@@ -1,0 +1,147 @@
+/*
+ * passjoin.h -- C ABI of libpassjoin, an MI355X (gfx950) implementation of the Pass-Join
+ * edit-distance similarity join (G. Li, D. Deng, J. Wang, J. Feng, "Pass-Join: A
+ * Partition-based Method for Similarity Joins").
+ *
+ * Problem (Sec. 2, Definition 1): given string sets R and S and a threshold tau, report every
+ * pair <r, s> in R x S with ED(r, s) <= tau, where ED is the Levenshtein distance (unit-cost
+ * insertions, deletions, substitutions).  The self-join (R = S, Sec. 2) reports each unordered
+ * pair of distinct ids once.
+ *
+ * Method (run on the GPU, integers only, exact): even partition of every indexed string into
+ * tau+1 segments (Sec. 3.1); an inverted index keyed by (length, slot, segment) (Sec. 3.2);
+ * multi-match-aware substring selection (Sec. 4.2, Algorithm 2); extension-based verification
+ * with tau_l = i-1, tau_r = tau+1-i (Sec. 5.2, Algorithm 3) using the length-aware band and the
+ * expected-edit-distance early termination (Sec. 5.1, Lemma 4).  Strings shorter than tau+1 are
+ * not partitionable (footnote to Sec. 3.1); pairs that involve one are verified directly.
+ *
+ * Conventions for every entry point:
+ *  - Return value 0 (PJ_OK) on success, a negative PJ_E* code on failure.  On failure every
+ *    output is zeroed, nothing is leaked, and pj_last_error() describes the cause.
+ *  - Strings are raw bytes (no normalisation).  A string set is an arena: `bytes` holds all
+ *    strings back to back, `offsets[k] .. offsets[k+1]` delimits string k (id k), offsets[0] must
+ *    be 0 and offsets must be non-decreasing.  Lengths are limited to PJ_LEN_MAX, tau to
+ *    [0, PJ_TAU_MAX].
+ *  - Inputs are borrowed for the duration of the call; they are host pointers unless
+ *    pj_options.inputs_on_device is set, in which case they are device pointers on the current
+ *    HIP device.  The call returns when its results are complete.
+ *  - Outputs are owned by the caller and released with pj_pairs_free / pj_index_free.
+ *  - Results are sets with one canonical order, so a given input has exactly one correct output.
+ *  - Calls are thread-safe with respect to each other; error text and statistics are kept per
+ *    calling thread.
+ */
+#ifndef PASSJOIN_H
+#define PASSJOIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PJ_OK        0
+#define PJ_EINVAL   -1   /* null pointer, n < 0, bad offsets, tau out of [0, PJ_TAU_MAX] */
+#define PJ_ERANGE   -2   /* a string longer than PJ_LEN_MAX, a query tau outside the index */
+#define PJ_ENOMEM   -3   /* host or device allocation failed, or the memory budget is exceeded */
+#define PJ_EDEVICE  -4   /* a HIP runtime error */
+
+#define PJ_TAU_MAX  63
+#define PJ_LEN_MAX  2047
+
+/* Execution modes (pj_options.mode). */
+#define PJ_MODE_AUTO     0   /* the fastest available: currently PJ_MODE_BATCHED */
+#define PJ_MODE_PLAIN    1   /* one kernel per phase, candidates materialised, host-sized */
+#define PJ_MODE_BATCHED  2   /* length-bucketed persistent probe/verify, graph-captured phases */
+
+/* A borrowed string set (see the conventions above). */
+typedef struct {
+    int64_t n;                 /* number of strings, >= 0 */
+    const uint8_t* bytes;      /* concatenated string bytes (may be NULL when offsets[n] == 0) */
+    const int32_t* offsets;    /* n + 1 offsets */
+} pj_strings;
+
+/* Result pairs, owned by the caller.  a[k], b[k] are ids; the list is sorted by (a, b) and has
+ * no duplicates.  on_device = 1 means a and b are device pointers (pj_options.outputs_on_device).
+ * Release with pj_pairs_free. */
+typedef struct {
+    int64_t count;
+    int32_t* a;
+    int32_t* b;
+    int32_t on_device;
+} pj_pairs;
+
+/* Per-call options; a NULL pointer means all defaults (zero-initialised struct). */
+typedef struct {
+    void* hip_stream;          /* hipStream_t the work is ordered on; NULL = the null stream */
+    int32_t inputs_on_device;  /* 1: pj_strings pointers are device pointers */
+    int32_t outputs_on_device; /* 1: pj_pairs stay in device memory */
+    int32_t mode;              /* PJ_MODE_* */
+    int32_t reserved;
+    int64_t mem_budget_bytes;  /* 0 = no limit; otherwise the device bytes a call may hold */
+    const char* tune_cache;    /* autotune cache file (read, and written when tuning); NULL = none */
+} pj_options;
+
+/* Counters and phase times of the last call made on the calling thread. */
+typedef struct {
+    int64_t strings;       /* strings in the probe and indexed sets */
+    int64_t index_entries; /* (string, slot) entries in the segment index */
+    int64_t selected;      /* substrings selected by the multi-match windows and looked up */
+    int64_t hits;          /* selected substrings that found a non-empty inverted list */
+    int64_t candidates;    /* (y, x, i, p) candidates after the visiting-order filter */
+    int64_t cells;         /* DP cells evaluated by extension verification (Sec. 5.1 band) */
+    int64_t accepted;      /* candidates that passed, before deduplication */
+    int64_t side_pairs;    /* pairs examined directly because a string is shorter than tau+1 */
+    int64_t pairs;         /* pairs reported */
+    double ms_upload, ms_index, ms_probe, ms_verify, ms_output, ms_total;
+} pj_stats;
+
+/* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with
+ * ED(S[a], S[b]) <= tau, sorted by (a, b).  Pairs are found from the later string in
+ * (length, id) order, which yields the same set as the paper's (length, bytes) order. */
+int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out);
+
+/* Join of two sets (Definition 1, Sec. 3.2): every (r, s) with ED(R[r], S[s]) <= tau, sorted by
+ * (r, s).  S is indexed and each r probes the lengths |r|-tau .. |r|+tau. */
+int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
+            pj_pairs* out);
+
+/* Opaque device-resident index of one string set for every tau in [tau_min, tau_max]: the even
+ * partition segments of Sec. 3.1 in inverted lists keyed by (length, slot, segment), Sec. 3.2.
+ * Read-only after build; may be shared by concurrent pj_query calls. */
+typedef struct pj_index pj_index;
+
+/* Builds an index of S for every tau in [tau_min, tau_max] (0 <= tau_min <= tau_max <=
+ * PJ_TAU_MAX).  S is copied to the device; the caller may release it after the call. */
+int pj_build_index(const pj_strings* S, int32_t tau_min, int32_t tau_max, const pj_options* opt,
+                   pj_index** out);
+
+/* Number of strings and the tau range of an index (any pointer may be NULL). */
+int pj_index_info(const pj_index* idx, int64_t* n, int32_t* tau_min, int32_t* tau_max,
+                  int64_t* device_bytes);
+
+/* Queries an index: query q (0 <= q < Q->n) with its own threshold taus[q] (a host array, each
+ * in the index's range) is joined against the indexed set as in pj_join.  Pairs are
+ * (q, s) sorted by (q, s). */
+int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, const pj_options* opt,
+             pj_pairs* out);
+
+/* Releases pairs (host or device memory as recorded in on_device) and zeroes the struct. */
+void pj_pairs_free(pj_pairs* pairs);
+
+/* Releases an index; NULL is ignored. */
+void pj_index_free(pj_index* idx);
+
+/* Text describing the last failure on the calling thread ("" if none). */
+const char* pj_last_error(void);
+
+/* Copies the statistics of the last successful call on the calling thread. */
+int pj_last_stats(pj_stats* out);
+
+/* Library version string. */
+const char* pj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PASSJOIN_H */

@@ -1,0 +1,301 @@
+"""MI355X (gfx950) Pass-Join edit-distance similarity join.
+
+Thin ctypes binding of libpassjoin (C ABI declared in include/passjoin.h).  It only marshals
+arguments: every step of the join runs in the library's HIP kernels.  If the library has not
+been built, every call raises :class:`PassJoinError` -- there is no CPU fallback.
+
+String sets are given as any of:
+  * an object with ``chars`` (uint8) and ``offsets`` (int32, n+1) numpy arrays (host memory);
+  * a ``(chars, offsets)`` tuple of numpy arrays (host memory);
+  * a ``(chars, offsets)`` tuple of torch tensors on a HIP device (device memory; the work is
+    ordered on torch's current stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "PassJoinError", "load", "pj_self_join", "pj_join", "pj_build_index", "pj_query",
+    "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
+    "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpassjoin.so")
+
+PJ_OK, PJ_EINVAL, PJ_ERANGE, PJ_ENOMEM, PJ_EDEVICE = 0, -1, -2, -3, -4
+PJ_TAU_MAX, PJ_LEN_MAX = 63, 2047
+MODE_AUTO, MODE_PLAIN, MODE_BATCHED = 0, 1, 2
+_CODES = {PJ_EINVAL: "EINVAL", PJ_ERANGE: "ERANGE", PJ_ENOMEM: "ENOMEM", PJ_EDEVICE: "EDEVICE"}
+
+
+class PassJoinError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PjStrings(C.Structure):
+    _fields_ = [("n", C.c_int64), ("bytes", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+class PjPairs(C.Structure):
+    _fields_ = [("count", C.c_int64), ("a", C.c_void_p), ("b", C.c_void_p),
+                ("on_device", C.c_int32)]
+
+
+class PjOptions(C.Structure):
+    _fields_ = [("hip_stream", C.c_void_p), ("inputs_on_device", C.c_int32),
+                ("outputs_on_device", C.c_int32), ("mode", C.c_int32), ("reserved", C.c_int32),
+                ("mem_budget_bytes", C.c_int64), ("tune_cache", C.c_char_p)]
+
+
+class PjStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("strings", "index_entries", "selected", "hits",
+                                         "candidates", "cells", "accepted", "side_pairs",
+                                         "pairs")] + \
+               [(k, C.c_double) for k in ("ms_upload", "ms_index", "ms_probe", "ms_verify",
+                                          "ms_output", "ms_total")]
+
+
+_lib = None
+
+
+def load():
+    """Loads libpassjoin.so (built in-tree by paper_1111_7171_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PassJoinError(PJ_EDEVICE, f"{LIB_PATH} is not built; run "
+                                "`python -m paper_1111_7171_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        sp, pp, op = C.POINTER(PjStrings), C.POINTER(PjPairs), C.POINTER(PjOptions)
+        lib.pj_self_join.argtypes = [sp, C.c_int32, op, pp]
+        lib.pj_self_join.restype = C.c_int
+        lib.pj_join.argtypes = [sp, sp, C.c_int32, op, pp]
+        lib.pj_join.restype = C.c_int
+        lib.pj_build_index.argtypes = [sp, C.c_int32, C.c_int32, op, C.POINTER(C.c_void_p)]
+        lib.pj_build_index.restype = C.c_int
+        lib.pj_index_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        lib.pj_index_info.restype = C.c_int
+        lib.pj_query.argtypes = [C.c_void_p, sp, C.c_void_p, op, pp]
+        lib.pj_query.restype = C.c_int
+        lib.pj_pairs_free.argtypes = [pp]
+        lib.pj_pairs_free.restype = None
+        lib.pj_index_free.argtypes = [C.c_void_p]
+        lib.pj_index_free.restype = None
+        lib.pj_last_error.argtypes = []
+        lib.pj_last_error.restype = C.c_char_p
+        lib.pj_last_stats.argtypes = [C.POINTER(PjStats)]
+        lib.pj_last_stats.restype = C.c_int
+        lib.pj_version.argtypes = []
+        lib.pj_version.restype = C.c_char_p
+        _lib = lib
+    return _lib
+
+
+def pj_last_error() -> str:
+    return load().pj_last_error().decode()
+
+
+def pj_version() -> str:
+    return load().pj_version().decode()
+
+
+def pj_last_stats() -> dict:
+    st = PjStats()
+    load().pj_last_stats(C.byref(st))
+    return {k: getattr(st, k) for k, _ in PjStats._fields_}
+
+
+def _check(rc: int):
+    if rc != PJ_OK:
+        raise PassJoinError(rc, pj_last_error())
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class _Marshalled:
+    """A PjStrings view of a string set plus whatever keeps its memory alive."""
+
+    def __init__(self, strings):
+        if hasattr(strings, "chars") and hasattr(strings, "offsets"):
+            chars, offs = strings.chars, strings.offsets
+        else:
+            chars, offs = strings
+        self.on_device = _is_torch(offs) and offs.is_cuda
+        if self.on_device:
+            import torch
+            if chars.dtype != torch.uint8 or offs.dtype != torch.int32:
+                raise PassJoinError(PJ_EINVAL, "device strings must be uint8 chars, int32 offsets")
+            if not (chars.is_contiguous() and offs.is_contiguous()):
+                raise PassJoinError(PJ_EINVAL, "device strings must be contiguous")
+            self.keep = (chars, offs)
+            self.s = PjStrings(offs.numel() - 1, chars.data_ptr() if chars.numel() else None,
+                               offs.data_ptr())
+        else:
+            if _is_torch(chars):
+                chars, offs = chars.numpy(), offs.numpy()
+            chars = np.ascontiguousarray(chars, dtype=np.uint8)
+            offs = np.ascontiguousarray(offs, dtype=np.int32)
+            if offs.ndim != 1 or offs.size < 1:
+                raise PassJoinError(PJ_EINVAL, "offsets must be a 1-D array of n+1 entries")
+            self.keep = (chars, offs)
+            self.s = PjStrings(offs.size - 1, chars.ctypes.data if chars.size else None,
+                               offs.ctypes.data)
+
+
+def _options(on_device: bool, outputs_on_device: bool, mode: int, mem_budget: int,
+             stream, tune_cache: str | None) -> PjOptions:
+    o = PjOptions()
+    o.inputs_on_device = 1 if on_device else 0
+    o.outputs_on_device = 1 if outputs_on_device else 0
+    o.mode = mode
+    o.mem_budget_bytes = int(mem_budget)
+    o.tune_cache = tune_cache.encode() if tune_cache else None
+    if stream is None and on_device:
+        import torch
+        stream = torch.cuda.current_stream()
+    if stream is not None:
+        o.hip_stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    return o
+
+
+@dataclass
+class DevicePairs:
+    """Result pairs left in device memory (outputs_on_device=True).  Call free() when done."""
+    raw: PjPairs
+
+    @property
+    def count(self) -> int:
+        return int(self.raw.count)
+
+    def to_numpy(self) -> np.ndarray:
+        m = self.count
+        out = np.empty((m, 2), dtype=np.int32)
+        if m:
+            for col, ptr in ((0, self.raw.a), (1, self.raw.b)):
+                host = np.empty(m, dtype=np.int32)
+                _hip_d2h(host, ptr)
+                out[:, col] = host
+        return out
+
+    def free(self):
+        load().pj_pairs_free(C.byref(self.raw))
+
+
+_hip = None
+
+
+def _hip_d2h(host: np.ndarray, dev_ptr: int):
+    """Copies device memory into a host array with the HIP runtime's hipMemcpy."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    rc = _hip.hipMemcpy(host.ctypes.data, dev_ptr, host.nbytes, 2)   # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise PassJoinError(PJ_EDEVICE, f"hipMemcpy failed ({rc})")
+
+
+def _take_pairs(raw: PjPairs, outputs_on_device: bool):
+    if outputs_on_device:
+        return DevicePairs(raw)
+    m = int(raw.count)
+    out = np.empty((m, 2), dtype=np.int32)
+    if m:
+        out[:, 0] = np.ctypeslib.as_array(C.cast(raw.a, C.POINTER(C.c_int32)), shape=(m,))
+        out[:, 1] = np.ctypeslib.as_array(C.cast(raw.b, C.POINTER(C.c_int32)), shape=(m,))
+    load().pj_pairs_free(C.byref(raw))
+    return out
+
+
+def pj_self_join(strings, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = False,
+                 mem_budget: int = 0, stream=None, tune_cache: str | None = None):
+    """All pairs (a, b), a < b, of one string set with ED <= tau, as an int32 [m, 2] array
+    sorted by (a, b)."""
+    lib = load()
+    s = _Marshalled(strings)
+    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache)
+    raw = PjPairs()
+    _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
+    return _take_pairs(raw, outputs_on_device)
+
+
+def pj_join(R, S, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = False,
+            mem_budget: int = 0, stream=None, tune_cache: str | None = None):
+    """All (r, s) with ED(R[r], S[s]) <= tau, int32 [m, 2] sorted by (r, s)."""
+    lib = load()
+    r = _Marshalled(R)
+    s = _Marshalled(S)
+    if r.on_device != s.on_device:
+        raise PassJoinError(PJ_EINVAL, "R and S must both be on the host or both on the device")
+    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache)
+    raw = PjPairs()
+    _check(lib.pj_join(C.byref(r.s), C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
+    return _take_pairs(raw, outputs_on_device)
+
+
+class Index:
+    """A device-resident index (pj_build_index); released by free() or garbage collection."""
+
+    def __init__(self, handle: int):
+        self.handle = C.c_void_p(handle)
+
+    def info(self) -> dict:
+        return pj_index_info(self)
+
+    def free(self):
+        if self.handle:
+            load().pj_index_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pj_build_index(strings, tau_min: int, tau_max: int, *, mem_budget: int = 0,
+                   stream=None) -> Index:
+    lib = load()
+    s = _Marshalled(strings)
+    o = _options(s.on_device, False, MODE_AUTO, mem_budget, stream, None)
+    h = C.c_void_p()
+    _check(lib.pj_build_index(C.byref(s.s), int(tau_min), int(tau_max), C.byref(o), C.byref(h)))
+    return Index(h.value)
+
+
+def pj_index_info(index: Index) -> dict:
+    n, tmin, tmax, nb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+    _check(load().pj_index_info(index.handle, C.byref(n), C.byref(tmin), C.byref(tmax),
+                                C.byref(nb)))
+    return {"n": n.value, "tau_min": tmin.value, "tau_max": tmax.value, "device_bytes": nb.value}
+
+
+def pj_index_free(index: Index):
+    index.free()
+
+
+def pj_query(index: Index, queries, taus, *, outputs_on_device: bool = False,
+             mem_budget: int = 0, stream=None):
+    """(q, s) pairs with ED(Q[q], S[s]) <= taus[q], int32 [m, 2] sorted by (q, s)."""
+    lib = load()
+    q = _Marshalled(queries)
+    t = np.ascontiguousarray(taus, dtype=np.int32)
+    if t.size != q.s.n:
+        raise PassJoinError(PJ_EINVAL, "one tau per query is required")
+    o = _options(q.on_device, outputs_on_device, MODE_AUTO, mem_budget, stream, None)
+    raw = PjPairs()
+    _check(lib.pj_query(index.handle, C.byref(q.s), t.ctypes.data if t.size else None,
+                        C.byref(o), C.byref(raw)))
+    return _take_pairs(raw, outputs_on_device)

@@ -1,0 +1,901 @@
+// pj_device.hip -- gfx950 kernels of libpassjoin (plain one-kernel-per-phase path).
+//
+// Everything here is integer work on wave64: no MFMA (nothing is a dense contraction).  The
+// phases are HBM/L2-bound streaming (arena packing, index build, radix sort), random-access
+// lookups (probe) and integer-VALU dynamic programming (verification).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pj_internal.h"
+#include "pj_device_common.h"
+
+namespace pj {
+
+// ------------------------------------------------------------------------------------------
+// Wave / block primitives (wave64, 256-thread blocks)
+// ------------------------------------------------------------------------------------------
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+template <typename T>
+__device__ inline T wave_incl_scan(T v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block; *total receives the block sum.
+template <typename T>
+__device__ inline T block_excl_scan(T v, T* s_wave, T* total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = wave_incl_scan(v);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        T s = s_wave[k];
+        if (k < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
+// ------------------------------------------------------------------------------------------
+// Device-wide exclusive scan (reduce -> scan partials -> apply), 2048 elements per block
+// ------------------------------------------------------------------------------------------
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI* __restrict__ in, uint64_t n,
+                                                        TO* __restrict__ partial)
+{
+    __shared__ TO s_wave[kWaves];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    TO sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) sum += (TO)in[base + k];
+    TO tot;
+    block_excl_scan<TO>(sum, s_wave, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_partials(TO* __restrict__ partial, uint64_t nb)
+{
+    __shared__ TO s_wave[kWaves];
+    __shared__ TO s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint64_t c = 0; c < nb; c += kBlock) {
+        uint64_t k = c + threadIdx.x;
+        TO v = (k < nb) ? partial[k] : 0;
+        TO tot;
+        TO ex = block_excl_scan<TO>(v, s_wave, &tot);
+        TO carry = s_carry;
+        if (k < nb) partial[k] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const TI* __restrict__ in, TO* __restrict__ out,
+                                                       uint64_t n, const TO* __restrict__ partial)
+{
+    __shared__ TO s_wave[kWaves];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    TO v[kScanItems];
+    TO sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? (TO)in[base + k] : 0;
+        sum += v[k];
+    }
+    TO tot;
+    TO run = block_excl_scan<TO>(sum, s_wave, &tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    // the thread holding the last element writes the total
+    if (n > 0 && base <= n - 1 && n - 1 < base + kScanItems) out[n] = run;
+}
+
+size_t scan_tmp_bytes(uint64_t n)
+{
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb + 1) * sizeof(unsigned long long);
+}
+
+template <typename TI, typename TO>
+static hipError_t scan_impl(const TI* in, TO* out, uint64_t n, void* tmp, size_t tmp_bytes,
+                            hipStream_t s)
+{
+    if (n == 0) return hipMemsetAsync(out, 0, sizeof(TO), s);
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (tmp_bytes < (nb + 1) * sizeof(TO)) return hipErrorInvalidValue;
+    TO* partial = (TO*)tmp;
+    hipLaunchKernelGGL((k_scan_reduce<TI, TO>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, partial);
+    hipLaunchKernelGGL((k_scan_partials<TO>), dim3(1), dim3(kBlock), 0, s, partial, nb);
+    hipLaunchKernelGGL((k_scan_apply<TI, TO>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+                       (const TO*)partial);
+    return hipGetLastError();
+}
+
+hipError_t scan_u32_to_u32(const uint32_t* in, uint32_t* out, uint64_t n, void* tmp,
+                           size_t tmp_bytes, hipStream_t s)
+{
+    return scan_impl<uint32_t, uint32_t>(in, out, n, tmp, tmp_bytes, s);
+}
+
+hipError_t scan_u32_to_u64(const uint32_t* in, unsigned long long* out, uint64_t n, void* tmp,
+                           size_t tmp_bytes, hipStream_t s)
+{
+    return scan_impl<uint32_t, unsigned long long>(in, out, n, tmp, tmp_bytes, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  A block owns a tile of 16 rounds x 256 keys; within a
+// round, keys with equal digits are ranked by wave ballots (8 ballots per key find its peers)
+// and across waves/rounds by LDS counters, so every pass is stable.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kRadixRounds = 16;
+constexpr int kRadixTile = kBlock * kRadixRounds;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const K* __restrict__ keys, uint64_t n,
+                                                       int shift, uint32_t* __restrict__ hist,
+                                                       uint32_t nblocks)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+#pragma unroll 4
+    for (int r = 0; r < kRadixRounds; ++r) {
+        uint64_t idx = base + (uint64_t)r * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vals,
+                                                          uint64_t n, int shift,
+                                                          const uint32_t* __restrict__ offsets,
+                                                          uint32_t nblocks,
+                                                          K* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out)
+{
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int w = threadIdx.x >> 6;
+    cnt[threadIdx.x] = offsets[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) wcnt[k][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        uint64_t idx = base + (uint64_t)r * kBlock + threadIdx.x;
+        bool valid = idx < n;
+        K key = valid ? keys[idx] : (K)0;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bb = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        bool leader = valid && ((peers & lanemask_lt()) == 0);
+        if (leader) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = cnt[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+            keys_out[pos] = key;
+            if (vals) vals_out[pos] = vals[idx];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            add += wcnt[k][threadIdx.x];
+            wcnt[k][threadIdx.x] = 0;
+        }
+        cnt[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+size_t radix_tmp_bytes(uint64_t n)
+{
+    uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t h = 256 * nb;
+    // histogram + its scan + scan partials
+    return (size_t)(2 * (h + 1)) * sizeof(uint32_t) + scan_tmp_bytes(h) + 256;
+}
+
+template <typename K>
+static hipError_t radix_impl(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt,
+                             uint64_t n, int bits, void* tmp, size_t tmp_bytes, bool* in_alt,
+                             hipStream_t s)
+{
+    *in_alt = false;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t h = 256 * nb;
+    if (tmp_bytes < radix_tmp_bytes(n)) return hipErrorInvalidValue;
+    uint32_t* hist = (uint32_t*)tmp;
+    uint32_t* offs = hist + (h + 1);
+    void* stmp = (void*)(offs + (h + 1));
+    size_t stmp_bytes = tmp_bytes - (size_t)(2 * (h + 1)) * sizeof(uint32_t);
+    K* kin = keys; uint32_t* vin = vals;
+    K* kout = keys_alt; uint32_t* vout = vals_alt;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n,
+                           shift, hist, (uint32_t)nb);
+        hipError_t e = scan_u32_to_u32(hist, offs, h, stmp, stmp_bytes, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)nb), dim3(kBlock), 0, s, kin,
+                           vin, n, shift, offs, (uint32_t)nb, kout, vout);
+        K* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+        *in_alt = !*in_alt;
+    }
+    return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                          uint64_t n, int bits, void* tmp, size_t tmp_bytes, bool* in_alt,
+                          hipStream_t s)
+{
+    return radix_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, tmp_bytes, in_alt, s);
+}
+
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                          uint64_t n, int bits, void* tmp, size_t tmp_bytes, bool* in_alt,
+                          hipStream_t s)
+{
+    return radix_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, tmp_bytes, in_alt, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// String arena: length histogram + validation, (length, id) keys, packing
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_length_hist(const int32_t* __restrict__ offs,
+                                                        int64_t n, int32_t* __restrict__ lcount,
+                                                        int32_t* __restrict__ err)
+{
+    __shared__ int32_t h[kLenTab];
+    for (int k = threadIdx.x; k < kLenTab; k += kBlock) h[k] = 0;
+    __syncthreads();
+    int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t e = 0;
+    if (id < n) {
+        int32_t a = offs[id], b = offs[id + 1];
+        int32_t l = b - a;
+        if (id == 0 && a != 0) e |= 1;
+        if (l < 0) e |= 2;
+        else if (l > kLenMax) e |= 4;
+        else atomicAdd(&h[l], 1);
+    }
+    if (e) atomicOr(err, e);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kLenTab; k += kBlock)
+        if (h[k]) atomicAdd(&lcount[k], h[k]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_len_keys(const int32_t* __restrict__ offs, int64_t n,
+                                                     uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals)
+{
+    int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id < n) {
+        keys[id] = (uint32_t)(offs[id + 1] - offs[id]);
+        vals[id] = (uint32_t)id;
+    }
+}
+
+// One wave per sorted position: copies the string into its padded slot of the sorted arena.
+__global__ __launch_bounds__(kBlock) void k_pack_arena(const uint8_t* __restrict__ bytes,
+                                                       const int32_t* __restrict__ offs,
+                                                       const int32_t* __restrict__ perm, int64_t n,
+                                                       const int32_t* __restrict__ lenstart,
+                                                       const int64_t* __restrict__ gbase,
+                                                       uint8_t* __restrict__ sarena,
+                                                       uint16_t* __restrict__ slen)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t gstep = ((int64_t)gridDim.x * kBlock) >> 6;
+    for (; g < n; g += gstep) {
+        int32_t id = perm[g];
+        int32_t a = offs[id];
+        int32_t l = offs[id + 1] - a;
+        uint8_t* dst = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
+        int32_t st = (int32_t)stride_of(l);
+        for (int32_t k = lane; k < st; k += 64) dst[k] = (k < l) ? bytes[a + k] : (uint8_t)0;
+        if (lane == 0) slen[g] = (uint16_t)l;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Segment index
+// ------------------------------------------------------------------------------------------
+
+// One thread per (indexed string, slot): emits (key, g) at a position grouped by (l, i) and
+// ordered by g inside the group, so a stable sort by key keeps lists in ascending g.
+__global__ __launch_bounds__(kBlock) void k_emit_segments(const uint8_t* __restrict__ sarena,
+                                                          const uint16_t* __restrict__ slen,
+                                                          const int32_t* __restrict__ lenstart,
+                                                          const int64_t* __restrict__ gbase,
+                                                          const int64_t* __restrict__ ebase,
+                                                          int tau, int64_t g_first,
+                                                          int64_t g_count, Div div,
+                                                          uint64_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals)
+{
+    const int T1 = tau + 1;
+    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g_count * T1) return;
+    int64_t g = g_first + t / T1;
+    int i = (int)(t % T1) + 1;
+    int l = slen[g];
+    Seg sg = partition_seg(l, i, tau, div);
+    const uint8_t* s = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
+    uint64_t h = seg_hash(s + sg.p - 1, sg.len);
+    int64_t nl = lenstart[l + 1] - lenstart[l];
+    int64_t e = ebase[l] + (int64_t)(i - 1) * nl + (g - lenstart[l]);
+    keys[e] = make_key(l, i, tau, h);
+    vals[e] = (uint32_t)g;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_heads(const uint64_t* __restrict__ keys, int64_t E,
+                                                       uint32_t* __restrict__ flags)
+{
+    int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < E) flags[e] = (e == 0 || keys[e] != keys[e - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_clear_table(uint4* __restrict__ table, uint64_t slots)
+{
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < slots) table[k] = make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
+}
+
+// runstart[r] = first entry of list r (runid[e] = number of list heads before e).
+__global__ __launch_bounds__(kBlock) void k_scatter_runstart(const uint32_t* __restrict__ flags,
+                                                             const uint32_t* __restrict__ runid,
+                                                             int64_t E,
+                                                             uint32_t* __restrict__ runstart)
+{
+    int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < E && flags[e]) runstart[runid[e]] = (uint32_t)e;
+}
+
+// One thread per list: inserts key -> (start, count) into the table by linear probing.
+__global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ runstart,
+                                                        uint32_t nruns, uint32_t E,
+                                                        uint4* __restrict__ table, uint64_t mask)
+{
+    uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nruns) return;
+    uint32_t start = runstart[r];
+    uint32_t end = (r + 1 < nruns) ? runstart[r + 1] : E;
+    uint64_t key = keys[start];
+    uint64_t slot = table_slot(key) & mask;
+    while (true) {
+        unsigned long long* kp = reinterpret_cast<unsigned long long*>(&table[slot]);
+        unsigned long long prev = atomicCAS(kp, (unsigned long long)kEmptyKey,
+                                            (unsigned long long)key);
+        if (prev == (unsigned long long)kEmptyKey) {
+            table[slot].z = start;
+            table[slot].w = end - start;
+            return;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Probe: multi-match substring selection + bucket lookup (Sec. 4.2, Algorithm 2)
+// ------------------------------------------------------------------------------------------
+
+// One thread per (probe string x, probed length l, slot i).  The thread walks the window
+// [bot_i, top_i] with a rolling hash of x[p, l_i], looks each substring up, trims the list to
+// the members visited before x (self-join, l == |x|), and appends non-empty lookups as hits.
+__global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int T1 = P.tau + 1;
+    bool valid = t < P.threads;
+    uint64_t my_sel = 0;
+    int n = 0, l = 0, i = 0, lo = 1, hi = 0;
+    uint32_t gx = 0;
+    Seg sg{1, 0};
+    const uint8_t* x = nullptr;
+    if (valid) {
+        uint64_t per = (uint64_t)P.nl * T1;
+        gx = P.g_begin + (uint32_t)(t / per);
+        uint32_t rem = (uint32_t)(t % per);
+        i = (int)(rem % T1) + 1;
+        int dl = (int)(rem / T1);
+        n = P.x_slen[gx];
+        l = P.self ? n - dl : n - P.tau + dl;
+        // substrings selected for L_l^1 .. L_l^{tau+1}: the Lemma 2 count, whether or not
+        // strings of length l exist (Algorithm 1 selects for every l in the length window)
+        if (l >= T1 && i == 1) {
+            const int d = n - l;
+            my_sel = (uint64_t)((P.tau * P.tau - d * d) / 2 + P.tau + 1);
+        }
+        valid = (l >= T1) && (l >= P.ymin) && (l <= P.ymax) &&
+                (P.y_lenstart[l + 1] > P.y_lenstart[l]);
+        if (valid) {
+            sg = partition_seg(l, i, P.tau, div);
+            multimatch_window(n, l, P.tau, i, sg, &lo, &hi);
+            x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
+        }
+    }
+    uint64_t my_cand = 0;
+    uint64_t h = 0, top = 0;
+    if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
+    for (int s = 0; s < T1; ++s) {
+        int p = lo + s;
+        bool active = valid && p <= hi;
+        if (__ballot(active) == 0) break;
+        uint32_t start = 0, count = 0;
+        if (active) {
+            const uint8_t* w = x + p - 1;
+            if (s == 0) h = seg_hash(w, sg.len);
+            else h = roll_hash(h, w[-1], w[sg.len - 1], top);
+            uint64_t key = make_key(l, i, P.tau, h);
+            if (table_lookup(P.table, P.mask, key, &start, &count)) {
+                if (P.self && l == n) {
+                    // keep members with g < gx (lists are ascending in g)
+                    uint32_t a = 0, b = count;
+                    while (a < b) {
+                        uint32_t m = (a + b) >> 1;
+                        if (P.vals[start + m] < gx) a = m + 1; else b = m;
+                    }
+                    count = a;
+                }
+            } else {
+                count = 0;
+            }
+        }
+        bool found = active && count > 0;
+        uint64_t fm = __ballot(found);
+        if (fm) {
+            int leader = __ffsll((unsigned long long)fm) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&P.counters[0], (unsigned long long)__popcll(fm));
+            base = __shfl(base, leader, 64);
+            if (found) {
+                uint64_t idx = base + (uint64_t)__popcll(fm & lanemask_lt());
+                if (idx < P.hit_cap) {
+                    Hit hh;
+                    hh.gx = gx; hh.start = start; hh.count = count;
+                    hh.meta = (uint32_t)(p - 1) | ((uint32_t)(i - 1) << 11) | ((uint32_t)l << 17);
+                    P.hits[idx] = hh;
+                }
+                my_cand += count;
+            }
+        }
+    }
+    my_cand = wave_sum(my_cand);
+    my_sel = wave_sum(my_sel);
+    if (lane == 0) {
+        if (my_cand) atomicAdd(&P.counters[1], (unsigned long long)my_cand);
+        if (my_sel) atomicAdd(&P.counters[2], (unsigned long long)my_sel);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Verify: extension-based verification (Sec. 5.2, Algorithm 3), lane per candidate, candidates
+// distributed over lanes by a load-balanced search over the hits' prefix sums.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kVerifyChunk = 1024;
+
+template <int MAXW>
+__global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
+{
+    __shared__ unsigned long long sP[kVerifyChunk + 1];
+    __shared__ uint64_t s_h0;
+    const int lane = threadIdx.x & 63;
+    const int tau = V.tau;
+    uint64_t my_cells = 0, my_miss = 0;
+    const uint64_t nchunks = (V.ncand + kVerifyChunk - 1) / kVerifyChunk;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t c0 = ch * kVerifyChunk;
+        const uint64_t c1 = (c0 + kVerifyChunk < V.ncand) ? c0 + kVerifyChunk : V.ncand;
+        if (threadIdx.x == 0) {
+            uint64_t a = 0, b = V.nhits - 1;      // largest h with prefix[h] <= c0
+            while (a < b) {
+                uint64_t m = (a + b + 1) >> 1;
+                if (V.prefix[m] <= c0) a = m; else b = m - 1;
+            }
+            s_h0 = a;
+        }
+        __syncthreads();
+        const uint64_t h0 = s_h0;
+        for (int k = threadIdx.x; k <= kVerifyChunk; k += kBlock)
+            sP[k] = (h0 + k <= V.nhits) ? V.prefix[h0 + k] : ~0ull;
+        __syncthreads();
+        for (uint64_t c = c0 + threadIdx.x; c - c0 < (uint64_t)kVerifyChunk; c += kBlock) {
+            bool pass = false;
+            uint32_t gx = 0, gy = 0;
+            if (c < c1) {
+                int a = 0, b = kVerifyChunk;
+                while (a < b) {
+                    int m = (a + b + 1) >> 1;
+                    if (sP[m] <= c) a = m; else b = m - 1;
+                }
+                const Hit hit = V.hits[h0 + a];
+                const uint64_t mem = c - sP[a];
+                gx = hit.gx;
+                gy = V.vals[hit.start + mem];
+                const int p = (int)(hit.meta & 2047u) + 1;
+                const int i = (int)((hit.meta >> 11) & 63u) + 1;
+                const int l = (int)(hit.meta >> 17);
+                const int n = V.x_slen[gx];
+                const uint8_t* x = V.x_arena + V.x_gbase[n] +
+                                   (int64_t)(gx - V.x_lenstart[n]) * stride_of(n);
+                const uint8_t* y = V.y_arena + V.y_gbase[l] +
+                                   (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
+                const Seg sg = partition_seg(l, i, tau, div);
+                bool same = true;
+                for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
+                if (!same) {
+                    my_miss += 1;
+                } else {
+                    int cl = 0;
+                    const int tl = i - 1, tr = tau + 1 - i;
+                    int dl = vsp_global<MAXW>(y, sg.p - 1, x, p - 1, tl, &cl);
+                    my_cells += cl;
+                    if (dl <= tl) {
+                        int cr = 0;
+                        const int ry = sg.p - 1 + sg.len, rx = p - 1 + sg.len;
+                        int dr = vsp_global<MAXW>(y + ry, l - ry, x + rx, n - rx, tr, &cr);
+                        my_cells += cr;
+                        pass = dr <= tr;
+                    }
+                }
+            }
+            uint64_t pm = __ballot(pass);
+            if (pm) {
+                int leader = __ffsll((unsigned long long)pm) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&V.counters[3], (unsigned long long)__popcll(pm));
+                base = __shfl(base, leader, 64);
+                if (pass) {
+                    uint64_t idx = base + (uint64_t)__popcll(pm & lanemask_lt());
+                    if (idx < V.out_cap) V.out[idx] = ((uint64_t)gx << 32) | gy;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    my_cells = wave_sum(my_cells);
+    my_miss = wave_sum(my_miss);
+    if (lane == 0) {
+        if (my_cells) atomicAdd(&V.counters[4], (unsigned long long)my_cells);
+        if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Short strings (length <= tau): not partitionable (footnote to Sec. 3.1).  One block per short
+// string y of the indexed set; its partners are the probe-set strings in the length window
+// [|y| - tau, |y| + tau] -- a contiguous range of sorted positions.  In a self-join a pair of
+// two short strings is taken once (from the later one).
+// ------------------------------------------------------------------------------------------
+
+template <int MAXW>
+__global__ __launch_bounds__(kBlock) void k_short(const uint8_t* __restrict__ x_arena,
+                                                  const uint16_t* __restrict__ x_slen,
+                                                  const int32_t* __restrict__ x_lenstart,
+                                                  const int64_t* __restrict__ x_gbase,
+                                                  int x_lmax,
+                                                  const uint8_t* __restrict__ y_arena,
+                                                  const uint16_t* __restrict__ y_slen,
+                                                  const int32_t* __restrict__ y_lenstart,
+                                                  const int64_t* __restrict__ y_gbase,
+                                                  uint32_t y_first, uint32_t y_count, int tau,
+                                                  int self, uint64_t* __restrict__ out,
+                                                  uint64_t out_cap,
+                                                  unsigned long long* __restrict__ counters)
+{
+    const int lane = threadIdx.x & 63;
+    for (uint32_t yi = blockIdx.x; yi < y_count; yi += gridDim.x) {
+        const uint32_t gy = y_first + yi;
+        const int ly = y_slen[gy];
+        const uint8_t* y = y_arena + y_gbase[ly] + (int64_t)(gy - y_lenstart[ly]) * stride_of(ly);
+        const int lo_len = ly - tau < 0 ? 0 : ly - tau;
+        int hi_len = ly + tau;
+        if (hi_len > x_lmax) hi_len = x_lmax;
+        if (hi_len < lo_len) continue;
+        const uint32_t g0 = (uint32_t)x_lenstart[lo_len], g1 = (uint32_t)x_lenstart[hi_len + 1];
+        uint64_t examined = 0;
+        for (uint32_t base = g0; base < g1; base += kBlock) {
+            uint32_t gx = base + threadIdx.x;
+            bool pass = false;
+            if (gx < g1) {
+                const int lx = x_slen[gx];
+                bool take = !(self && lx <= tau && gx >= gy);
+                if (take) {
+                    const uint8_t* x = x_arena + x_gbase[lx] +
+                                       (int64_t)(gx - x_lenstart[lx]) * stride_of(lx);
+                    int c = 0;
+                    pass = vsp_global<MAXW>(y, ly, x, lx, tau, &c) <= tau;
+                    examined += 1;
+                }
+            }
+            uint64_t pm = __ballot(pass);
+            if (pm) {
+                int leader = __ffsll((unsigned long long)pm) - 1;
+                unsigned long long b = 0;
+                if (lane == leader) b = atomicAdd(&counters[3], (unsigned long long)__popcll(pm));
+                b = __shfl(b, leader, 64);
+                if (pass) {
+                    uint64_t idx = b + (uint64_t)__popcll(pm & lanemask_lt());
+                    if (idx < out_cap) out[idx] = ((uint64_t)gx << 32) | gy;
+                }
+            }
+        }
+        examined = wave_sum(examined);
+        if (lane == 0 && examined) atomicAdd(&counters[6], (unsigned long long)examined);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Output: map accepted (gx, gy) to ids, sort, deduplicate (the result is a set, Algorithm 1)
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_pairs_to_keys(const uint64_t* __restrict__ acc,
+                                                          uint64_t m,
+                                                          const int32_t* __restrict__ xperm,
+                                                          const int32_t* __restrict__ yperm,
+                                                          int self, int bbits,
+                                                          uint64_t* __restrict__ keys)
+{
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= m) return;
+    uint64_t v = acc[k];
+    uint32_t a = (uint32_t)xperm[v >> 32];
+    uint32_t b = (uint32_t)yperm[v & 0xffffffffu];
+    if (self && b < a) { uint32_t t = a; a = b; b = t; }
+    keys[k] = ((uint64_t)a << bbits) | b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_unique_flags(const uint64_t* __restrict__ keys,
+                                                         uint64_t m, uint32_t* __restrict__ flags)
+{
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m) flags[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_pairs(const uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ flags,
+                                                          const uint32_t* __restrict__ pos,
+                                                          uint64_t m, int bbits,
+                                                          int32_t* __restrict__ a,
+                                                          int32_t* __restrict__ b)
+{
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m && flags[k]) {
+        uint64_t v = keys[k];
+        a[pos[k]] = (int32_t)(v >> bbits);
+        b[pos[k]] = (int32_t)(v & ((1ull << bbits) - 1));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+
+static inline unsigned blocks_for(uint64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_length_hist(const int32_t* offs, int64_t n, int32_t* lcount, int32_t* err,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_length_hist, dim3(blocks_for(n)), dim3(kBlock), 0, s, offs, n, lcount, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota_len_keys(const int32_t* offs, int64_t n, uint32_t* keys, uint32_t* vals,
+                                hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_len_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, offs, n, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const int32_t* perm,
+                             int64_t n, const int32_t* lenstart, const int64_t* gbase,
+                             uint8_t* sarena, uint16_t* slen, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    uint64_t waves = (uint64_t)n;
+    uint64_t blocks = (waves * 64 + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_pack_arena, dim3((unsigned)blocks), dim3(kBlock), 0, s, bytes, offs, perm,
+                       n, lenstart, gbase, sarena, slen);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
+                                int64_t g_first, int64_t g_count, uint64_t* keys, uint32_t* vals,
+                                hipStream_t s)
+{
+    if (g_count <= 0) return hipSuccess;
+    uint64_t threads = (uint64_t)g_count * (tau + 1);
+    hipLaunchKernelGGL(k_emit_segments, dim3(blocks_for(threads)), dim3(kBlock), 0, s, S.sarena,
+                       S.slen, S.lenstart, S.gbase, ebase_dev, tau, g_first, g_count,
+                       make_div(tau + 1), keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_heads(const uint64_t* keys, int64_t E, uint32_t* flags, hipStream_t s)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_heads, dim3(blocks_for(E)), dim3(kBlock), 0, s, keys, E, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_table(uint4* table, uint64_t slots, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_table, dim3(blocks_for(slots)), dim3(kBlock), 0, s, table, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid, int64_t E,
+                                   uint32_t* runstart, hipStream_t s)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_runstart, dim3(blocks_for(E)), dim3(kBlock), 0, s, flags, runid, E,
+                       runstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                              uint32_t E, uint4* table, uint64_t mask, hipStream_t s)
+{
+    if (nruns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_insert_runs, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, keys, runstart,
+                       nruns, E, table, mask);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_hit_counts(const Hit* __restrict__ hits, uint64_t nh,
+                                                       uint32_t* __restrict__ counts)
+{
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < nh) counts[k] = hits[k].count;
+}
+
+hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s)
+{
+    if (nh == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hit_counts, dim3(blocks_for(nh)), dim3(kBlock), 0, s, hits, nh, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const ProbeParams& P, hipStream_t s)
+{
+    if (P.threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe, dim3(blocks_for(P.threads)), dim3(kBlock), 0, s, P,
+                       make_div(P.tau + 1));
+    return hipGetLastError();
+}
+
+template <int W>
+static void verify_w(const VerifyParams& V, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_verify<W>), dim3(grid), dim3(kBlock), 0, s, V, make_div(V.tau + 1));
+}
+
+hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s)
+{
+    if (V.ncand == 0) return hipSuccess;
+    const int w = V.tau + 1;
+    if (w <= 2) verify_w<2>(V, grid, s);
+    else if (w <= 3) verify_w<3>(V, grid, s);
+    else if (w <= 5) verify_w<5>(V, grid, s);
+    else if (w <= 9) verify_w<9>(V, grid, s);
+    else if (w <= 17) verify_w<17>(V, grid, s);
+    else if (w <= 33) verify_w<33>(V, grid, s);
+    else verify_w<64>(V, grid, s);
+    return hipGetLastError();
+}
+
+template <int W>
+static void short_w(const DevSet& P, const DevSet& Y, int tau, int self, uint32_t y_first,
+                    uint32_t y_count, uint64_t* out, uint64_t cap, unsigned long long* ctr,
+                    hipStream_t s)
+{
+    unsigned grid = y_count < 65536 ? y_count : 65536;
+    hipLaunchKernelGGL((k_short<W>), dim3(grid), dim3(kBlock), 0, s, P.sarena, P.slen, P.lenstart,
+                       P.gbase, P.lmax, Y.sarena, Y.slen, Y.lenstart, Y.gbase, y_first, y_count,
+                       tau, self, out, cap, ctr);
+}
+
+hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self, uint64_t* out,
+                             uint64_t out_cap, unsigned long long* counters, hipStream_t s)
+{
+    if (Y.n == 0 || P.n == 0 || Y.lmin > tau) return hipSuccess;
+    const int top = tau < Y.lmax ? tau : Y.lmax;
+    uint32_t y_first = (uint32_t)Y.h_lenstart[0];
+    uint32_t y_end = (uint32_t)Y.h_lenstart[top + 1];
+    if (y_end <= y_first) return hipSuccess;
+    uint32_t cnt = y_end - y_first;
+    const int w = tau + 1;
+    if (w <= 2) short_w<2>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 5) short_w<5>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 9) short_w<9>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 17) short_w<17>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 33) short_w<33>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    else short_w<64>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_to_keys(const uint64_t* acc, uint64_t m, const int32_t* xperm,
+                                const int32_t* yperm, int self, int bbits, uint64_t* keys,
+                                hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs_to_keys, dim3(blocks_for(m)), dim3(kBlock), 0, s, acc, m, xperm,
+                       yperm, self, bbits, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_unique_flags(const uint64_t* keys, uint64_t m, uint32_t* flags, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unique_flags, dim3(blocks_for(m)), dim3(kBlock), 0, s, keys, m, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, const uint32_t* pos,
+                                uint64_t m, int bbits, int32_t* a, int32_t* b, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_pairs, dim3(blocks_for(m)), dim3(kBlock), 0, s, keys, flags, pos,
+                       m, bbits, a, b);
+    return hipGetLastError();
+}
+
+}  // namespace pj

@@ -1,0 +1,203 @@
+// pj_device_common.h -- device helpers of libpassjoin: even partition, multi-match windows,
+// segment hashing, index keys, bucket-table lookup and the banded verification DP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pj_internal.h"
+
+namespace pj {
+
+// Division by d <= 64 of l < 2048 by multiply-shift: q = (l * m) >> 21 with m = ceil(2^21 / d)
+// is exact because l * (m - 2^21/d) / 2^21 < 2^-10 < 1/d.
+struct Div {
+    uint32_t d, m;
+    __host__ __device__ inline int operator()(int l) const { return (int)(((uint32_t)l * m) >> 21); }
+};
+
+inline Div make_div(int d)
+{
+    Div v;
+    v.d = (uint32_t)d;
+    v.m = (uint32_t)(((1u << 21) + (uint32_t)d - 1) / (uint32_t)d);
+    return v;
+}
+
+// Segment i (1-based) of a length-l string under the even partition into tau+1 segments
+// (Sec. 3.1): with q = floor(l/(tau+1)) and k = l - q(tau+1), the first tau+1-k segments have
+// length q and the last k have length q+1; p is the 1-based start.
+struct Seg {
+    int p, len;
+};
+
+__device__ inline Seg partition_seg(int l, int i, int tau, Div div)
+{
+    const int T1 = tau + 1;
+    const int q = div(l);
+    const int k = l - q * T1;
+    Seg s;
+    s.len = q + (i > T1 - k ? 1 : 0);
+    const int extra = i - 1 - (T1 - k);
+    s.p = 1 + (i - 1) * q + (extra > 0 ? extra : 0);
+    return s;
+}
+
+// Multi-match-aware window (Sec. 4.2): start positions p of x[p, l_i] selected for L_l^i,
+// intersecting the left-side bounds p_i -/+ (i-1) and the right-side bounds
+// p_i + Delta -/+ (tau+1-i), Delta = n - l, within [1, n - l_i + 1].
+__device__ inline void multimatch_window(int n, int l, int tau, int i, Seg sg, int* lo, int* hi)
+{
+    const int delta = n - l;
+    const int last = n - sg.len + 1;
+    const int r = tau + 1 - i;
+    int bl = sg.p - (i - 1), tl = sg.p + (i - 1);
+    int br = sg.p + delta - r, tr = sg.p + delta + r;
+    int a = bl > br ? bl : br;
+    int b = tl < tr ? tl : tr;
+    if (a < 1) a = 1;
+    if (b > last) b = last;
+    *lo = a;
+    *hi = b;
+}
+
+// Polynomial segment hash h = sum (c_k + 1) * B^(L-1-k) mod 2^64 (Horner form), rolled across
+// consecutive start positions.  Equal segments always hash equal; unequal ones that collide are
+// rejected by the byte comparison done before verification.
+constexpr uint64_t kHashBase = 0x9E3779B97F4A7C15ull;
+
+__device__ inline uint64_t seg_hash(const uint8_t* w, int len)
+{
+    uint64_t h = 0;
+    for (int k = 0; k < len; ++k) h = h * kHashBase + (uint64_t)w[k] + 1ull;
+    return h;
+}
+
+__device__ inline uint64_t pow_hash(int len)   // B^(len-1)
+{
+    uint64_t r = 1, b = kHashBase;
+    int e = len - 1;
+    while (e > 0) {
+        if (e & 1) r *= b;
+        b *= b;
+        e >>= 1;
+    }
+    return r;
+}
+
+__device__ inline uint64_t roll_hash(uint64_t h, uint8_t out, uint8_t in, uint64_t top)
+{
+    return (h - ((uint64_t)out + 1ull) * top) * kHashBase + (uint64_t)in + 1ull;
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014), used to spread hash bits.
+__host__ __device__ inline uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__device__ inline uint64_t make_key(int l, int i, int tau, uint64_t h)
+{
+    const uint64_t grp = (uint64_t)(l - (tau + 1)) * (uint64_t)(tau + 1) + (uint64_t)(i - 1);
+    return (grp << kHashBits) | (mix64(h) >> (64 - kHashBits));
+}
+
+__device__ inline uint64_t table_slot(uint64_t key) { return mix64(key ^ 0x5851F42D4C957F2Dull); }
+
+__device__ inline bool table_lookup(const uint4* __restrict__ table, uint64_t mask, uint64_t key,
+                                    uint32_t* start, uint32_t* count)
+{
+    uint64_t slot = table_slot(key) & mask;
+    while (true) {
+        const uint4 v = table[slot];
+        const uint64_t k = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        if (k == key) {
+            *start = v.z;
+            *count = v.w;
+            return true;
+        }
+        if (k == kEmptyKey) return false;
+        slot = (slot + 1) & mask;
+    }
+}
+
+// VerifyStringPair (Sec. 5.1; function of Algorithm 3): min(t+1, ED(r, s)) with the length-aware
+// band and the expected-edit-distance early termination (Lemma 4).  r is the indexed string's
+// part and s the probe string's part; the shorter one gives the rows (r when equal).  With
+// Delta = |cols| - |rows| (> t: return t+1), row i keeps the cells j in
+// [i - floor((t-Delta)/2), i + floor((t+Delta)/2)], held in registers R[k], j = i - a + k.
+// Cells out of the band or the matrix are infinite; values saturate at t+1.  After each row,
+// E(i,j) = M(i,j) + |Delta + a - k| (the length gap of the remaining suffixes) is reduced to its
+// minimum; above t the pair cannot be within t.  *cells counts recurrence cells (j >= 1).
+// MAXW >= t+1 bounds the band width at compile time.
+template <int MAXW>
+__device__ inline int vsp_global(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
+                                 int* cells)
+{
+    const uint8_t* A;
+    const uint8_t* B;
+    int nr, nc;
+    if (lr <= ls) { A = r; nr = lr; B = s; nc = ls; }
+    else          { A = s; nr = ls; B = r; nc = lr; }
+    const int delta = nc - nr;
+    *cells = 0;
+    if (delta > t) return t + 1;
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    const int W = a + b + 1;
+    const int INF = t + 1;
+    int R[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int j = k - a;
+        R[k] = (k < W && j >= 0 && j <= nc) ? (j < INF ? j : INF) : INF;
+    }
+    int ncell = 0;
+    for (int i = 1; i <= nr; ++i) {
+        const int ai = A[i - 1];
+        int left = INF;
+        int emin = 1 << 20;
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) {
+            if (k < W) {
+                const int j = i - a + k;
+                int v = INF;
+                if (j >= 0 && j <= nc) {
+                    if (j == 0) {
+                        v = i < INF ? i : INF;
+                    } else {
+                        const int up = (k + 1 < MAXW && k + 1 < W) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
+                        const int d = (ai != (int)B[j - 1]) ? 1 : 0;
+                        const int m1 = (up < left ? up : left) + 1;
+                        const int m2 = R[k] + d;
+                        v = m1 < m2 ? m1 : m2;
+                        v = v < INF ? v : INF;
+                        ++ncell;
+                    }
+                    const int dd = delta + a - k;
+                    const int e = v + (dd < 0 ? -dd : dd);
+                    emin = e < emin ? e : emin;
+                }
+                R[k] = v;
+                left = v;
+            }
+        }
+        if (emin > t) {
+            *cells = ncell;
+            return t + 1;
+        }
+    }
+    *cells = ncell;
+    int res = INF;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k)
+        if (k == delta + a) res = R[k];
+    return res;
+}
+
+}  // namespace pj

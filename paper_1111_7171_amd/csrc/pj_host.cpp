@@ -1,0 +1,695 @@
+// pj_host.cpp -- host runtime and C ABI of libpassjoin.
+//
+// A call runs: validate -> upload -> length-sorted arena -> segment index -> probe -> verify
+// (+ short-string path) -> deduplicate -> output.  Device scratch comes from a per-thread cache
+// of grow-only buffers, so repeated calls on one thread do not reallocate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/passjoin.h"
+#include "pj_internal.h"
+#include "pj_host_internal.h"
+
+namespace pj {
+
+// ------------------------------------------------------------------------------------------
+// Errors and per-thread state
+// ------------------------------------------------------------------------------------------
+
+thread_local std::string t_last_error;
+thread_local pj_stats t_stats;
+thread_local pj_stats t_last_ok_stats;
+
+Error::Error(int c, const char* fmt, ...) : code(c)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    msg = buf;
+}
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (e == hipErrorOutOfMemory) throw Error(PJ_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+        throw Error(PJ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Device memory
+// ------------------------------------------------------------------------------------------
+
+Workspace::~Workspace()
+{
+    for (auto& kv : bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+}
+
+void* Workspace::get(const char* name, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (budget > 0 && used + bytes > (size_t)budget)
+        throw Error(PJ_ENOMEM, "memory budget of %lld bytes exceeded (%s needs %zu more)",
+                    (long long)budget, name, bytes);
+    used += bytes;
+    Buf& b = bufs[name];
+    if (b.cap < bytes) {
+        if (b.p) hip_check(hipFree(b.p), "hipFree");
+        b.p = nullptr;
+        b.cap = 0;
+        size_t want = bytes + bytes / 8;
+        hipError_t e = hipMalloc(&b.p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            throw Error(PJ_ENOMEM, "hipMalloc(%zu) for %s failed: %s", want, name,
+                        hipGetErrorString(e));
+        }
+        b.cap = want;
+    }
+    return b.p;
+}
+
+void Workspace::release_all()
+{
+    for (auto& kv : bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    bufs.clear();
+}
+
+Owned::~Owned()
+{
+    for (void* p : ptrs) (void)hipFree(p);
+}
+
+void* Owned::get(const char* name, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (budget > 0 && used + bytes > (size_t)budget)
+        throw Error(PJ_ENOMEM, "memory budget of %lld bytes exceeded (%s)", (long long)budget,
+                    name);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(PJ_ENOMEM, "hipMalloc(%zu) for %s failed", bytes, name);
+    }
+    used += bytes;
+    ptrs.push_back(p);
+    return p;
+}
+
+static thread_local Workspace* t_ws = nullptr;
+
+Workspace& thread_workspace()
+{
+    if (!t_ws) t_ws = new Workspace();
+    return *t_ws;
+}
+
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        int v = 0;
+        hip_check(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev),
+                  "hipDeviceGetAttribute");
+        cus = v > 0 ? v : 256;
+    }
+    return cus;
+}
+
+static int bitlen(uint64_t v)
+{
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+// ------------------------------------------------------------------------------------------
+// Timing
+// ------------------------------------------------------------------------------------------
+
+Timer::Timer(hipStream_t s) : st(s) {}
+
+Timer::~Timer()
+{
+    for (auto e : evs) (void)hipEventDestroy(e);
+}
+
+int Timer::mark()
+{
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    hip_check(hipEventRecord(e, st), "hipEventRecord");
+    evs.push_back(e);
+    return (int)evs.size() - 1;
+}
+
+double Timer::ms(int a, int b)
+{
+    float v = 0.f;
+    hip_check(hipEventSynchronize(evs[b]), "hipEventSynchronize");
+    hip_check(hipEventElapsedTime(&v, evs[a], evs[b]), "hipEventElapsedTime");
+    return (double)v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Input validation and the length-sorted arena
+// ------------------------------------------------------------------------------------------
+
+void validate_host_strings(const pj_strings* S, const char* what)
+{
+    if (!S) throw Error(PJ_EINVAL, "%s: null pj_strings", what);
+    if (S->n < 0) throw Error(PJ_EINVAL, "%s: n < 0", what);
+    if (S->n >= (int64_t)INT32_MAX) throw Error(PJ_ERANGE, "%s: too many strings", what);
+    if (!S->offsets) throw Error(PJ_EINVAL, "%s: null offsets", what);
+    if (S->offsets[0] != 0) throw Error(PJ_EINVAL, "%s: offsets[0] != 0", what);
+    for (int64_t k = 0; k < S->n; ++k) {
+        int64_t l = (int64_t)S->offsets[k + 1] - S->offsets[k];
+        if (l < 0) throw Error(PJ_EINVAL, "%s: offsets decrease at %lld", what, (long long)k);
+        if (l > kLenMax)
+            throw Error(PJ_ERANGE, "%s: string %lld has length %lld > %d", what, (long long)k,
+                        (long long)l, kLenMax);
+    }
+    if (S->offsets[S->n] > 0 && !S->bytes) throw Error(PJ_EINVAL, "%s: null bytes", what);
+}
+
+void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
+               hipStream_t st)
+{
+    if (!S) throw Error(PJ_EINVAL, "%s: null pj_strings", tag.c_str());
+    if (!on_device) validate_host_strings(S, tag.c_str());
+    else {
+        if (S->n < 0) throw Error(PJ_EINVAL, "%s: n < 0", tag.c_str());
+        if (S->n >= (int64_t)INT32_MAX) throw Error(PJ_ERANGE, "%s: too many strings", tag.c_str());
+        if (!S->offsets) throw Error(PJ_EINVAL, "%s: null offsets", tag.c_str());
+    }
+    const int64_t n = S->n;
+    D.n = n;
+    auto nm = [&](const char* s) { return tag + "." + s; };
+
+    const int32_t* d_offs = nullptr;
+    const uint8_t* d_bytes = nullptr;
+    int64_t total = 0;
+    if (on_device) {
+        d_offs = S->offsets;
+        d_bytes = S->bytes;
+    } else {
+        total = S->offsets[n];
+        int32_t* o = (int32_t*)A.get(nm("offs").c_str(), sizeof(int32_t) * (size_t)(n + 1));
+        hip_check(hipMemcpyAsync(o, S->offsets, sizeof(int32_t) * (size_t)(n + 1),
+                                 hipMemcpyHostToDevice, st), "upload offsets");
+        uint8_t* bb = (uint8_t*)A.get(nm("bytes").c_str(), (size_t)total + 16);
+        if (total > 0)
+            hip_check(hipMemcpyAsync(bb, S->bytes, (size_t)total, hipMemcpyHostToDevice, st),
+                      "upload bytes");
+        d_offs = o;
+        d_bytes = bb;
+    }
+
+    // length histogram (+ validation of device inputs)
+    int32_t* lcount = (int32_t*)A.get(nm("lcount").c_str(), sizeof(int32_t) * (kLenTab + 1));
+    hip_check(hipMemsetAsync(lcount, 0, sizeof(int32_t) * (kLenTab + 1), st), "memset");
+    hip_check(launch_length_hist(d_offs, n, lcount, lcount + kLenTab, st), "length_hist");
+    std::vector<int32_t> h(kLenTab + 1);
+    hip_check(hipMemcpyAsync(h.data(), lcount, sizeof(int32_t) * (kLenTab + 1),
+                             hipMemcpyDeviceToHost, st), "download lcount");
+    hip_check(hipStreamSynchronize(st), "sync");
+    int err = h[kLenTab];
+    if (err & 1) throw Error(PJ_EINVAL, "%s: offsets[0] != 0", tag.c_str());
+    if (err & 2) throw Error(PJ_EINVAL, "%s: offsets decrease", tag.c_str());
+    if (err & 4) throw Error(PJ_ERANGE, "%s: a string is longer than %d", tag.c_str(), kLenMax);
+
+    int64_t pos = 0, bytes = 0;
+    D.lmin = kLenTab;
+    D.lmax = -1;
+    for (int l = 0; l < kLenTab; ++l) {
+        D.h_lenstart[l] = (int32_t)pos;
+        D.h_gbase[l] = bytes;
+        if (h[l] > 0) {
+            D.lmin = std::min(D.lmin, l);
+            D.lmax = std::max(D.lmax, l);
+        }
+        pos += h[l];
+        bytes += (int64_t)h[l] * stride_of(l);
+    }
+    D.h_lenstart[kLenTab] = (int32_t)pos;
+    if (D.lmax < 0) D.lmin = 0;
+    D.arena_bytes = bytes;
+
+    D.lenstart = (int32_t*)A.get(nm("lenstart").c_str(), sizeof(int32_t) * (kLenTab + 1));
+    D.gbase = (int64_t*)A.get(nm("gbase").c_str(), sizeof(int64_t) * kLenTab);
+    hip_check(hipMemcpyAsync(D.lenstart, D.h_lenstart, sizeof(int32_t) * (kLenTab + 1),
+                             hipMemcpyHostToDevice, st), "upload lenstart");
+    hip_check(hipMemcpyAsync(D.gbase, D.h_gbase, sizeof(int64_t) * kLenTab,
+                             hipMemcpyHostToDevice, st), "upload gbase");
+
+    D.perm = (int32_t*)A.get(nm("perm").c_str(), sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    D.slen = (uint16_t*)A.get(nm("slen").c_str(), sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1));
+    D.sarena = (uint8_t*)A.get(nm("sarena").c_str(), (size_t)bytes + 64);
+    if (n == 0) return;
+
+    // stable sort of ids by length -> perm
+    Workspace& W = thread_workspace();
+    uint32_t* k0 = (uint32_t*)W.get("lensort.k0", sizeof(uint32_t) * (size_t)n);
+    uint32_t* k1 = (uint32_t*)W.get("lensort.k1", sizeof(uint32_t) * (size_t)n);
+    uint32_t* v1 = (uint32_t*)W.get("lensort.v1", sizeof(uint32_t) * (size_t)n);
+    size_t tb = radix_tmp_bytes((uint64_t)n);
+    void* tmp = W.get("radix.tmp", tb);
+    uint32_t* v0 = (uint32_t*)D.perm;
+    hip_check(launch_iota_len_keys(d_offs, n, k0, v0, st), "len_keys");
+    bool alt = false;
+    hip_check(radix_sort_u32(k0, v0, k1, v1, (uint64_t)n, bitlen((uint64_t)std::max(D.lmax, 1)),
+                             tmp, tb, &alt, st), "radix(len)");
+    if (alt)
+        hip_check(hipMemcpyAsync(D.perm, v1, sizeof(uint32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, st), "perm copy");
+    hip_check(launch_pack_arena(d_bytes, d_offs, D.perm, n, D.lenstart, D.gbase, D.sarena, D.slen,
+                                st), "pack_arena");
+}
+
+// ------------------------------------------------------------------------------------------
+// Segment index
+// ------------------------------------------------------------------------------------------
+
+void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
+                 hipStream_t st)
+{
+    const int T1 = tau + 1;
+    X.tau = tau;
+    auto nm = [&](const char* s) { return tag + "." + s; };
+    int64_t g_first = (T1 <= kLenMax + 1) ? D.h_lenstart[std::min(T1, kLenTab)] : D.n;
+    int64_t g_count = D.n - g_first;
+    int64_t E = g_count * T1;
+    if (E >= (int64_t)UINT32_MAX) throw Error(PJ_ERANGE, "index too large (%lld entries)", (long long)E);
+    X.entries = E;
+    if (E == 0) {
+        X.keys = (uint64_t*)A.get(nm("keys").c_str(), 16);
+        X.vals = (uint32_t*)A.get(nm("vals").c_str(), 16);
+        X.mask = 1023;
+        X.table = (uint4*)A.get(nm("table").c_str(), sizeof(uint4) * 1024);
+        hip_check(launch_clear_table(X.table, 1024, st), "clear_table");
+        X.lists = 0;
+        return;
+    }
+    std::vector<int64_t> ebase(kLenTab, 0);
+    int64_t run = 0;
+    for (int l = 0; l < kLenTab; ++l) {
+        ebase[l] = run;
+        if (l >= T1) run += (int64_t)(D.h_lenstart[l + 1] - D.h_lenstart[l]) * T1;
+    }
+    Workspace& W = thread_workspace();
+    int64_t* d_ebase = (int64_t*)W.get("index.ebase", sizeof(int64_t) * kLenTab);
+    hip_check(hipMemcpyAsync(d_ebase, ebase.data(), sizeof(int64_t) * kLenTab,
+                             hipMemcpyHostToDevice, st), "upload ebase");
+    uint64_t* keys = (uint64_t*)A.get(nm("keys").c_str(), sizeof(uint64_t) * (size_t)E);
+    uint32_t* vals = (uint32_t*)A.get(nm("vals").c_str(), sizeof(uint32_t) * (size_t)E);
+    uint64_t* keys2 = (uint64_t*)W.get("index.keys2", sizeof(uint64_t) * (size_t)E);
+    uint32_t* vals2 = (uint32_t*)W.get("index.vals2", sizeof(uint32_t) * (size_t)E);
+    hip_check(launch_emit_segments(D, tau, d_ebase, g_first, g_count, keys, vals, st), "emit");
+    uint64_t grp_max = (uint64_t)(D.lmax - T1) * T1 + tau;
+    int bits = kHashBits + std::max(1, bitlen(grp_max));
+    size_t tb = radix_tmp_bytes((uint64_t)E);
+    void* tmp = W.get("radix.tmp", tb);
+    bool alt = false;
+    hip_check(radix_sort_u64(keys, vals, keys2, vals2, (uint64_t)E, bits, tmp, tb, &alt, st),
+              "radix(index)");
+    if (alt) {
+        hip_check(hipMemcpyAsync(keys, keys2, sizeof(uint64_t) * (size_t)E,
+                                 hipMemcpyDeviceToDevice, st), "keys copy");
+        hip_check(hipMemcpyAsync(vals, vals2, sizeof(uint32_t) * (size_t)E,
+                                 hipMemcpyDeviceToDevice, st), "vals copy");
+    }
+    X.keys = keys;
+    X.vals = vals;
+    // lists = runs of equal keys
+    uint32_t* flags = (uint32_t*)W.get("index.flags", sizeof(uint32_t) * (size_t)E);
+    uint32_t* runid = (uint32_t*)W.get("index.runid", sizeof(uint32_t) * (size_t)(E + 1));
+    hip_check(launch_mark_heads(keys, E, flags, st), "mark_heads");
+    size_t sb = scan_tmp_bytes((uint64_t)E);
+    void* stmp = W.get("scan.tmp", sb);
+    hip_check(scan_u32_to_u32(flags, runid, (uint64_t)E, stmp, sb, st), "scan(runs)");
+    uint32_t nruns = 0;
+    hip_check(hipMemcpyAsync(&nruns, runid + E, sizeof(uint32_t), hipMemcpyDeviceToHost, st),
+              "download nruns");
+    hip_check(hipStreamSynchronize(st), "sync");
+    X.lists = nruns;
+    uint32_t* runstart = (uint32_t*)W.get("index.runstart", sizeof(uint32_t) * (size_t)(nruns + 1));
+    hip_check(launch_scatter_runstart(flags, runid, E, runstart, st), "runstart");
+    uint64_t slots = 1024;
+    while (slots < 2ull * nruns) slots <<= 1;
+    X.mask = slots - 1;
+    X.table = (uint4*)A.get(nm("table").c_str(), sizeof(uint4) * (size_t)slots);
+    hip_check(launch_clear_table(X.table, slots, st), "clear_table");
+    hip_check(launch_insert_runs(keys, runstart, nruns, (uint32_t)E, X.table, X.mask, st),
+              "insert_runs");
+}
+
+// ------------------------------------------------------------------------------------------
+// Probe + verify + short-string path
+// ------------------------------------------------------------------------------------------
+
+// Upper bound on the selected substrings (Lemma 2 count per probed length), which bounds hits.
+static uint64_t selection_bound(const DevSet& P, const DevSet& Y, int tau, bool self,
+                                int64_t* probe_first)
+{
+    const int T1 = tau + 1;
+    uint64_t total = 0;
+    for (int n = 0; n < kLenTab; ++n) {
+        int64_t cnt = P.h_lenstart[n + 1] - P.h_lenstart[n];
+        if (cnt == 0) continue;
+        int lo = self ? n - tau : n - tau, hi = self ? n : n + tau;
+        uint64_t per = 0;
+        for (int l = std::max(lo, T1); l <= hi && l <= kLenMax; ++l) {
+            if (Y.h_lenstart[l + 1] == Y.h_lenstart[l]) continue;
+            int d = n - l;
+            per += (uint64_t)((tau * tau - d * d) / 2 + tau + 1);
+        }
+        total += per * (uint64_t)cnt;
+    }
+    *probe_first = self ? (T1 <= kLenMax ? P.h_lenstart[T1] : P.n) : 0;
+    return total;
+}
+
+void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau, bool self,
+                    JoinScratch& J, pj_stats& stats, Timer& tm, hipStream_t st)
+{
+    Workspace& W = thread_workspace();
+    const int T1 = tau + 1;
+    J.counters = (unsigned long long*)W.get("join.counters", 8 * sizeof(unsigned long long));
+    hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
+    int64_t probe_first = 0;
+    uint64_t bound = selection_bound(P, Y, tau, self, &probe_first);
+    int64_t nprobe = P.n - probe_first;
+    J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)std::max<uint64_t>(bound, 1));
+    int t_probe0 = tm.mark();
+    if (nprobe > 0 && bound > 0 && X.entries > 0) {
+        ProbeParams pp{};
+        pp.x_arena = P.sarena; pp.x_slen = P.slen; pp.x_lenstart = P.lenstart; pp.x_gbase = P.gbase;
+        pp.g_begin = (uint32_t)probe_first;
+        pp.nl = self ? T1 : 2 * tau + 1;
+        pp.threads = (uint64_t)nprobe * (uint64_t)pp.nl * (uint64_t)T1;
+        pp.self = self ? 1 : 0;
+        pp.q_tau = nullptr;
+        pp.y_lenstart = Y.lenstart;
+        pp.keys = X.keys; pp.vals = X.vals; pp.table = X.table; pp.mask = X.mask;
+        pp.tau = tau;
+        pp.ymin = Y.lmin; pp.ymax = Y.lmax;
+        pp.hits = J.hits; pp.hit_cap = bound;
+        pp.counters = J.counters;
+        hip_check(launch_probe(pp, st), "probe");
+    }
+    unsigned long long c[8];
+    hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
+    hip_check(hipStreamSynchronize(st), "sync");
+    int t_probe1 = tm.mark();
+    J.nhits = c[0];
+    J.ncand = c[1];
+    stats.selected += (int64_t)c[2];
+    stats.hits += (int64_t)c[0];
+    stats.candidates += (int64_t)c[1];
+    if (J.nhits > bound) throw Error(PJ_EDEVICE, "hit buffer overflow (%llu > %llu)",
+                                     (unsigned long long)J.nhits, (unsigned long long)bound);
+
+    // candidate prefix sums
+    J.prefix = (unsigned long long*)W.get("join.prefix",
+                                          sizeof(unsigned long long) * (size_t)(J.nhits + 1));
+    if (J.nhits > 0) {
+        uint32_t* counts = (uint32_t*)W.get("join.counts", sizeof(uint32_t) * (size_t)J.nhits);
+        hip_check(launch_hit_counts(J.hits, J.nhits, counts, st), "hit_counts");
+        size_t sb = scan_tmp_bytes(J.nhits);
+        void* stmp = W.get("scan.tmp", sb);
+        hip_check(scan_u32_to_u64(counts, J.prefix, J.nhits, stmp, sb, st), "scan(prefix)");
+    }
+
+    // verify (+ short path); rerun once with an exact buffer when the first guess overflows
+    uint64_t cap = std::min<uint64_t>(J.ncand + 4096, 1ull << 26);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        J.out = (uint64_t*)W.get("join.out", sizeof(uint64_t) * (size_t)cap);
+        hip_check(hipMemsetAsync(J.counters + 3, 0, 5 * sizeof(unsigned long long), st), "memset");
+        if (J.ncand > 0) {
+            VerifyParams vp{};
+            vp.x_arena = P.sarena; vp.x_slen = P.slen; vp.x_lenstart = P.lenstart;
+            vp.x_gbase = P.gbase;
+            vp.y_arena = Y.sarena; vp.y_lenstart = Y.lenstart; vp.y_gbase = Y.gbase;
+            vp.vals = X.vals;
+            vp.hits = J.hits; vp.prefix = J.prefix;
+            vp.nhits = J.nhits; vp.ncand = J.ncand;
+            vp.tau = tau;
+            vp.out = J.out; vp.out_cap = cap;
+            vp.counters = J.counters;
+            uint64_t nchunks = (J.ncand + 1023) / 1024;
+            int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 16);
+            hip_check(launch_verify(vp, grid, st), "verify");
+        }
+        hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, J.out, cap, J.counters, st),
+                  "short_path");
+        hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
+        hip_check(hipStreamSynchronize(st), "sync");
+        if (c[3] <= cap) break;
+        cap = c[3];
+    }
+    int t_verify1 = tm.mark();
+    J.naccepted = c[3];
+    stats.accepted += (int64_t)c[3];
+    stats.cells += (int64_t)c[4];
+    stats.side_pairs += (int64_t)c[6];
+    J.guard_misses = c[5];
+    stats.ms_probe += tm.ms(t_probe0, t_probe1);
+    stats.ms_verify += tm.ms(t_probe1, t_verify1);
+}
+
+// Sorts and deduplicates accepted (gx, gy) into id pairs; returns device arrays (workspace).
+uint64_t finish_pairs(const DevSet& P, const DevSet& Y, bool self, const uint64_t* acc,
+                      uint64_t m, int32_t** a_out, int32_t** b_out, hipStream_t st)
+{
+    Workspace& W = thread_workspace();
+    if (m >= (uint64_t)UINT32_MAX) throw Error(PJ_ERANGE, "too many accepted candidates");
+    int bbits = std::max(1, bitlen((uint64_t)std::max<int64_t>(std::max(P.n, Y.n) - 1, 1)));
+    uint64_t* k0 = (uint64_t*)W.get("out.k0", sizeof(uint64_t) * (size_t)std::max<uint64_t>(m, 1));
+    uint64_t* k1 = (uint64_t*)W.get("out.k1", sizeof(uint64_t) * (size_t)std::max<uint64_t>(m, 1));
+    int32_t* a = (int32_t*)W.get("out.a", sizeof(int32_t) * (size_t)std::max<uint64_t>(m, 1));
+    int32_t* b = (int32_t*)W.get("out.b", sizeof(int32_t) * (size_t)std::max<uint64_t>(m, 1));
+    *a_out = a;
+    *b_out = b;
+    if (m == 0) return 0;
+    hip_check(launch_pairs_to_keys(acc, m, P.perm, Y.perm, self ? 1 : 0, bbits, k0, st), "keys");
+    size_t tb = radix_tmp_bytes(m);
+    void* tmp = W.get("radix.tmp", tb);
+    bool alt = false;
+    hip_check(radix_sort_u64(k0, nullptr, k1, nullptr, m, 2 * bbits, tmp, tb, &alt, st),
+              "radix(pairs)");
+    uint64_t* ks = alt ? k1 : k0;
+    uint32_t* flags = (uint32_t*)W.get("out.flags", sizeof(uint32_t) * (size_t)m);
+    uint32_t* pos = (uint32_t*)W.get("out.pos", sizeof(uint32_t) * (size_t)(m + 1));
+    hip_check(launch_unique_flags(ks, m, flags, st), "unique");
+    size_t sb = scan_tmp_bytes(m);
+    void* stmp = W.get("scan.tmp", sb);
+    hip_check(scan_u32_to_u32(flags, pos, m, stmp, sb, st), "scan(unique)");
+    hip_check(launch_compact_pairs(ks, flags, pos, m, bbits, a, b, st), "compact");
+    uint32_t M = 0;
+    hip_check(hipMemcpyAsync(&M, pos + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st), "count");
+    hip_check(hipStreamSynchronize(st), "sync");
+    return M;
+}
+
+void emit_output(const int32_t* da, const int32_t* db, uint64_t M, bool to_device, pj_pairs* out,
+                 hipStream_t st)
+{
+    out->count = (int64_t)M;
+    out->on_device = to_device ? 1 : 0;
+    out->a = nullptr;
+    out->b = nullptr;
+    size_t bytes = sizeof(int32_t) * (size_t)std::max<uint64_t>(M, 1);
+    if (to_device) {
+        void *pa = nullptr, *pb = nullptr;
+        if (hipMalloc(&pa, bytes) != hipSuccess || hipMalloc(&pb, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (pa) (void)hipFree(pa);
+            throw Error(PJ_ENOMEM, "output allocation failed");
+        }
+        out->a = (int32_t*)pa;
+        out->b = (int32_t*)pb;
+        if (M) {
+            hip_check(hipMemcpyAsync(pa, da, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, st), "out");
+            hip_check(hipMemcpyAsync(pb, db, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, st), "out");
+        }
+    } else {
+        out->a = (int32_t*)malloc(bytes);
+        out->b = (int32_t*)malloc(bytes);
+        if (!out->a || !out->b) {
+            free(out->a);
+            free(out->b);
+            out->a = out->b = nullptr;
+            throw Error(PJ_ENOMEM, "host output allocation failed");
+        }
+        if (M) {
+            hip_check(hipMemcpyAsync(out->a, da, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "out");
+            hip_check(hipMemcpyAsync(out->b, db, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "out");
+        }
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+}
+
+// ------------------------------------------------------------------------------------------
+// Entry points
+// ------------------------------------------------------------------------------------------
+
+static void check_tau(int32_t tau)
+{
+    if (tau < 0 || tau > kTauMax) throw Error(PJ_EINVAL, "tau %d out of [0, %d]", tau, kTauMax);
+}
+
+static hipStream_t stream_of(const pj_options* opt)
+{
+    return opt ? (hipStream_t)opt->hip_stream : (hipStream_t)0;
+}
+
+static void zero_pairs(pj_pairs* out)
+{
+    if (out) {
+        out->count = 0;
+        out->a = nullptr;
+        out->b = nullptr;
+        out->on_device = 0;
+    }
+}
+
+template <typename F>
+static int guarded(pj_pairs* out, F&& f)
+{
+    t_stats = pj_stats{};
+    try {
+        f();
+        t_last_ok_stats = t_stats;
+        t_last_error.clear();
+        return PJ_OK;
+    } catch (const Error& e) {
+        t_last_error = e.msg;
+        if (out) pj_pairs_free(out);
+        zero_pairs(out);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        t_last_error = "host allocation failed";
+        if (out) pj_pairs_free(out);
+        zero_pairs(out);
+        return PJ_ENOMEM;
+    } catch (...) {
+        t_last_error = "unexpected internal error";
+        if (out) pj_pairs_free(out);
+        zero_pairs(out);
+        return PJ_EDEVICE;
+    }
+}
+
+static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
+                      pj_pairs* out, bool self)
+{
+    if (!out) throw Error(PJ_EINVAL, "null output");
+    zero_pairs(out);
+    check_tau(tau);
+    hipStream_t st = stream_of(opt);
+    bool on_dev = opt && opt->inputs_on_device;
+    if (!on_dev) {
+        // host inputs are fully validated before any device work
+        validate_host_strings(self ? S : R, self ? "S" : "R");
+        if (!self) validate_host_strings(S, "S");
+    }
+    Workspace& W = thread_workspace();
+    W.begin_call(opt ? opt->mem_budget_bytes : 0);
+    auto t0 = std::chrono::steady_clock::now();
+    Timer tm(st);
+    int e0 = tm.mark();
+    DevSet P, Y;
+    build_set(self ? S : R, on_dev, W, "P", P, st);
+    if (!self) build_set(S, on_dev, W, "Y", Y, st);
+    const DevSet& YY = self ? P : Y;
+    int e1 = tm.mark();
+    DevIndex X;
+    build_index(YY, tau, W, "X", X, st);
+    int e2 = tm.mark();
+    t_stats.strings = P.n + (self ? 0 : Y.n);
+    t_stats.index_entries = X.entries;
+    JoinScratch J;
+    run_candidates(P, YY, X, tau, self, J, t_stats, tm, st);
+    int e3 = tm.mark();
+    int32_t *da = nullptr, *db = nullptr;
+    uint64_t M = finish_pairs(P, YY, self, J.out, J.naccepted, &da, &db, st);
+    emit_output(da, db, M, opt && opt->outputs_on_device, out, st);
+    int e4 = tm.mark();
+    t_stats.pairs = (int64_t)M;
+    t_stats.ms_upload = tm.ms(e0, e1);
+    t_stats.ms_index = tm.ms(e1, e2);
+    t_stats.ms_output = tm.ms(e3, e4);
+    t_stats.ms_total = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace pj
+
+using namespace pj;
+
+extern "C" {
+
+int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out)
+{
+    return guarded(out, [&] { join_impl(nullptr, S, tau, opt, out, true); });
+}
+
+int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
+            pj_pairs* out)
+{
+    return guarded(out, [&] {
+        if (!R || !S) throw Error(PJ_EINVAL, "null pj_strings");
+        join_impl(R, S, tau, opt, out, false);
+    });
+}
+
+void pj_pairs_free(pj_pairs* p)
+{
+    if (!p) return;
+    if (p->on_device) {
+        if (p->a) (void)hipFree(p->a);
+        if (p->b) (void)hipFree(p->b);
+    } else {
+        free(p->a);
+        free(p->b);
+    }
+    p->a = p->b = nullptr;
+    p->count = 0;
+    p->on_device = 0;
+}
+
+const char* pj_last_error(void) { return t_last_error.c_str(); }
+
+int pj_last_stats(pj_stats* out)
+{
+    if (!out) return PJ_EINVAL;
+    *out = t_last_ok_stats;
+    return PJ_OK;
+}
+
+const char* pj_version(void) { return "passjoin-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// pj_host_internal.h -- host-side runtime pieces of libpassjoin shared by the join, index and
+// serving translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/passjoin.h"
+#include "pj_internal.h"
+
+namespace pj {
+
+struct Error {
+    int code;
+    std::string msg;
+    Error(int c, const char* fmt, ...);
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Device allocator interface: named buffers, so a workspace can reuse them across calls.
+struct Alloc {
+    long long budget = 0;   // 0 = unlimited
+    size_t used = 0;        // bytes requested in the current call
+    virtual ~Alloc() = default;
+    virtual void* get(const char* name, size_t bytes) = 0;
+};
+
+// Grow-only named buffers cached per thread (scratch of one call at a time).
+struct Workspace : Alloc {
+    struct Buf {
+        void* p = nullptr;
+        size_t cap = 0;
+    };
+    std::unordered_map<std::string, Buf> bufs;
+    ~Workspace() override;
+    void* get(const char* name, size_t bytes) override;
+    void begin_call(long long b) { budget = b; used = 0; }
+    void release_all();
+};
+
+// Allocations owned by a long-lived object (an index); freed with it.
+struct Owned : Alloc {
+    std::vector<void*> ptrs;
+    ~Owned() override;
+    void* get(const char* name, size_t bytes) override;
+};
+
+Workspace& thread_workspace();
+int device_cus();
+
+// hipEvent marks on one stream.
+struct Timer {
+    hipStream_t st;
+    std::vector<hipEvent_t> evs;
+    explicit Timer(hipStream_t s);
+    ~Timer();
+    int mark();
+    double ms(int a, int b);
+};
+
+struct JoinScratch {
+    unsigned long long* counters = nullptr;
+    Hit* hits = nullptr;
+    unsigned long long* prefix = nullptr;
+    uint64_t nhits = 0, ncand = 0;
+    uint64_t* out = nullptr;
+    uint64_t naccepted = 0;
+    uint64_t guard_misses = 0;
+};
+
+void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
+               hipStream_t st);
+void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
+                 hipStream_t st);
+void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau, bool self,
+                    JoinScratch& J, pj_stats& stats, Timer& tm, hipStream_t st);
+uint64_t finish_pairs(const DevSet& P, const DevSet& Y, bool self, const uint64_t* acc,
+                      uint64_t m, int32_t** a_out, int32_t** b_out, hipStream_t st);
+void emit_output(const int32_t* da, const int32_t* db, uint64_t M, bool to_device, pj_pairs* out,
+                 hipStream_t st);
+
+extern thread_local std::string t_last_error;
+extern thread_local pj_stats t_stats;
+extern thread_local pj_stats t_last_ok_stats;
+
+}  // namespace pj

@@ -1,0 +1,250 @@
+// pj_index.cpp -- device-resident indices (one per tau of a range) and per-query-tau probing.
+//
+// pj_build_index keeps the length-sorted arena of S and, for each tau in [tau_min, tau_max], the
+// sorted (key, g) entries and the bucket table of the even-partition segments (Sec. 3.1, 3.2).
+// pj_query groups the queries by their threshold and runs the two-set join of Sec. 3.2 of each
+// group against the index of that threshold.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/passjoin.h"
+#include "pj_host_internal.h"
+#include "pj_internal.h"
+
+struct pj_index {
+    int tau_min = 0, tau_max = -1;
+    pj::Owned mem;
+    pj::DevSet S;
+    std::vector<pj::DevIndex> X;
+};
+
+namespace pj {
+
+void validate_host_strings(const pj_strings* S, const char* what);
+
+const DevSet& index_set(const pj_index* idx) { return idx->S; }
+const DevIndex& index_for(const pj_index* idx, int tau) { return idx->X[tau - idx->tau_min]; }
+void index_taus(const pj_index* idx, int* lo, int* hi)
+{
+    *lo = idx->tau_min;
+    *hi = idx->tau_max;
+}
+
+// Host copy of a string set whose pointers may be device pointers.
+struct HostStrings {
+    std::vector<uint8_t> bytes;
+    std::vector<int32_t> offs;
+    pj_strings view{};
+};
+
+static void to_host(const pj_strings* Q, bool on_device, HostStrings& H)
+{
+    if (!on_device) {
+        H.view = *Q;
+        return;
+    }
+    if (Q->n < 0 || !Q->offsets) throw Error(PJ_EINVAL, "Q: bad strings");
+    H.offs.resize((size_t)Q->n + 1);
+    hip_check(hipMemcpy(H.offs.data(), Q->offsets, sizeof(int32_t) * H.offs.size(),
+                        hipMemcpyDeviceToHost), "download offsets");
+    int64_t total = H.offs.back();
+    if (total < 0) throw Error(PJ_EINVAL, "Q: bad offsets");
+    H.bytes.resize((size_t)total + 1);
+    if (total > 0)
+        hip_check(hipMemcpy(H.bytes.data(), Q->bytes, (size_t)total, hipMemcpyDeviceToHost),
+                  "download bytes");
+    H.view.n = Q->n;
+    H.view.bytes = H.bytes.data();
+    H.view.offsets = H.offs.data();
+}
+
+// Runs the queries `ids` (all with threshold tau) against the index; appends (q, s) pairs.
+void query_group(const pj_index* idx, const pj_strings* Q, const std::vector<int32_t>& ids,
+                 int tau, std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st)
+{
+    std::vector<uint8_t> bytes;
+    std::vector<int32_t> offs(1, 0);
+    for (int32_t q : ids) {
+        int32_t a = Q->offsets[q], b = Q->offsets[q + 1];
+        bytes.insert(bytes.end(), Q->bytes + a, Q->bytes + b);
+        offs.push_back((int32_t)bytes.size());
+    }
+    pj_strings sub{(int64_t)ids.size(), bytes.empty() ? nullptr : bytes.data(), offs.data()};
+    Workspace& W = thread_workspace();
+    DevSet P;
+    build_set(&sub, false, W, "Q", P, st);
+    JoinScratch J;
+    Timer tm(st);
+    run_candidates(P, idx->S, index_for(idx, tau), tau, false, J, stats, tm, st);
+    int32_t *da = nullptr, *db = nullptr;
+    uint64_t M = finish_pairs(P, idx->S, false, J.out, J.naccepted, &da, &db, st);
+    std::vector<int32_t> ha(M), hb(M);
+    if (M) {
+        hip_check(hipMemcpyAsync(ha.data(), da, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "d2h");
+        hip_check(hipMemcpyAsync(hb.data(), db, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "d2h");
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+    for (uint64_t k = 0; k < M; ++k)
+        pairs.push_back(((uint64_t)(uint32_t)ids[(size_t)ha[k]] << 32) | (uint32_t)hb[k]);
+}
+
+}  // namespace pj
+
+using namespace pj;
+
+extern "C" {
+
+int pj_build_index(const pj_strings* S, int32_t tau_min, int32_t tau_max, const pj_options* opt,
+                   pj_index** out)
+{
+    t_stats = pj_stats{};
+    try {
+        if (!out) throw Error(PJ_EINVAL, "null output");
+        *out = nullptr;
+        if (tau_min < 0 || tau_max > kTauMax || tau_min > tau_max)
+            throw Error(PJ_EINVAL, "tau range [%d, %d] invalid", tau_min, tau_max);
+        bool on_dev = opt && opt->inputs_on_device;
+        if (!on_dev) validate_host_strings(S, "S");
+        else if (!S) throw Error(PJ_EINVAL, "null pj_strings");
+        hipStream_t st = opt ? (hipStream_t)opt->hip_stream : (hipStream_t)0;
+        auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<pj_index> idx(new pj_index());
+        idx->tau_min = tau_min;
+        idx->tau_max = tau_max;
+        idx->mem.budget = opt ? opt->mem_budget_bytes : 0;
+        thread_workspace().begin_call(0);
+        build_set(S, on_dev, idx->mem, "I", idx->S, st);
+        idx->X.resize((size_t)(tau_max - tau_min + 1));
+        int64_t entries = 0;
+        for (int t = tau_min; t <= tau_max; ++t) {
+            build_index(idx->S, t, idx->mem, "I.t" + std::to_string(t), idx->X[(size_t)(t - tau_min)], st);
+            entries += idx->X[(size_t)(t - tau_min)].entries;
+        }
+        hip_check(hipStreamSynchronize(st), "sync");
+        t_stats.strings = idx->S.n;
+        t_stats.index_entries = entries;
+        t_stats.ms_index = std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - t0).count();
+        t_stats.ms_total = t_stats.ms_index;
+        *out = idx.release();
+        t_last_ok_stats = t_stats;
+        t_last_error.clear();
+        return PJ_OK;
+    } catch (const Error& e) {
+        t_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        t_last_error = "host allocation failed";
+        return PJ_ENOMEM;
+    }
+}
+
+int pj_index_info(const pj_index* idx, int64_t* n, int32_t* tau_min, int32_t* tau_max,
+                  int64_t* device_bytes)
+{
+    if (!idx) {
+        t_last_error = "null index";
+        return PJ_EINVAL;
+    }
+    if (n) *n = idx->S.n;
+    if (tau_min) *tau_min = idx->tau_min;
+    if (tau_max) *tau_max = idx->tau_max;
+    if (device_bytes) *device_bytes = (int64_t)idx->mem.used;
+    return PJ_OK;
+}
+
+void pj_index_free(pj_index* idx) { delete idx; }
+
+int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, const pj_options* opt,
+             pj_pairs* out)
+{
+    t_stats = pj_stats{};
+    if (out) {
+        out->count = 0;
+        out->a = out->b = nullptr;
+        out->on_device = 0;
+    }
+    try {
+        if (!out) throw Error(PJ_EINVAL, "null output");
+        if (!idx) throw Error(PJ_EINVAL, "null index");
+        if (!Q) throw Error(PJ_EINVAL, "null pj_strings");
+        if (!taus && Q->n > 0) throw Error(PJ_EINVAL, "null taus");
+        bool on_dev = opt && opt->inputs_on_device;
+        if (!on_dev) validate_host_strings(Q, "Q");
+        for (int64_t q = 0; q < Q->n; ++q)
+            if (taus[q] < idx->tau_min || taus[q] > idx->tau_max)
+                throw Error(PJ_ERANGE, "query %lld: tau %d outside the index range [%d, %d]",
+                            (long long)q, taus[q], idx->tau_min, idx->tau_max);
+        hipStream_t st = opt ? (hipStream_t)opt->hip_stream : (hipStream_t)0;
+        auto t0 = std::chrono::steady_clock::now();
+        HostStrings H;
+        to_host(Q, on_dev, H);
+        if (on_dev) validate_host_strings(&H.view, "Q");
+        thread_workspace().begin_call(opt ? opt->mem_budget_bytes : 0);
+        std::vector<std::vector<int32_t>> groups((size_t)(idx->tau_max - idx->tau_min + 1));
+        for (int64_t q = 0; q < Q->n; ++q) groups[(size_t)(taus[q] - idx->tau_min)].push_back((int32_t)q);
+        std::vector<uint64_t> pairs;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            if (groups[g].empty()) continue;
+            thread_workspace().begin_call(opt ? opt->mem_budget_bytes : 0);
+            query_group(idx, &H.view, groups[g], idx->tau_min + (int)g, pairs, t_stats, st);
+        }
+        std::sort(pairs.begin(), pairs.end());
+        uint64_t M = pairs.size();
+        std::vector<int32_t> a(M), b(M);
+        for (uint64_t k = 0; k < M; ++k) {
+            a[k] = (int32_t)(pairs[k] >> 32);
+            b[k] = (int32_t)(pairs[k] & 0xffffffffu);
+        }
+        bool to_dev = opt && opt->outputs_on_device;
+        size_t bytes = sizeof(int32_t) * (size_t)std::max<uint64_t>(M, 1);
+        out->count = (int64_t)M;
+        out->on_device = to_dev ? 1 : 0;
+        if (to_dev) {
+            void *pa = nullptr, *pb = nullptr;
+            if (hipMalloc(&pa, bytes) != hipSuccess || hipMalloc(&pb, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                if (pa) (void)hipFree(pa);
+                throw Error(PJ_ENOMEM, "output allocation failed");
+            }
+            out->a = (int32_t*)pa;
+            out->b = (int32_t*)pb;
+            if (M) {
+                hip_check(hipMemcpy(pa, a.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice), "h2d");
+                hip_check(hipMemcpy(pb, b.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice), "h2d");
+            }
+        } else {
+            out->a = (int32_t*)malloc(bytes);
+            out->b = (int32_t*)malloc(bytes);
+            if (!out->a || !out->b) throw Error(PJ_ENOMEM, "host output allocation failed");
+            if (M) {
+                memcpy(out->a, a.data(), sizeof(int32_t) * M);
+                memcpy(out->b, b.data(), sizeof(int32_t) * M);
+            }
+        }
+        t_stats.strings = Q->n;
+        t_stats.pairs = (int64_t)M;
+        t_stats.ms_total = std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - t0).count();
+        t_last_ok_stats = t_stats;
+        t_last_error.clear();
+        return PJ_OK;
+    } catch (const Error& e) {
+        t_last_error = e.msg;
+        pj_pairs_free(out);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        t_last_error = "host allocation failed";
+        pj_pairs_free(out);
+        return PJ_ENOMEM;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// pj_internal.h -- types and kernel launchers shared by the device and host parts of libpassjoin.
+//
+// Device data layout (all in HBM, built once per string set):
+//   * length-sorted arena: strings reordered by (length, id) and stored back to back, each at a
+//     4-byte aligned slot of stride(l) = round_up(l, 4) bytes, so the byte offset of the string at
+//     sorted position g of length l is gbase[l] + (g - lenstart[l]) * stride(l) -- computed from
+//     two per-length tables, never gathered per string;
+//   * perm[g] = original id of sorted position g, slen[g] = its length;
+//   * segment index for one tau: (key, g) entries sorted by key, key = group(l, i) << 40 |
+//     hash(segment) >> 24, group(l, i) = (l - (tau+1)) * (tau+1) + (i-1); equal keys form one
+//     inverted list L_l^i(w) whose members are in ascending g (Sec. 3.2);
+//   * bucket table: open-addressing hash table key -> (start, count) of the list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pj {
+
+constexpr int kLenMax = 2047;          // PJ_LEN_MAX
+constexpr int kLenTab = kLenMax + 2;   // per-length tables are indexed 0 .. kLenMax + 1
+constexpr int kTauMax = 63;            // PJ_TAU_MAX
+constexpr int kHashBits = 40;          // hash bits kept in an index key
+constexpr uint64_t kEmptyKey = ~0ull;  // keys use at most 57 bits, so this never collides
+
+__host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 3) & ~3); }
+
+// Length-sorted device arena of one string set.
+struct DevSet {
+    int64_t n = 0;
+    int lmin = 0, lmax = -1;            // smallest / largest length present (lmax < lmin: empty)
+    int64_t arena_bytes = 0;
+    uint8_t* sarena = nullptr;          // padded, length-sorted bytes
+    int32_t* perm = nullptr;            // [n] sorted position -> id
+    uint16_t* slen = nullptr;           // [n] sorted position -> length
+    int32_t* lenstart = nullptr;        // [kLenTab + 1] first sorted position of each length
+    int64_t* gbase = nullptr;           // [kLenTab] byte base of each length group
+    // host copies of the per-length tables
+    int32_t h_lenstart[kLenTab + 1];
+    int64_t h_gbase[kLenTab];
+};
+
+// Segment index of one set for one tau.
+struct DevIndex {
+    int tau = 0;
+    int64_t entries = 0;                // (string, slot) entries
+    int64_t lists = 0;                  // distinct keys (inverted lists)
+    uint64_t* keys = nullptr;           // [entries] sorted
+    uint32_t* vals = nullptr;           // [entries] sorted position g of the string
+    uint4* table = nullptr;             // [mask + 1] {key lo, key hi, start, count}
+    uint64_t mask = 0;
+};
+
+// One selected substring that found a non-empty list: candidates (vals[start + m], x, i, p).
+struct Hit {
+    uint32_t gx;      // sorted position of the probe string in the probe set
+    uint32_t start;   // first entry of the list in DevIndex::vals
+    uint32_t count;   // list members that are candidates (after the visiting-order filter)
+    uint32_t meta;    // (p - 1) | (i - 1) << 11 | l << 17
+};
+
+struct ProbeParams {
+    // probe side
+    const uint8_t* x_arena; const uint16_t* x_slen; const int32_t* x_lenstart;
+    const int64_t* x_gbase;
+    uint32_t g_begin;           // first probe position
+    uint64_t threads;           // probe positions * nl * (tau+1)
+    int nl;                     // lengths probed per string: tau+1 (self) or 2tau+1 (two sets)
+    int self;                   // 1: self-join (l in [n-tau, n], y before x when l == n)
+    const int32_t* q_tau;       // per-probe tau (serving) or nullptr (uniform tau)
+    // index side
+    const int32_t* y_lenstart;  // to know which lengths are present
+    const uint64_t* keys; const uint32_t* vals; const uint4* table; uint64_t mask;
+    int tau;
+    int ymin, ymax;             // indexed lengths present
+    // output
+    Hit* hits; uint64_t hit_cap;
+    unsigned long long* counters;   // [0] hits, [1] candidates, [2] selected
+};
+
+struct VerifyParams {
+    const uint8_t* x_arena; const uint16_t* x_slen; const int32_t* x_lenstart;
+    const int64_t* x_gbase;
+    const uint8_t* y_arena; const int32_t* y_lenstart; const int64_t* y_gbase;
+    const uint32_t* vals;
+    const Hit* hits; const unsigned long long* prefix;   // [nhits + 1] exclusive prefix of counts
+    uint64_t nhits; uint64_t ncand;
+    int tau;
+    uint64_t* out; uint64_t out_cap;                      // accepted (gx << 32 | gy)
+    unsigned long long* counters;                         // [3] accepted, [4] cells, [5] guard misses
+};
+
+// ---- launchers (pj_device.hip) ----
+hipError_t launch_length_hist(const int32_t* offs, int64_t n, int32_t* lcount, int32_t* err,
+                              hipStream_t s);
+hipError_t launch_iota_len_keys(const int32_t* offs, int64_t n, uint32_t* keys, uint32_t* vals,
+                                hipStream_t s);
+hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const int32_t* perm,
+                             int64_t n, const int32_t* lenstart, const int64_t* gbase,
+                             uint8_t* sarena, uint16_t* slen, hipStream_t s);
+hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
+                                int64_t g_first, int64_t g_count, uint64_t* keys, uint32_t* vals,
+                                hipStream_t s);
+hipError_t launch_mark_heads(const uint64_t* keys, int64_t E, uint32_t* flags, hipStream_t s);
+hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid, int64_t E,
+                                   uint32_t* runstart, hipStream_t s);
+hipError_t launch_clear_table(uint4* table, uint64_t slots, hipStream_t s);
+hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                              uint32_t E, uint4* table, uint64_t mask, hipStream_t s);
+hipError_t launch_probe(const ProbeParams& P, hipStream_t s);
+hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
+hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
+hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self,
+                             uint64_t* out, uint64_t out_cap, unsigned long long* counters,
+                             hipStream_t s);
+hipError_t launch_pairs_to_keys(const uint64_t* acc, uint64_t m, const int32_t* xperm,
+                                const int32_t* yperm, int self, int bbits, uint64_t* keys,
+                                hipStream_t s);
+hipError_t launch_unique_flags(const uint64_t* keys, uint64_t m, uint32_t* flags, hipStream_t s);
+hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, const uint32_t* pos,
+                                uint64_t m, int bbits, int32_t* a, int32_t* b, hipStream_t s);
+
+// Exclusive scans; out has n + 1 entries (out[n] = total).
+hipError_t scan_u32_to_u32(const uint32_t* in, uint32_t* out, uint64_t n, void* tmp,
+                           size_t tmp_bytes, hipStream_t s);
+hipError_t scan_u32_to_u64(const uint32_t* in, unsigned long long* out, uint64_t n, void* tmp,
+                           size_t tmp_bytes, hipStream_t s);
+size_t scan_tmp_bytes(uint64_t n);
+
+// Stable LSD radix sort by the low `bits` bits of the keys, 8 bits per pass.  Buffers ping-pong;
+// returns in *result_in_alt whether the sorted data ended in the alternate buffers.
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                          uint32_t* vals_alt, uint64_t n, int bits, void* tmp, size_t tmp_bytes,
+                          bool* result_in_alt, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                          uint32_t* vals_alt, uint64_t n, int bits, void* tmp, size_t tmp_bytes,
+                          bool* result_in_alt, hipStream_t s);
+size_t radix_tmp_bytes(uint64_t n);
+
+}  // namespace pj

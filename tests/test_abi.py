@@ -1,0 +1,71 @@
+"""The C ABI library loads, exports every function include/passjoin.h declares, and rejects
+invalid host inputs before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1111_7171_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "passjoin.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pj_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for need in ("pj_self_join", "pj_join", "pj_build_index", "pj_query", "pj_pairs_free",
+                 "pj_index_free", "pj_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), C._CFuncPtr)
+
+
+def test_version_string():
+    assert P.pj_version().startswith("passjoin")
+
+
+def _err(fn, *a, **k):
+    with pytest.raises(P.PassJoinError) as ei:
+        fn(*a, **k)
+    return ei.value.code
+
+
+def test_invalid_inputs_rejected_on_host():
+    ok = (np.frombuffer(b"abcabc", np.uint8), np.array([0, 3, 6], np.int32))
+    assert _err(P.pj_self_join, ok, -1) == P.PJ_EINVAL
+    assert _err(P.pj_self_join, ok, 64) == P.PJ_EINVAL
+    assert _err(P.pj_self_join, (ok[0], np.array([1, 3, 6], np.int32)), 1) == P.PJ_EINVAL
+    assert _err(P.pj_self_join, (ok[0], np.array([0, 4, 3], np.int32)), 1) == P.PJ_EINVAL
+    long = np.zeros(2048, np.uint8)
+    assert _err(P.pj_self_join, (long, np.array([0, 2048], np.int32)), 1) == P.PJ_ERANGE
+    assert _err(P.pj_join, ok, (ok[0], np.array([0, 5, 3], np.int32)), 1) == P.PJ_EINVAL
+    assert "offsets" in P.pj_last_error()
+
+
+def test_null_arguments_rejected():
+    lib = P.load()
+    assert lib.pj_self_join(None, 1, None, None) == P.PJ_EINVAL
+    raw = P.PjPairs()
+    assert lib.pj_self_join(None, 1, None, C.byref(raw)) == P.PJ_EINVAL
+    assert raw.count == 0 and not raw.a
+    h = C.c_void_p()
+    s = P.PjStrings(0, None, None)
+    assert lib.pj_build_index(C.byref(s), 3, 2, None, C.byref(h)) == P.PJ_EINVAL
+    assert not h.value
+    assert lib.pj_query(None, C.byref(s), None, None, C.byref(raw)) == P.PJ_EINVAL
+    assert lib.pj_index_info(None, None, None, None, None) == P.PJ_EINVAL
+    lib.pj_index_free(None)
+    lib.pj_pairs_free(None)
+    lib.pj_pairs_free(C.byref(raw))

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP join equals the oracle bit-exactly (sorted pair lists), and its candidate
+and cell counts equal the oracle's Pass-Join counts.  Every call goes through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1111_7171_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _same(got, exp, what=""):
+    assert got.dtype == np.int32 and got.ndim == 2 and got.shape[1] == 2
+    if not np.array_equal(got, exp):
+        g = {tuple(p) for p in got.tolist()}
+        e = {tuple(p) for p in exp.tolist()}
+        raise AssertionError(f"{what}: {len(got)} pairs vs {len(exp)} expected; "
+                             f"missing {sorted(e - g)[:5]} extra {sorted(g - e)[:5]}")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.load()
+    yield
+
+
+def test_table1_all_tau(golden):
+    col = W.from_list(golden["table1"]["strings"])
+    for tau in range(0, 8):
+        _say("table1 tau", tau)
+        _same(P.pj_self_join(col, tau), O.self_join_bf(col, tau, 1), f"tau={tau}")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_self_join(seed):
+    rng = np.random.default_rng(1000 + seed)
+    alph = [b"ab", b"abc", b"abcd", b"abcdefgh"][seed % 4]
+    col = W.random_small(rng, 400, alphabet=alph, lmin=0, lmax=16, dup_frac=0.4, kmax=3)
+    for tau in range(0, 6):
+        _say("random self seed", seed, "tau", tau)
+        got = P.pj_self_join(col, tau)
+        _same(got, O.self_join_bf(col, tau, 8), f"seed={seed} tau={tau}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small_join(seed):
+    rng = np.random.default_rng(2000 + seed)
+    alph = [b"ab", b"abc", b"abcd", b"abcdefgh"][seed % 4]
+    R = W.random_small(rng, 250, alphabet=alph, lmin=0, lmax=14, dup_frac=0.3)
+    S = W.random_small(rng, 300, alphabet=alph, lmin=0, lmax=14, dup_frac=0.3)
+    for tau in range(0, 6):
+        _say("random join seed", seed, "tau", tau)
+        _same(P.pj_join(R, S, tau), O.join_bf(R, S, tau, 8), f"seed={seed} tau={tau}")
+
+
+def test_cfg1_full_exact_pairs_and_counts():
+    col = W.cfg1()
+    exp = O.self_join_bf(col, 2)
+    got = P.pj_self_join(col, 2)
+    st = P.pj_last_stats()
+    _same(got, exp, "cfg1")
+    pj = O.self_join_pj(col, 2)
+    assert st["candidates"] == pj.candidates
+    assert st["cells"] == pj.cells
+    assert st["selected"] == pj.selected
+
+
+@pytest.mark.parametrize("cfg,n,taus", [
+    (2, 20_000, (1, 2, 3, 4)),
+    (3, 8_000, (2, 4, 6, 8)),
+    (4, 1_500, (8, 16, 32)),
+])
+def test_scaled_configs_match_oracle(cfg, n, taus):
+    col = W.CONFIGS[cfg](n)
+    for tau in taus:
+        _say("cfg", cfg, "n", n, "tau", tau)
+        pj = O.self_join_pj(col, tau)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"cfg{cfg} tau={tau}")
+        assert st["candidates"] == pj.candidates, (st["candidates"], pj.candidates)
+        assert st["cells"] == pj.cells, (st["cells"], pj.cells)
+
+
+def test_join_two_sets_counts():
+    R = W.cfg2(6000, seed=7)
+    S = W.cfg2(9000, seed=8)
+    for tau in (1, 2, 3):
+        _say("join tau", tau)
+        pj = O.join_pj(R, S, tau)
+        got = P.pj_join(R, S, tau)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"join tau={tau}")
+        assert st["candidates"] == pj.candidates
+
+
+def test_edge_cases():
+    # empty set, one string, all-empty strings, all shorter than tau+1, exact duplicates
+    empty = W.from_list([])
+    assert P.pj_self_join(empty, 2).shape == (0, 2)
+    one = W.from_list([b"abc"])
+    assert P.pj_self_join(one, 2).shape == (0, 2)
+    blanks = W.from_list([b""] * 5)
+    _same(P.pj_self_join(blanks, 0), O.self_join_bf(blanks, 0, 1), "blanks")
+    shorts = W.from_list([b"a", b"b", b"ab", b"", b"ba", b"abc"])
+    for tau in range(0, 5):
+        _same(P.pj_self_join(shorts, tau), O.self_join_bf(shorts, tau, 1), f"shorts {tau}")
+    dups = W.from_list([b"hello world"] * 7 + [b"hello warld"] * 3)
+    for tau in (0, 1, 2):
+        _same(P.pj_self_join(dups, tau), O.self_join_bf(dups, tau, 1), f"dups {tau}")
+    # join with an empty side
+    _same(P.pj_join(empty, dups, 1), np.empty((0, 2), np.int32), "empty R")
+    _same(P.pj_join(dups, empty, 1), np.empty((0, 2), np.int32), "empty S")
+
+
+def test_maximum_length_and_tau():
+    rng = np.random.default_rng(5)
+    base = bytes(rng.integers(97, 101, size=2047).astype(np.uint8))
+    strs = [base]
+    for k in range(5):
+        b = bytearray(base)
+        for _ in range(k * 12):
+            b[int(rng.integers(len(b)))] = int(rng.integers(97, 101))
+        strs.append(bytes(b[: 2047 - k]))
+    col = W.from_list(strs)
+    for tau in (0, 31, 63):
+        _say("maxlen tau", tau)
+        _same(P.pj_self_join(col, tau), O.self_join_bf(col, tau, 4), f"maxlen tau={tau}")
+
+
+def test_device_inputs_and_outputs():
+    import torch
+    col = W.cfg1(4000)
+    chars = torch.from_numpy(col.chars.copy()).cuda()
+    offs = torch.from_numpy(col.offsets.copy()).cuda()
+    host = P.pj_self_join(col, 2)
+    dev_in = P.pj_self_join((chars, offs), 2)
+    _same(dev_in, host, "device inputs")
+    dp = P.pj_self_join((chars, offs), 2, outputs_on_device=True)
+    try:
+        _same(dp.to_numpy(), host, "device outputs")
+    finally:
+        dp.free()
+
+
+def test_query_matches_oracle_per_tau():
+    S = W.cfg5_index(20_000)
+    rng = np.random.default_rng(9)
+    Q, taus = W.cfg5_batch(rng, S, mean=64)
+    idx = P.pj_build_index(S, 1, 8)
+    try:
+        got = P.pj_query(idx, Q, taus)
+    finally:
+        idx.free()
+    exp = []
+    for t in range(1, 9):
+        ids = np.nonzero(taus == t)[0]
+        if len(ids) == 0:
+            continue
+        sub = Q.subset(ids)
+        for a, b in O.join_pj(sub, S, t).pairs.tolist():
+            exp.append((int(ids[a]), b))
+    exp = np.array(sorted(exp), dtype=np.int32).reshape(-1, 2)
+    _same(got, exp, "query")
+
+
+def test_repeatable_runs_identical():
+    col = W.cfg2(30_000, seed=11)
+    a = P.pj_self_join(col, 3)
+    b = P.pj_self_join(col, 3)
+    assert np.array_equal(a, b)
