@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: Pass-Join self-join of the short-string collection on one MI355X.
+
+One step = the self-join of 1,000,000 synthetic short strings (lengths ~N(15, 4) in [5, 40],
+27 symbols with English letter frequencies, 30% near-duplicates with 1-4 edits) at every
+threshold tau in {1, 2, 3, 4}: all phases (arena, index, probe, verify, short path, dedupe) run
+on the GPU with inputs resident in HBM and the pairs left in HBM.
+
+Prints ONE JSON line on stdout.  `value` is candidates verified per second over the whole
+step (the candidate count is the paper's: every (y, x, i, p) the multi-match probe generates).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline
+PEAK_HBM_GBS = 8000.0
+CUS, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
+PEAK_INT32_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0      # 39.3 T int32 lane-ops/s
+OPS_PER_CELL = 7   # recurrence: compare, add, min, add, min; expected distance: add, min
+
+WORKLOAD = ("cfg2 short-string self-join: 1,000,000 strings, lengths round(N(15,4)) in [5,40], "
+            "27 symbols (a-z, space) with English letter frequencies, 30% near-duplicates with "
+            "1-4 edits, tau in {1,2,3,4}")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1111_7171_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, sha: str):
+    """HBM traffic per launch measured by rocprofv3 PMC runs (profiles/traffic.json), only if
+    the kernels have not changed since."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    e = d.get(kernel)
+    if not e or e.get("source_sha") != sha:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(col, taus):
+    """The oracle's Pass-Join (single-threaded C) on a bounded sample: every string is indexed,
+    every k-th visited string probes.  Returns candidates per second."""
+    import oracle as O
+    strides = {1: 1, 2: 4, 3: 30, 4: 200}
+    cands, secs = 0, 0.0
+    parts = []
+    for t in taus:
+        k = strides.get(t, 200)
+        t0 = time.perf_counter()
+        r = O.self_join_pj(col, t, probe_stride=k)
+        dt = time.perf_counter() - t0
+        cands += r.candidates
+        secs += dt
+        parts.append(f"tau={t}: every {k}th probe string, {r.candidates} candidates, {dt:.1f}s")
+        log("cpu baseline", parts[-1])
+    return {"value": cands / secs, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+            "sample": "all 1,000,000 strings indexed; " + "; ".join(parts) +
+                      " (time includes the oracle's index build)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--taus", default="1,2,3,4")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 plain, 2 batched")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (PMC calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the Pass-Join hot path here is a single-GPU build "
+              "(multi-GPU sharding is a design note, not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1111_7171_amd as P
+    import workloads as W
+
+    taus = [int(t) for t in args.taus.split(",")]
+    log(f"generating workload n={args.n}")
+    col = W.cfg2(args.n)
+    dev = torch.device("cuda:0")
+    chars = torch.from_numpy(col.chars.copy()).to(dev)
+    offs = torch.from_numpy(col.offsets.copy()).to(dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    if args.calib_copy_mib:
+        nbytes = args.calib_copy_mib << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes x 3")
+
+    def step(collect):
+        outs = []
+        for t in taus:
+            r = P.pj_self_join((chars, offs), t, mode=args.mode, outputs_on_device=True,
+                               stream=stream)
+            st = P.pj_last_stats()
+            outs.append(r)
+            if collect is not None:
+                collect.append((t, st))
+        return outs
+
+    for w in range(args.warmup):
+        for r in step(None):
+            r.free()
+        log(f"warmup {w + 1}/{args.warmup} done")
+
+    torch.cuda.synchronize()
+    stats = []
+    keep = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        keep.extend(step(stats))
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for r in keep:
+        r.free()
+
+    cand = sum(s["candidates"] for _, s in stats)
+    cells = sum(s["cells"] for _, s in stats)
+    verify_ms = sum(s["ms_verify_kernel"] for _, s in stats)
+    verify_launches = sum(s["verify_launches"] for _, s in stats)
+    probe_ms = sum(s["ms_probe_kernel"] for _, s in stats)
+    per_tau = {}
+    for t, s in stats[-len(taus):]:
+        per_tau[str(t)] = {
+            "ms": round(s["ms_total"], 3), "candidates": s["candidates"], "cells": s["cells"],
+            "pairs": s["pairs"], "selected": s["selected"], "hits": s["hits"],
+            "index_entries": s["index_entries"],
+            "ms_index": round(s["ms_index"], 3), "ms_probe": round(s["ms_probe"], 3),
+            "ms_verify": round(s["ms_verify"], 3), "ms_output": round(s["ms_output"], 3),
+            "ms_verify_kernel": round(s["ms_verify_kernel"], 3),
+            "candidates_per_s": s["candidates"] / max(s["ms_total"], 1e-9) * 1e3,
+            "gcups": s["cells"] / max(s["ms_verify_kernel"], 1e-9) / 1e6,
+        }
+
+    sha = kernel_source_sha()
+    # dominant kernel: verification; algorithmic work = OPS_PER_CELL integer ops per DP cell
+    per_launch_s = verify_ms / 1e3 / max(verify_launches, 1)
+    ops_per_launch = OPS_PER_CELL * cells / max(verify_launches, 1)
+    achieved = ops_per_launch / max(per_launch_s, 1e-12) / 1e12
+    traffic = load_traffic("k_verify", sha)
+    line = {
+        "metric": "self-join wall time, candidates/s, GCUPS; serving p50/p99 latency at fixed QPS",
+        "value": cand / elapsed,
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": args.n, "taus": taus, "mode": args.mode},
+        "gcups": cells / max(verify_ms, 1e-9) / 1e6,
+        "self_join_ms": {k: v["ms"] for k, v in per_tau.items()},
+        "per_tau": per_tau,
+        "probe_kernel_ms_per_step": probe_ms / args.steps,
+        "verify_kernel_ms_per_step": verify_ms / args.steps,
+        "roofline": {
+            "kernel": "k_verify",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_INT32_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / PEAK_INT32_TOPS,
+            "traffic": traffic,
+            "ops_per_cell": OPS_PER_CELL,
+            "launches": verify_launches,
+            "avg_launch_ms": per_launch_s * 1e3,
+        },
+        "kernel_source_sha": sha,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(col, taus)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,9 @@ typedef struct {
     int64_t side_pairs;    /* pairs examined directly because a string is shorter than tau+1 */
     int64_t pairs;         /* pairs reported */
     double ms_upload, ms_index, ms_probe, ms_verify, ms_output, ms_total;
+    double ms_probe_kernel;    /* device time of the probe kernel launches (hipEvents) */
+    double ms_verify_kernel;   /* device time of the verification kernel launches (hipEvents) */
+    int64_t verify_launches;   /* verification kernel launches */
 } pj_stats;
 
 /* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with

@@ -59,7 +59,9 @@ class PjStats(C.Structure):
                                          "candidates", "cells", "accepted", "side_pairs",
                                          "pairs")] + \
                [(k, C.c_double) for k in ("ms_upload", "ms_index", "ms_probe", "ms_verify",
-                                          "ms_output", "ms_total")]
+                                          "ms_output", "ms_total", "ms_probe_kernel",
+                                          "ms_verify_kernel")] + \
+               [("verify_launches", C.c_int64)]
 
 
 _lib = None

@@ -418,7 +418,10 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
         pp.hits = J.hits; pp.hit_cap = bound;
         pp.counters = J.counters;
+        int k0 = tm.mark();
         hip_check(launch_probe(pp, st), "probe");
+        int k1 = tm.mark();
+        J.kernel_marks.push_back({k0, k1, 0});
     }
     unsigned long long c[8];
     hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
@@ -444,7 +447,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
     }
 
     // verify (+ short path); rerun once with an exact buffer when the first guess overflows
-    uint64_t cap = std::min<uint64_t>(J.ncand + 4096, 1ull << 26);
+    uint64_t cap = std::min<uint64_t>(J.ncand + 4096, 1ull << 28);
     for (int attempt = 0; attempt < 2; ++attempt) {
         J.out = (uint64_t*)W.get("join.out", sizeof(uint64_t) * (size_t)cap);
         hip_check(hipMemsetAsync(J.counters + 3, 0, 5 * sizeof(unsigned long long), st), "memset");
@@ -461,7 +464,11 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
             vp.counters = J.counters;
             uint64_t nchunks = (J.ncand + 1023) / 1024;
             int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 16);
+            int k0 = tm.mark();
             hip_check(launch_verify(vp, grid, st), "verify");
+            int k1 = tm.mark();
+            J.kernel_marks.push_back({k0, k1, 1});
+            stats.verify_launches += 1;
         }
         hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, J.out, cap, J.counters, st),
                   "short_path");
@@ -478,6 +485,12 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
     J.guard_misses = c[5];
     stats.ms_probe += tm.ms(t_probe0, t_probe1);
     stats.ms_verify += tm.ms(t_probe1, t_verify1);
+    for (const auto& km : J.kernel_marks) {
+        double v = tm.ms(km.a, km.b);
+        if (km.kind == 0) stats.ms_probe_kernel += v;
+        else stats.ms_verify_kernel += v;
+    }
+    J.kernel_marks.clear();
 }
 
 // Sorts and deduplicates accepted (gx, gy) into id pairs; returns device arrays (workspace).

@@ -70,6 +70,8 @@ struct JoinScratch {
     uint64_t* out = nullptr;
     uint64_t naccepted = 0;
     uint64_t guard_misses = 0;
+    struct Mark { int a, b, kind; };     // event pairs around kernel launches (0 probe, 1 verify)
+    std::vector<Mark> kernel_marks;
 };
 
 void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
