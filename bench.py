@@ -8,6 +8,8 @@ on the GPU with inputs resident in HBM and the pairs left in HBM.
 
 Prints ONE JSON line on stdout.  `value` is candidates verified per second over the whole
 step (the candidate count is the paper's: every (y, x, i, p) the multi-match probe generates).
+The line also carries a serving measurement (p50/p99 latency at fixed arrival rates over a
+resident index; see serving_bench) unless --no-serve is given.
 """
 from __future__ import annotations
 
@@ -82,6 +84,100 @@ def cpu_baseline(col, taus):
                       " (time includes the oracle's index build)"}
 
 
+def serving_bench(P, W, n_index: int, seconds: float, slots: int):
+    """Open-loop serving: batches of Poisson(64) queries (tau U{1..8}, lengths U{10..120}, half
+    edited copies of indexed strings) arrive as a Poisson process against a resident index of
+    n_index strings.  The arrival rate is fixed at 50% and 80% of the closed-loop saturation
+    throughput measured first.  Latency = submit -> pairs in host memory (server clock)."""
+    import threading
+
+    import numpy as np
+    log(f"serving: building index of {n_index} strings, tau 1..8")
+    S = W.cfg5_index(n_index)
+    t0 = time.perf_counter()
+    idx = P.pj_build_index(S, 1, 8)
+    build_s = time.perf_counter() - t0
+    info = idx.info()
+    rng = np.random.default_rng(71715)
+    pool = [W.cfg5_batch(rng, S) for _ in range(256)]
+    out = {"index_strings": n_index, "index_build_s": round(build_s, 3),
+           "index_device_bytes": info["device_bytes"], "slots": slots}
+    with P.Server(idx, slots=slots, max_batch_queries=512, mem_budget=8 << 30) as srv:
+        for k in range(8):                                   # warm the slots' scratch
+            srv.wait(srv.submit(*pool[k]))
+        # closed loop: keep 2 * slots batches outstanding
+        t_end = time.perf_counter() + max(2.0, seconds / 4)
+        pend, done, k = [], 0, 0
+        t0 = time.perf_counter()
+        while time.perf_counter() < t_end or pend:
+            while time.perf_counter() < t_end and len(pend) < 2 * slots:
+                pend.append(srv.submit(*pool[k % len(pool)]))
+                k += 1
+            srv.wait(pend.pop(0))
+            done += 1
+        sat = done / (time.perf_counter() - t0)
+        out["saturation_batches_per_s"] = round(sat, 2)
+        levels = []
+        for frac in (0.5, 0.8):
+            lam = frac * sat
+            ids, lock = [], threading.Lock()
+            stop = threading.Event()
+            lats, nq, batch_sizes = [], [0], []
+
+            def collector():
+                j = 0
+                while True:
+                    with lock:
+                        have = j < len(ids)
+                    if not have:
+                        if stop.is_set():
+                            with lock:
+                                if j >= len(ids):
+                                    return
+                        time.sleep(0.0005)
+                        continue
+                    rid, m = ids[j]
+                    _, inf = srv.wait(rid)
+                    lats.append(inf["t_done_ms"] - inf["t_submit_ms"])
+                    batch_sizes.append(inf["batch_requests"])
+                    nq[0] += m
+                    j += 1
+
+            th = threading.Thread(target=collector)
+            th.start()
+            arr = np.random.default_rng(int(frac * 100))
+            t0 = time.perf_counter()
+            t_next = t0
+            k = 0
+            while t_next - t0 < seconds:
+                now = time.perf_counter()
+                if now < t_next:
+                    time.sleep(min(t_next - now, 0.002))
+                    continue
+                q, t = pool[k % len(pool)]
+                rid = srv.submit(q, t)
+                with lock:
+                    ids.append((rid, q.n))
+                k += 1
+                t_next += arr.exponential(1.0 / lam)
+            stop.set()
+            th.join()
+            wall = time.perf_counter() - t0
+            L = np.array(lats)
+            levels.append({
+                "load": frac, "lambda_batches_per_s": round(lam, 2), "batches": len(L),
+                "p50_ms": round(float(np.percentile(L, 50)), 3),
+                "p99_ms": round(float(np.percentile(L, 99)), 3),
+                "p999_ms": round(float(np.percentile(L, 99.9)), 3),
+                "batches_per_s": round(len(L) / wall, 2), "queries_per_s": round(nq[0] / wall, 1),
+                "mean_requests_per_device_batch": round(float(np.mean(batch_sizes)), 2),
+            })
+            log("serving", levels[-1])
+        out["levels"] = levels
+    idx.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +189,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-n", type=int, default=1_000_000)
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -210,6 +310,8 @@ def main():
         },
         "kernel_source_sha": sha,
     }
+    if not args.no_serve:
+        line["serving"] = serving_bench(P, W, args.serve_n, args.serve_seconds, args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(col, taus)
     print(json.dumps(line), flush=True)

@@ -128,6 +128,49 @@ int pj_index_info(const pj_index* idx, int64_t* n, int32_t* tau_min, int32_t* ta
 int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, const pj_options* opt,
              pj_pairs* out);
 
+/* ---- Serving: a request loop over a resident index ------------------------------------------
+ *
+ * A server owns worker slots, each with its own HIP stream (default priority) and device
+ * scratch.  Submitted requests (a query set with per-query thresholds, joined against the index
+ * as in pj_query) wait in a FIFO queue; a scheduler thread admits them continuously: whenever a
+ * slot is free it merges queued requests into one device batch (up to max_batch_queries queries)
+ * as long as the batch's estimated device footprint fits in what the in-flight batches leave of
+ * mem_budget_bytes.  Batches on different slots run concurrently on the device.  A request's
+ * result does not depend on what it was batched with.
+ */
+typedef struct pj_server pj_server;
+
+typedef struct {
+    int32_t slots;              /* device batches in flight at once, >= 1 */
+    int32_t max_batch_queries;  /* queries merged into one device batch, >= 1 */
+    int64_t mem_budget_bytes;   /* bound on the summed footprint estimates in flight; 0 = none */
+} pj_server_config;
+
+/* Timestamps (ms on the server's steady clock since pj_server_start) and admission data. */
+typedef struct {
+    double t_submit_ms;         /* pj_server_submit accepted the request */
+    double t_admit_ms;          /* the scheduler placed it in a device batch */
+    double t_done_ms;           /* its pairs were ready in host memory */
+    int64_t footprint_bytes;    /* admission estimate: 16 B per selectable substring + arena */
+    int32_t batch_requests;     /* requests in the same device batch */
+    int32_t slot;               /* slot that ran it */
+} pj_request_info;
+
+/* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0}. */
+int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server** out);
+
+/* Submits a request: Q (host memory, copied) with one threshold per query in the index's
+ * range.  Returns a request id >= 0, or a negative PJ_E* code (PJ_ENOMEM when the request's own
+ * footprint exceeds the budget).  Never blocks on device work. */
+int64_t pj_server_submit(pj_server* srv, const pj_strings* Q, const int32_t* taus);
+
+/* Blocks until the request is done; its (q, s) pairs (sorted, q local to the request) go to
+ * *out (host memory) and its timing to *info (may be NULL).  Each id can be waited once. */
+int pj_server_wait(pj_server* srv, int64_t request, pj_pairs* out, pj_request_info* info);
+
+/* Stops admitting, finishes the work in flight and queued, then frees the server. */
+int pj_server_stop(pj_server* srv);
+
 /* Releases pairs (host or device memory as recorded in on_device) and zeroes the struct. */
 void pj_pairs_free(pj_pairs* pairs);
 

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "PassJoinError", "load", "pj_self_join", "pj_join", "pj_build_index", "pj_query",
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
-    "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX",
+    "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX", "Server", "Index",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -64,6 +64,17 @@ class PjStats(C.Structure):
                [("verify_launches", C.c_int64)]
 
 
+class PjServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_batch_queries", C.c_int32),
+                ("mem_budget_bytes", C.c_int64)]
+
+
+class PjRequestInfo(C.Structure):
+    _fields_ = [("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
+                ("t_done_ms", C.c_double), ("footprint_bytes", C.c_int64),
+                ("batch_requests", C.c_int32), ("slot", C.c_int32)]
+
+
 _lib = None
 
 
@@ -97,6 +108,15 @@ def load():
         lib.pj_last_stats.restype = C.c_int
         lib.pj_version.argtypes = []
         lib.pj_version.restype = C.c_char_p
+        lib.pj_server_start.argtypes = [C.c_void_p, C.POINTER(PjServerConfig),
+                                        C.POINTER(C.c_void_p)]
+        lib.pj_server_start.restype = C.c_int
+        lib.pj_server_submit.argtypes = [C.c_void_p, sp, C.c_void_p]
+        lib.pj_server_submit.restype = C.c_int64
+        lib.pj_server_wait.argtypes = [C.c_void_p, C.c_int64, pp, C.POINTER(PjRequestInfo)]
+        lib.pj_server_wait.restype = C.c_int
+        lib.pj_server_stop.argtypes = [C.c_void_p]
+        lib.pj_server_stop.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -301,3 +321,46 @@ def pj_query(index: Index, queries, taus, *, outputs_on_device: bool = False,
     _check(lib.pj_query(index.handle, C.byref(q.s), t.ctypes.data if t.size else None,
                         C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
+
+
+class Server:
+    """Serving loop over a resident index (pj_server_*): submit() returns a request id at once;
+    wait(id) returns the request's (q, s) pairs and its timing info."""
+
+    def __init__(self, index: Index, slots: int = 2, max_batch_queries: int = 256,
+                 mem_budget: int = 0):
+        self.index = index          # keeps the index alive while the server runs
+        cfg = PjServerConfig(slots, max_batch_queries, int(mem_budget))
+        h = C.c_void_p()
+        _check(load().pj_server_start(index.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h
+
+    def submit(self, queries, taus) -> int:
+        q = _Marshalled(queries)
+        if q.on_device:
+            raise PassJoinError(PJ_EINVAL, "server requests are host memory")
+        t = np.ascontiguousarray(taus, dtype=np.int32)
+        if t.size != q.s.n:
+            raise PassJoinError(PJ_EINVAL, "one tau per query is required")
+        rid = load().pj_server_submit(self.handle, C.byref(q.s), t.ctypes.data if t.size else None)
+        if rid < 0:
+            raise PassJoinError(int(rid), pj_last_error())
+        return int(rid)
+
+    def wait(self, rid: int):
+        raw = PjPairs()
+        info = PjRequestInfo()
+        _check(load().pj_server_wait(self.handle, int(rid), C.byref(raw), C.byref(info)))
+        pairs = _take_pairs(raw, False)
+        return pairs, {k: getattr(info, k) for k, _ in PjRequestInfo._fields_}
+
+    def stop(self):
+        if self.handle:
+            _check(load().pj_server_stop(self.handle))
+            self.handle = C.c_void_p(None)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "pj_internal.h"
 #include "pj_device_common.h"
 
@@ -373,10 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_segments(const uint8_t* __restr
     int l = slen[g];
     Seg sg = partition_seg(l, i, tau, div);
     const uint8_t* s = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
-    uint64_t h = seg_hash(s + sg.p - 1, sg.len);
+    uint64_t h = seg_code(s + sg.p - 1, sg.len);
     int64_t nl = lenstart[l + 1] - lenstart[l];
     int64_t e = ebase[l] + (int64_t)(i - 1) * nl + (g - lenstart[l]);
-    keys[e] = make_key(l, i, tau, h);
+    keys[e] = make_key(l, i, tau, sg.len, h);
     vals[e] = (uint32_t)g;
 }
 
@@ -442,10 +444,13 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
     const int T1 = P.tau + 1;
     bool valid = t < P.threads;
     uint64_t my_sel = 0;
-    int n = 0, l = 0, i = 0, lo = 1, hi = 0;
+    int n = 0, l = 0, i = 0, lo = 1, hi = 0, tau = P.tau;
     uint32_t gx = 0;
     Seg sg{1, 0};
     const uint8_t* x = nullptr;
+    const uint4* table = P.table;
+    const uint32_t* vals = P.vals;
+    uint64_t mask = P.mask;
     if (valid) {
         uint64_t per = (uint64_t)P.nl * T1;
         gx = P.g_begin + (uint32_t)(t / per);
@@ -453,18 +458,29 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         i = (int)(rem % T1) + 1;
         int dl = (int)(rem / T1);
         n = P.x_slen[gx];
-        l = P.self ? n - dl : n - P.tau + dl;
+        Div dv = div;
+        if (P.q_tau) {                       // mixed-tau batch: this probe string's own tau
+            tau = P.q_tau[gx];
+            const IndexRef ref = P.refs[tau];
+            table = ref.table;
+            vals = ref.vals;
+            mask = ref.mask;
+            dv.d = (uint32_t)(tau + 1);
+            dv.m = ref.div_m;
+        }
+        l = P.self ? n - dl : n - tau + dl;
+        const bool in_window = i <= tau + 1 && dl <= (P.self ? tau : 2 * tau) && l >= tau + 1;
         // substrings selected for L_l^1 .. L_l^{tau+1}: the Lemma 2 count, whether or not
         // strings of length l exist (Algorithm 1 selects for every l in the length window)
-        if (l >= T1 && i == 1) {
+        if (in_window && i == 1) {
             const int d = n - l;
-            my_sel = (uint64_t)((P.tau * P.tau - d * d) / 2 + P.tau + 1);
+            my_sel = (uint64_t)((tau * tau - d * d) / 2 + tau + 1);
         }
-        valid = (l >= T1) && (l >= P.ymin) && (l <= P.ymax) &&
+        valid = in_window && (l >= P.ymin) && (l <= P.ymax) &&
                 (P.y_lenstart[l + 1] > P.y_lenstart[l]);
         if (valid) {
-            sg = partition_seg(l, i, P.tau, div);
-            multimatch_window(n, l, P.tau, i, sg, &lo, &hi);
+            sg = partition_seg(l, i, tau, dv);
+            multimatch_window(n, l, tau, i, sg, &lo, &hi);
             x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
         }
     }
@@ -478,16 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         uint32_t start = 0, count = 0;
         if (active) {
             const uint8_t* w = x + p - 1;
-            if (s == 0) h = seg_hash(w, sg.len);
-            else h = roll_hash(h, w[-1], w[sg.len - 1], top);
-            uint64_t key = make_key(l, i, P.tau, h);
-            if (table_lookup(P.table, P.mask, key, &start, &count)) {
+            if (s == 0) h = seg_code(w, sg.len);
+            else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top);
+            uint64_t key = make_key(l, i, tau, sg.len, h);
+            if (table_lookup(table, mask, key, &start, &count)) {
                 if (P.self && l == n) {
                     // keep members with g < gx (lists are ascending in g)
                     uint32_t a = 0, b = count;
                     while (a < b) {
                         uint32_t m = (a + b) >> 1;
-                        if (P.vals[start + m] < gx) a = m + 1; else b = m;
+                        if (vals[start + m] < gx) a = m + 1; else b = m;
                     }
                     count = a;
                 }
@@ -535,7 +551,6 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
     __shared__ unsigned long long sP[kVerifyChunk + 1];
     __shared__ uint64_t s_h0;
     const int lane = threadIdx.x & 63;
-    const int tau = V.tau;
     uint64_t my_cells = 0, my_miss = 0;
     const uint64_t nchunks = (V.ncand + kVerifyChunk - 1) / kVerifyChunk;
     for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
@@ -566,7 +581,16 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
                 const Hit hit = V.hits[h0 + a];
                 const uint64_t mem = c - sP[a];
                 gx = hit.gx;
-                gy = V.vals[hit.start + mem];
+                int tau = V.tau;
+                const uint32_t* vals = V.vals;
+                Div dv = div;
+                if (V.q_tau) {
+                    tau = V.q_tau[gx];
+                    vals = V.refs[tau].vals;
+                    dv.d = (uint32_t)(tau + 1);
+                    dv.m = V.refs[tau].div_m;
+                }
+                gy = vals[hit.start + mem];
                 const int p = (int)(hit.meta & 2047u) + 1;
                 const int i = (int)((hit.meta >> 11) & 63u) + 1;
                 const int l = (int)(hit.meta >> 17);
@@ -575,9 +599,10 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
                                    (int64_t)(gx - V.x_lenstart[n]) * stride_of(n);
                 const uint8_t* y = V.y_arena + V.y_gbase[l] +
                                    (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
-                const Seg sg = partition_seg(l, i, tau, div);
+                const Seg sg = partition_seg(l, i, tau, dv);
                 bool same = true;
-                for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
+                if (sg.len > kExactLen)
+                    for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
                 if (!same) {
                     my_miss += 1;
                 } else {
@@ -617,6 +642,216 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
 }
 
 // ------------------------------------------------------------------------------------------
+// Batched verification.  Hits are bucketed by slot i, so the candidates of a wave almost always
+// share (tau_l, tau_r) = (i - 1, tau + 1 - i) and run band DPs of exactly that width.  Each wave
+// walks its own chunks of 64 x kWaveRounds consecutive candidates; the hit of each lane is found
+// from the hits' end offsets with one OR-reduced boundary mask per 64 candidates.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kWaveRounds = 16;
+constexpr uint64_t kWaveChunk = 64ull * kWaveRounds;
+
+// counts[i - 1] = hits of slot i
+__global__ __launch_bounds__(kBlock) void k_slot_hist(const Hit* __restrict__ hits,
+                                                      const unsigned long long* __restrict__ nh_dev,
+                                                      uint32_t* __restrict__ counts)
+{
+    __shared__ uint32_t h[64];
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t nh = *nh_dev;
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < nh;
+         k += (uint64_t)gridDim.x * kBlock)
+        atomicAdd(&h[(hits[k].meta >> 11) & 63u], 1u);
+    __syncthreads();
+    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+// Moves every hit into its slot's region (regions in slot order; order inside a region is
+// arbitrary, which changes nothing downstream: the result is sorted).  cursor[64] starts at 0.
+__global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__ hits,
+                                                         const unsigned long long* __restrict__ nh_dev,
+                                                         const uint32_t* __restrict__ counts,
+                                                         uint32_t* __restrict__ cursor,
+                                                         Hit* __restrict__ out)
+{
+    __shared__ uint32_t base[64];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < 64; ++k) {
+            base[k] = run;
+            run += counts[k];
+        }
+    }
+    __syncthreads();
+    __shared__ uint32_t cnt[64], res[64];
+    const uint64_t nh = *nh_dev;
+    for (uint64_t k0 = (uint64_t)blockIdx.x * kBlock; k0 < nh; k0 += (uint64_t)gridDim.x * kBlock) {
+        // one global reservation per (block, slot) per round; local ranks from LDS atomics
+        if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t k = k0 + threadIdx.x;
+        Hit v{};
+        uint32_t sl = 0, rank = 0;
+        if (k < nh) {
+            v = hits[k];
+            sl = (v.meta >> 11) & 63u;
+            rank = atomicAdd(&cnt[sl], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64 && cnt[threadIdx.x])
+            res[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        __syncthreads();
+        if (k < nh) out[base[sl] + res[sl] + rank] = v;
+        __syncthreads();
+    }
+}
+
+// first[ch] = the hit containing candidate ch * kWaveChunk (largest h with prefix[h] <= it)
+__global__ __launch_bounds__(kBlock) void k_chunk_starts(const unsigned long long* __restrict__ prefix,
+                                                         uint64_t nhits, uint64_t nchunks,
+                                                         uint32_t* __restrict__ first)
+{
+    const uint64_t ch = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (ch >= nchunks) return;
+    const unsigned long long c0 = ch * kWaveChunk;
+    uint64_t a = 0, b = nhits - 1;
+    while (a < b) {
+        const uint64_t m = (a + b + 1) >> 1;
+        if (prefix[m] <= c0) a = m; else b = m - 1;
+    }
+    first[ch] = (uint32_t)a;
+}
+
+__device__ inline uint64_t wave_or64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+    return v;
+}
+
+// VerifyStringPair with the band width fixed at compile time when the threshold is the same on
+// every active lane of the wave (t <= 8), else the generic width class GMAXW.
+template <int GMAXW>
+__device__ inline int vsp_dispatch(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
+                                   int* cells)
+{
+    const int t0 = __builtin_amdgcn_readfirstlane(t);
+    if (t0 <= 8 && __ballot(t != t0) == 0) {
+        switch (t0) {
+        case 0: return vsp_fast<1>(r, lr, s, ls, t, cells);
+        case 1: return vsp_fast<2>(r, lr, s, ls, t, cells);
+        case 2: return vsp_fast<3>(r, lr, s, ls, t, cells);
+        case 3: return vsp_fast<4>(r, lr, s, ls, t, cells);
+        case 4: return vsp_fast<5>(r, lr, s, ls, t, cells);
+        case 5: return vsp_fast<6>(r, lr, s, ls, t, cells);
+        case 6: return vsp_fast<7>(r, lr, s, ls, t, cells);
+        case 7: return vsp_fast<8>(r, lr, s, ls, t, cells);
+        default: return vsp_fast<9>(r, lr, s, ls, t, cells);
+        }
+    }
+    return vsp_fast<GMAXW>(r, lr, s, ls, t, cells);
+}
+
+template <int GMAXW>
+__global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div div,
+                                                           const uint32_t* __restrict__ first,
+                                                           uint64_t nchunks)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    uint64_t my_cells = 0, my_miss = 0;
+    const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
+        const uint64_t c0 = ch * kWaveChunk;
+        const uint64_t cend = (c0 + kWaveChunk < V.ncand) ? c0 + kWaveChunk : V.ncand;
+        uint64_t h = first[ch];
+        unsigned long long hstart = V.prefix[h];
+        for (uint64_t g0 = c0; g0 < cend; g0 += 64) {
+            // end offsets of hits h .. h + 63; a boundary at relative position r means the
+            // candidates from r on belong to later hits
+            const uint64_t hk = h + (uint64_t)lane;
+            const unsigned long long bk = (hk < V.nhits) ? V.prefix[hk + 1] : ~0ull;
+            const uint64_t rel = bk - g0;                      // >= 1
+            const uint64_t M = wave_or64(rel < 64 ? (1ull << rel) : 0ull);
+            const int off = __popcll(M & le_mask);
+            const unsigned long long bprev = __shfl(bk, off > 0 ? off - 1 : 0, 64);
+            const unsigned long long hs = (off == 0) ? hstart : bprev;
+            const uint64_t c = g0 + (uint64_t)lane;
+            bool pass = false;
+            uint32_t gx = 0, gy = 0;
+            if (c < cend) {
+                const Hit hit = V.hits[h + (uint64_t)off];
+                const uint64_t mem = c - hs;
+                gx = hit.gx;
+                int tau = V.tau;
+                const uint32_t* vals = V.vals;
+                Div dv = div;
+                if (V.q_tau) {
+                    tau = V.q_tau[gx];
+                    vals = V.refs[tau].vals;
+                    dv.d = (uint32_t)(tau + 1);
+                    dv.m = V.refs[tau].div_m;
+                }
+                gy = vals[hit.start + mem];
+                const int p = (int)(hit.meta & 2047u) + 1;
+                const int i = (int)((hit.meta >> 11) & 63u) + 1;
+                const int l = (int)(hit.meta >> 17);
+                const int n = V.x_slen[gx];
+                const uint8_t* x = V.x_arena + V.x_gbase[n] +
+                                   (int64_t)(gx - V.x_lenstart[n]) * stride_of(n);
+                const uint8_t* y = V.y_arena + V.y_gbase[l] +
+                                   (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
+                const Seg sg = partition_seg(l, i, tau, dv);
+                bool same = true;
+                if (sg.len > kExactLen)
+                    for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
+                if (!same) {
+                    my_miss += 1;
+                } else {
+                    int cl = 0;
+                    const int tl = i - 1, tr = tau + 1 - i;
+                    const int dl = vsp_dispatch<GMAXW>(y, sg.p - 1, x, p - 1, tl, &cl);
+                    my_cells += cl;
+                    if (dl <= tl) {
+                        int cr = 0;
+                        const int ry = sg.p - 1 + sg.len, rx = p - 1 + sg.len;
+                        const int dr = vsp_dispatch<GMAXW>(y + ry, l - ry, x + rx, n - rx, tr, &cr);
+                        my_cells += cr;
+                        pass = dr <= tr;
+                    }
+                }
+            }
+            const uint64_t pm = __ballot(pass);
+            if (pm) {
+                const int leader = __ffsll((unsigned long long)pm) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&V.counters[3], (unsigned long long)__popcll(pm));
+                base = __shfl(base, leader, 64);
+                if (pass) {
+                    const uint64_t idx = base + (uint64_t)__popcll(pm & lanemask_lt());
+                    if (idx < V.out_cap) V.out[idx] = ((uint64_t)gx << 32) | gy;
+                }
+            }
+            // the hit containing candidate g0 + 64 starts the next group
+            const uint64_t nb = __ballot(rel <= 64);
+            const int adv = __popcll(nb);
+            if (adv > 0) {
+                hstart = __shfl(bk, adv - 1, 64);
+                h += (uint64_t)adv;
+            }
+        }
+    }
+    my_cells = wave_sum(my_cells);
+    my_miss = wave_sum(my_miss);
+    if (lane == 0) {
+        if (my_cells) atomicAdd(&V.counters[4], (unsigned long long)my_cells);
+        if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Short strings (length <= tau): not partitionable (footnote to Sec. 3.1).  One block per short
 // string y of the indexed set; its partners are the probe-set strings in the length window
 // [|y| - tau, |y| + tau] -- a contiguous range of sorted positions.  In a self-join a pair of
@@ -634,7 +869,8 @@ __global__ __launch_bounds__(kBlock) void k_short(const uint8_t* __restrict__ x_
                                                   const int32_t* __restrict__ y_lenstart,
                                                   const int64_t* __restrict__ y_gbase,
                                                   uint32_t y_first, uint32_t y_count, int tau,
-                                                  int self, uint64_t* __restrict__ out,
+                                                  int self, const int32_t* __restrict__ q_tau,
+                                                  uint64_t* __restrict__ out,
                                                   uint64_t out_cap,
                                                   unsigned long long* __restrict__ counters)
 {
@@ -654,12 +890,14 @@ __global__ __launch_bounds__(kBlock) void k_short(const uint8_t* __restrict__ x_
             bool pass = false;
             if (gx < g1) {
                 const int lx = x_slen[gx];
-                bool take = !(self && lx <= tau && gx >= gy);
+                const int tx = q_tau ? q_tau[gx] : tau;      // the pair's threshold
+                const int dlen = lx > ly ? lx - ly : ly - lx;
+                bool take = ly <= tx && dlen <= tx && !(self && lx <= tau && gx >= gy);
                 if (take) {
                     const uint8_t* x = x_arena + x_gbase[lx] +
                                        (int64_t)(gx - x_lenstart[lx]) * stride_of(lx);
                     int c = 0;
-                    pass = vsp_global<MAXW>(y, ly, x, lx, tau, &c) <= tau;
+                    pass = vsp_global<MAXW>(y, ly, x, lx, tx, &c) <= tx;
                     examined += 1;
                 }
             }
@@ -720,6 +958,15 @@ __global__ __launch_bounds__(kBlock) void k_compact_pairs(const uint64_t* __rest
         a[pos[k]] = (int32_t)(v >> bbits);
         b[pos[k]] = (int32_t)(v & ((1ull << bbits) - 1));
     }
+}
+
+// out[g] = in[perm[g]]: per-id values (a query's tau) moved to sorted positions.
+__global__ __launch_bounds__(kBlock) void k_gather_i32(const int32_t* __restrict__ in,
+                                                       const int32_t* __restrict__ perm, int64_t n,
+                                                       int32_t* __restrict__ out)
+{
+    int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g < n) out[g] = in[perm[g]];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -828,6 +1075,41 @@ static void verify_w(const VerifyParams& V, int grid, hipStream_t s)
     hipLaunchKernelGGL((k_verify<W>), dim3(grid), dim3(kBlock), 0, s, V, make_div(V.tau + 1));
 }
 
+template <int W>
+static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint64_t nchunks,
+                             int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_verify_batched<W>), dim3(grid), dim3(kBlock), 0, s, V,
+                       make_div(V.tau + 1), first, nchunks);
+}
+
+uint64_t batched_chunks(uint64_t ncand) { return (ncand + kWaveChunk - 1) / kWaveChunk; }
+
+hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
+                              uint32_t* counts, uint32_t* cursor, Hit* out, hipStream_t s)
+{
+    if (nh_cap == 0) return hipSuccess;
+    unsigned grid = (unsigned)std::min<uint64_t>((nh_cap + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, counts);
+    hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, counts,
+                       cursor, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s)
+{
+    if (V.ncand == 0) return hipSuccess;
+    const uint64_t nchunks = batched_chunks(V.ncand);
+    hipLaunchKernelGGL(k_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, V.prefix,
+                       V.nhits, nchunks, first);
+    const int w = V.tau + 1;
+    if (w <= 9) verify_batched_w<9>(V, first, nchunks, grid, s);
+    else if (w <= 17) verify_batched_w<17>(V, first, nchunks, grid, s);
+    else if (w <= 33) verify_batched_w<33>(V, first, nchunks, grid, s);
+    else verify_batched_w<64>(V, first, nchunks, grid, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s)
 {
     if (V.ncand == 0) return hipSuccess;
@@ -843,18 +1125,19 @@ hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s)
 }
 
 template <int W>
-static void short_w(const DevSet& P, const DevSet& Y, int tau, int self, uint32_t y_first,
-                    uint32_t y_count, uint64_t* out, uint64_t cap, unsigned long long* ctr,
-                    hipStream_t s)
+static void short_w(const DevSet& P, const DevSet& Y, int tau, int self, const int32_t* q_tau,
+                    uint32_t y_first, uint32_t y_count, uint64_t* out, uint64_t cap,
+                    unsigned long long* ctr, hipStream_t s)
 {
     unsigned grid = y_count < 65536 ? y_count : 65536;
     hipLaunchKernelGGL((k_short<W>), dim3(grid), dim3(kBlock), 0, s, P.sarena, P.slen, P.lenstart,
                        P.gbase, P.lmax, Y.sarena, Y.slen, Y.lenstart, Y.gbase, y_first, y_count,
-                       tau, self, out, cap, ctr);
+                       tau, self, q_tau, out, cap, ctr);
 }
 
-hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self, uint64_t* out,
-                             uint64_t out_cap, unsigned long long* counters, hipStream_t s)
+hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self,
+                             const int32_t* q_tau, uint64_t* out, uint64_t out_cap,
+                             unsigned long long* counters, hipStream_t s)
 {
     if (Y.n == 0 || P.n == 0 || Y.lmin > tau) return hipSuccess;
     const int top = tau < Y.lmax ? tau : Y.lmax;
@@ -863,12 +1146,12 @@ hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self
     if (y_end <= y_first) return hipSuccess;
     uint32_t cnt = y_end - y_first;
     const int w = tau + 1;
-    if (w <= 2) short_w<2>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
-    else if (w <= 5) short_w<5>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
-    else if (w <= 9) short_w<9>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
-    else if (w <= 17) short_w<17>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
-    else if (w <= 33) short_w<33>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
-    else short_w<64>(P, Y, tau, self, y_first, cnt, out, out_cap, counters, s);
+    if (w <= 2) short_w<2>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 5) short_w<5>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 9) short_w<9>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 17) short_w<17>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    else if (w <= 33) short_w<33>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    else short_w<64>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
     return hipGetLastError();
 }
 
@@ -895,6 +1178,14 @@ hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, con
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_compact_pairs, dim3(blocks_for(m)), dim3(kBlock), 0, s, keys, flags, pos,
                        m, bbits, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_i32, dim3(blocks_for(n)), dim3(kBlock), 0, s, in, perm, n, out);
     return hipGetLastError();
 }
 

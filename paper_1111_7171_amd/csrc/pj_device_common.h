@@ -101,10 +101,33 @@ __host__ __device__ inline uint64_t mix64(uint64_t x)
     return x;
 }
 
-__device__ inline uint64_t make_key(int l, int i, int tau, uint64_t h)
+// Segment code: the raw bytes (big-endian) when len <= kExactLen, else the polynomial hash.
+// Both roll across consecutive start positions.
+__device__ inline uint64_t seg_code(const uint8_t* w, int len)
+{
+    uint64_t h = 0;
+    if (len <= kExactLen) {
+        for (int k = 0; k < len; ++k) h = (h << 8) | (uint64_t)w[k];
+    } else {
+        for (int k = 0; k < len; ++k) h = h * kHashBase + (uint64_t)w[k] + 1ull;
+    }
+    return h;
+}
+
+__device__ inline uint64_t roll_code(uint64_t h, int len, uint8_t out, uint8_t in, uint64_t top)
+{
+    if (len <= kExactLen) {
+        const uint64_t mask = (len >= 8) ? ~0ull : ((1ull << (8 * len)) - 1ull);
+        return ((h << 8) | (uint64_t)in) & mask;
+    }
+    return roll_hash(h, out, in, top);
+}
+
+__device__ inline uint64_t make_key(int l, int i, int tau, int len, uint64_t code)
 {
     const uint64_t grp = (uint64_t)(l - (tau + 1)) * (uint64_t)(tau + 1) + (uint64_t)(i - 1);
-    return (grp << kHashBits) | (mix64(h) >> (64 - kHashBits));
+    const uint64_t c = (len <= kExactLen) ? code : (mix64(code) >> (64 - kHashBits));
+    return (grp << kHashBits) | c;
 }
 
 __device__ inline uint64_t table_slot(uint64_t key) { return mix64(key ^ 0x5851F42D4C957F2Dull); }
@@ -198,6 +221,94 @@ __device__ inline int vsp_global(const uint8_t* r, int lr, const uint8_t* s, int
     for (int k = 0; k < MAXW; ++k)
         if (k == delta + a) res = R[k];
     return res;
+}
+
+// Branch-free VerifyStringPair for the batched path: the same arithmetic, orientation, band,
+// saturation, early stop and cell count as vsp_global, written so that a row issues no branch
+// and no dependent load: the band's column characters B[j-1] (j = i - a + k) sit in a register
+// window w[k] that shifts by one per row, the character entering the window and the next row
+// character are loaded one row ahead, out-of-band or out-of-matrix cells are masked with
+// selects, and the row's recurrence-cell count is computed from the band bounds.
+// Characters outside the string read as 256, which equals no byte.
+template <int MAXW>
+__device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
+                               int* cells)
+{
+    const uint8_t* A;
+    const uint8_t* B;
+    int nr, nc;
+    if (lr <= ls) { A = r; nr = lr; B = s; nc = ls; }
+    else          { A = s; nr = ls; B = r; nc = lr; }
+    const int delta = nc - nr;
+    *cells = 0;
+    if (delta > t) return t + 1;
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    const int W = a + b + 1;
+    const int INF = t + 1;
+    constexpr int BIG = 1 << 20;
+    int R[MAXW], w[MAXW], ek[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int j = k - a;
+        R[k] = (k < W && j >= 0 && j <= nc) ? (j < INF ? j : INF) : INF;
+        const int idx = k - a;                       // B index of column j = 1 - a + k, row 1
+        w[k] = ((unsigned)idx < (unsigned)nc) ? (int)B[idx] : 256;
+        const int dd = delta + a - k;
+        ek[k] = dd < 0 ? -dd : dd;
+    }
+    // character entering the window at row 2, and the row characters of rows 1 and 2
+    int idx_in = MAXW - a;                           // B index of column j = 2 - a + MAXW - 1
+    int cin = ((unsigned)idx_in < (unsigned)nc) ? (int)B[idx_in] : 256;
+    int ai = nr > 0 ? (int)A[0] : 256;
+    int ai_next = nr > 1 ? (int)A[1] : 256;
+    int ncell = 0;
+    int res = -1;
+    for (int i = 1; i <= nr; ++i) {
+        // loads for the next row first, so their latency overlaps this row's arithmetic
+        const int idx2 = idx_in + 1;
+        const int cin_next = ((unsigned)idx2 < (unsigned)nc) ? (int)B[idx2] : 256;
+        const int ai_next2 = (i + 1 < nr) ? (int)A[i + 1] : 256;
+        const int j0 = i - a;
+        int left = INF;
+        int emin = BIG;
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) {
+            const int j = j0 + k;
+            const bool valid = (k < W) && j >= 0 && j <= nc;
+            const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
+            const int upk = (k + 1 < W) ? up : INF;
+            const int d = (ai != w[k]) ? 1 : 0;
+            int v = min(min(upk, left) + 1, R[k] + d);
+            v = min(v, INF);
+            v = (j == 0) ? min(i, INF) : v;
+            v = valid ? v : INF;
+            emin = min(emin, valid ? v + ek[k] : BIG);
+            R[k] = v;
+            left = v;
+        }
+        // recurrence cells of this row: j in [max(1, i - a), min(nc, i - a + W - 1)]
+        const int lo = max(1, j0), hi = min(nc, j0 + W - 1);
+        ncell += max(0, hi - lo + 1);
+        if (emin > t) {
+            res = t + 1;
+            break;
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
+        w[MAXW - 1] = cin;
+        cin = cin_next;
+        idx_in = idx2;
+        ai = ai_next;
+        ai_next = ai_next2;
+    }
+    *cells = ncell;
+    if (res >= 0) return res;
+    int out = INF;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k)
+        if (k == delta + a) out = R[k];
+    return out;
 }
 
 }  // namespace pj

@@ -125,6 +125,12 @@ Workspace& thread_workspace()
     return *t_ws;
 }
 
+void release_thread_workspace()
+{
+    delete t_ws;
+    t_ws = nullptr;
+}
+
 int device_cus()
 {
     static int cus = 0;
@@ -392,28 +398,35 @@ static uint64_t selection_bound(const DevSet& P, const DevSet& Y, int tau, bool 
     return total;
 }
 
-void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau, bool self,
-                    JoinScratch& J, pj_stats& stats, Timer& tm, hipStream_t st)
+void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, JoinScratch& J,
+                    pj_stats& stats, Timer& tm, hipStream_t st)
 {
     Workspace& W = thread_workspace();
+    const int tau = spec.tau;
+    const bool self = spec.self;
     const int T1 = tau + 1;
     J.counters = (unsigned long long*)W.get("join.counters", 8 * sizeof(unsigned long long));
     hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
     int64_t probe_first = 0;
-    uint64_t bound = selection_bound(P, Y, tau, self, &probe_first);
+    uint64_t bound = spec.q_tau ? spec.bound : selection_bound(P, Y, tau, self, &probe_first);
     int64_t nprobe = P.n - probe_first;
     J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)std::max<uint64_t>(bound, 1));
+    const bool entries = spec.q_tau ? spec.has_entries : (spec.X && spec.X->entries > 0);
     int t_probe0 = tm.mark();
-    if (nprobe > 0 && bound > 0 && X.entries > 0) {
+    if (nprobe > 0 && bound > 0 && entries) {
         ProbeParams pp{};
         pp.x_arena = P.sarena; pp.x_slen = P.slen; pp.x_lenstart = P.lenstart; pp.x_gbase = P.gbase;
         pp.g_begin = (uint32_t)probe_first;
         pp.nl = self ? T1 : 2 * tau + 1;
         pp.threads = (uint64_t)nprobe * (uint64_t)pp.nl * (uint64_t)T1;
         pp.self = self ? 1 : 0;
-        pp.q_tau = nullptr;
+        pp.q_tau = spec.q_tau;
+        pp.refs = spec.refs;
         pp.y_lenstart = Y.lenstart;
-        pp.keys = X.keys; pp.vals = X.vals; pp.table = X.table; pp.mask = X.mask;
+        if (spec.X) {
+            pp.keys = spec.X->keys; pp.vals = spec.X->vals; pp.table = spec.X->table;
+            pp.mask = spec.X->mask;
+        }
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
         pp.hits = J.hits; pp.hit_cap = bound;
@@ -434,6 +447,17 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
     stats.candidates += (int64_t)c[1];
     if (J.nhits > bound) throw Error(PJ_EDEVICE, "hit buffer overflow (%llu > %llu)",
                                      (unsigned long long)J.nhits, (unsigned long long)bound);
+
+    const bool batched = J.mode != PJ_MODE_PLAIN;
+    if (batched && J.nhits > 0) {
+        // bucket the hits by slot so that waves see one (tau_l, tau_r)
+        uint32_t* sc = (uint32_t*)W.get("join.slotcnt", 128 * sizeof(uint32_t));
+        hip_check(hipMemsetAsync(sc, 0, 128 * sizeof(uint32_t), st), "memset");
+        Hit* sorted = (Hit*)W.get("join.hits2", sizeof(Hit) * (size_t)J.nhits);
+        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, sc, sc + 64, sorted, st),
+                  "slot_bucket");
+        J.hits = sorted;
+    }
 
     // candidate prefix sums
     J.prefix = (unsigned long long*)W.get("join.prefix",
@@ -456,22 +480,35 @@ void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau
             vp.x_arena = P.sarena; vp.x_slen = P.slen; vp.x_lenstart = P.lenstart;
             vp.x_gbase = P.gbase;
             vp.y_arena = Y.sarena; vp.y_lenstart = Y.lenstart; vp.y_gbase = Y.gbase;
-            vp.vals = X.vals;
+            vp.vals = spec.X ? spec.X->vals : nullptr;
+            vp.q_tau = spec.q_tau;
+            vp.refs = spec.refs;
             vp.hits = J.hits; vp.prefix = J.prefix;
             vp.nhits = J.nhits; vp.ncand = J.ncand;
             vp.tau = tau;
             vp.out = J.out; vp.out_cap = cap;
             vp.counters = J.counters;
-            uint64_t nchunks = (J.ncand + 1023) / 1024;
-            int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 16);
-            int k0 = tm.mark();
-            hip_check(launch_verify(vp, grid, st), "verify");
+            int k0 = 0;
+            if (batched) {
+                const uint64_t nchunks = batched_chunks(J.ncand);
+                uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
+                // persistent: enough waves to fill the chip, each walking its chunks
+                const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
+                const int grid = (int)((waves + 3) / 4);
+                k0 = tm.mark();
+                hip_check(launch_verify_batched(vp, first, grid, st), "verify_batched");
+            } else {
+                const uint64_t nchunks = (J.ncand + 1023) / 1024;
+                const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 16);
+                k0 = tm.mark();
+                hip_check(launch_verify(vp, grid, st), "verify");
+            }
             int k1 = tm.mark();
             J.kernel_marks.push_back({k0, k1, 1});
             stats.verify_launches += 1;
         }
-        hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, J.out, cap, J.counters, st),
-                  "short_path");
+        hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, spec.q_tau, J.out, cap, J.counters,
+                                    st), "short_path");
         hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
         hip_check(hipStreamSynchronize(st), "sync");
         if (c[3] <= cap) break;
@@ -622,6 +659,8 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     if (!out) throw Error(PJ_EINVAL, "null output");
     zero_pairs(out);
     check_tau(tau);
+    if (opt && (opt->mode < PJ_MODE_AUTO || opt->mode > PJ_MODE_BATCHED))
+        throw Error(PJ_EINVAL, "unknown mode %d", opt->mode);
     hipStream_t st = stream_of(opt);
     bool on_dev = opt && opt->inputs_on_device;
     if (!on_dev) {
@@ -645,7 +684,12 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     t_stats.strings = P.n + (self ? 0 : Y.n);
     t_stats.index_entries = X.entries;
     JoinScratch J;
-    run_candidates(P, YY, X, tau, self, J, t_stats, tm, st);
+    J.mode = opt ? opt->mode : PJ_MODE_AUTO;
+    ProbeSpec spec;
+    spec.self = self;
+    spec.tau = tau;
+    spec.X = &X;
+    run_candidates(P, YY, spec, J, t_stats, tm, st);
     int e3 = tm.mark();
     int32_t *da = nullptr, *db = nullptr;
     uint64_t M = finish_pairs(P, YY, self, J.out, J.naccepted, &da, &db, st);

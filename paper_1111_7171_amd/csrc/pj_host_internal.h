@@ -63,6 +63,7 @@ struct Timer {
 };
 
 struct JoinScratch {
+    int mode = PJ_MODE_AUTO;
     unsigned long long* counters = nullptr;
     Hit* hits = nullptr;
     unsigned long long* prefix = nullptr;
@@ -78,12 +79,31 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
                hipStream_t st);
 void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
                  hipStream_t st);
-void run_candidates(const DevSet& P, const DevSet& Y, const DevIndex& X, int tau, bool self,
-                    JoinScratch& J, pj_stats& stats, Timer& tm, hipStream_t st);
+// What to probe: a uniform tau against one index, or per-probe thresholds (q_tau, by sorted
+// position of the probe set) against the per-tau indices in refs.
+struct ProbeSpec {
+    bool self = false;
+    int tau = 0;                       // uniform tau, or the largest tau of the batch
+    const DevIndex* X = nullptr;       // uniform index
+    const int32_t* q_tau = nullptr;    // device, per sorted position (mixed batch)
+    const IndexRef* refs = nullptr;    // device, [kTauMax + 1] (mixed batch)
+    uint64_t bound = 0;                // selection bound for a mixed batch (computed by the caller)
+    bool has_entries = true;           // some index has entries
+};
+
+void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, JoinScratch& J,
+                    pj_stats& stats, Timer& tm, hipStream_t st);
 uint64_t finish_pairs(const DevSet& P, const DevSet& Y, bool self, const uint64_t* acc,
                       uint64_t m, int32_t** a_out, int32_t** b_out, hipStream_t st);
 void emit_output(const int32_t* da, const int32_t* db, uint64_t M, bool to_device, pj_pairs* out,
                  hipStream_t st);
+
+void validate_host_strings(const pj_strings* S, const char* what);
+void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* taus,
+                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st);
+int64_t query_footprint(const pj_index* idx, int n, int tau);
+void index_taus(const pj_index* idx, int* lo, int* hi);
+void release_thread_workspace();
 
 extern thread_local std::string t_last_error;
 extern thread_local pj_stats t_stats;

@@ -23,6 +23,8 @@ struct pj_index {
     pj::Owned mem;
     pj::DevSet S;
     std::vector<pj::DevIndex> X;
+    pj::IndexRef* refs = nullptr;    // device [kTauMax + 1], entries for tau_min .. tau_max
+    bool has_entries = false;
 };
 
 namespace pj {
@@ -65,24 +67,41 @@ static void to_host(const pj_strings* Q, bool on_device, HostStrings& H)
     H.view.offsets = H.offs.data();
 }
 
-// Runs the queries `ids` (all with threshold tau) against the index; appends (q, s) pairs.
-void query_group(const pj_index* idx, const pj_strings* Q, const std::vector<int32_t>& ids,
-                 int tau, std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st)
+int64_t query_selections(const pj_index* idx, int n, int tau);
+
+// Joins the queries of Q (host memory, validated; taus[q] in the index's range) against the
+// index in one device pass: probe, verify and the short-string path take each query's own
+// threshold and per-tau index.  Appends (q << 32 | s) sorted by (q, s).
+void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* taus,
+                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st)
 {
-    std::vector<uint8_t> bytes;
-    std::vector<int32_t> offs(1, 0);
-    for (int32_t q : ids) {
-        int32_t a = Q->offsets[q], b = Q->offsets[q + 1];
-        bytes.insert(bytes.end(), Q->bytes + a, Q->bytes + b);
-        offs.push_back((int32_t)bytes.size());
-    }
-    pj_strings sub{(int64_t)ids.size(), bytes.empty() ? nullptr : bytes.data(), offs.data()};
+    if (Q->n == 0) return;
     Workspace& W = thread_workspace();
+    W.begin_call(0);
     DevSet P;
-    build_set(&sub, false, W, "Q", P, st);
+    build_set(Q, false, W, "Q", P, st);
+    int tmax = 0;
+    uint64_t bound = 0;
+    for (int64_t q = 0; q < Q->n; ++q) {
+        tmax = std::max(tmax, taus[q]);
+        bound += (uint64_t)query_selections(idx, Q->offsets[q + 1] - Q->offsets[q], taus[q]);
+    }
+    int32_t* d_tau_id = (int32_t*)W.get("Q.tau_id", sizeof(int32_t) * (size_t)Q->n);
+    int32_t* d_tau = (int32_t*)W.get("Q.tau", sizeof(int32_t) * (size_t)Q->n);
+    hip_check(hipMemcpyAsync(d_tau_id, taus, sizeof(int32_t) * (size_t)Q->n, hipMemcpyHostToDevice,
+                             st), "upload taus");
+    hip_check(launch_gather_i32(d_tau_id, P.perm, Q->n, d_tau, st), "gather taus");
+    ProbeSpec spec;
+    spec.self = false;
+    spec.tau = tmax;
+    spec.q_tau = d_tau;
+    spec.refs = idx->refs;
+    spec.bound = bound;
+    spec.has_entries = idx->has_entries;
     JoinScratch J;
+    J.mode = PJ_MODE_BATCHED;
     Timer tm(st);
-    run_candidates(P, idx->S, index_for(idx, tau), tau, false, J, stats, tm, st);
+    run_candidates(P, idx->S, spec, J, stats, tm, st);
     int32_t *da = nullptr, *db = nullptr;
     uint64_t M = finish_pairs(P, idx->S, false, J.out, J.naccepted, &da, &db, st);
     std::vector<int32_t> ha(M), hb(M);
@@ -91,8 +110,30 @@ void query_group(const pj_index* idx, const pj_strings* Q, const std::vector<int
         hip_check(hipMemcpyAsync(hb.data(), db, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "d2h");
     }
     hip_check(hipStreamSynchronize(st), "sync");
+    pairs.reserve(pairs.size() + M);
     for (uint64_t k = 0; k < M; ++k)
-        pairs.push_back(((uint64_t)(uint32_t)ids[(size_t)ha[k]] << 32) | (uint32_t)hb[k]);
+        pairs.push_back(((uint64_t)(uint32_t)ha[k] << 32) | (uint32_t)hb[k]);
+}
+
+// Substrings a length-n query with threshold tau selects against the lengths present in the
+// index (Lemma 2 count per probed length): the bound on its hit records.
+int64_t query_selections(const pj_index* idx, int n, int tau)
+{
+    const DevSet& S = idx->S;
+    int64_t sel = 0;
+    for (int l = std::max(n - tau, tau + 1); l <= n + tau && l <= kLenMax; ++l) {
+        if (S.h_lenstart[l + 1] == S.h_lenstart[l]) continue;
+        const int d = n - l;
+        sel += (tau * tau - d * d) / 2 + tau + 1;
+    }
+    return sel;
+}
+
+// Admission estimate of one query: 16 bytes per hit record it may produce, plus its bytes twice
+// (the uploaded and the length-sorted arena).
+int64_t query_footprint(const pj_index* idx, int n, int tau)
+{
+    return 16 * query_selections(idx, n, tau) + 2 * (int64_t)stride_of(n) + 64;
 }
 
 }  // namespace pj
@@ -123,10 +164,18 @@ int pj_build_index(const pj_strings* S, int32_t tau_min, int32_t tau_max, const 
         build_set(S, on_dev, idx->mem, "I", idx->S, st);
         idx->X.resize((size_t)(tau_max - tau_min + 1));
         int64_t entries = 0;
+        std::vector<IndexRef> refs(kTauMax + 1);
         for (int t = tau_min; t <= tau_max; ++t) {
-            build_index(idx->S, t, idx->mem, "I.t" + std::to_string(t), idx->X[(size_t)(t - tau_min)], st);
-            entries += idx->X[(size_t)(t - tau_min)].entries;
+            DevIndex& X = idx->X[(size_t)(t - tau_min)];
+            build_index(idx->S, t, idx->mem, "I.t" + std::to_string(t), X, st);
+            entries += X.entries;
+            refs[(size_t)t] = IndexRef{X.table, X.vals, X.mask,
+                                       (uint32_t)(((1u << 21) + (uint32_t)t) / (uint32_t)(t + 1)), 1u};
         }
+        idx->has_entries = entries > 0;
+        idx->refs = (IndexRef*)idx->mem.get("I.refs", sizeof(IndexRef) * (kTauMax + 1));
+        hip_check(hipMemcpyAsync(idx->refs, refs.data(), sizeof(IndexRef) * (kTauMax + 1),
+                                 hipMemcpyHostToDevice, st), "upload refs");
         hip_check(hipStreamSynchronize(st), "sync");
         t_stats.strings = idx->S.n;
         t_stats.index_entries = entries;
@@ -187,16 +236,8 @@ int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, cons
         HostStrings H;
         to_host(Q, on_dev, H);
         if (on_dev) validate_host_strings(&H.view, "Q");
-        thread_workspace().begin_call(opt ? opt->mem_budget_bytes : 0);
-        std::vector<std::vector<int32_t>> groups((size_t)(idx->tau_max - idx->tau_min + 1));
-        for (int64_t q = 0; q < Q->n; ++q) groups[(size_t)(taus[q] - idx->tau_min)].push_back((int32_t)q);
         std::vector<uint64_t> pairs;
-        for (size_t g = 0; g < groups.size(); ++g) {
-            if (groups[g].empty()) continue;
-            thread_workspace().begin_call(opt ? opt->mem_budget_bytes : 0);
-            query_group(idx, &H.view, groups[g], idx->tau_min + (int)g, pairs, t_stats, st);
-        }
-        std::sort(pairs.begin(), pairs.end());
+        run_query_batch(idx, &H.view, taus, pairs, t_stats, st);
         uint64_t M = pairs.size();
         std::vector<int32_t> a(M), b(M);
         for (uint64_t k = 0; k < M; ++k) {

@@ -2,12 +2,13 @@
 //
 // Device data layout (all in HBM, built once per string set):
 //   * length-sorted arena: strings reordered by (length, id) and stored back to back, each at a
-//     4-byte aligned slot of stride(l) = round_up(l, 4) bytes, so the byte offset of the string at
+//     16-byte aligned slot of stride(l) = round_up(l, 16) bytes, so the byte offset of the string at
 //     sorted position g of length l is gbase[l] + (g - lenstart[l]) * stride(l) -- computed from
 //     two per-length tables, never gathered per string;
 //   * perm[g] = original id of sorted position g, slen[g] = its length;
-//   * segment index for one tau: (key, g) entries sorted by key, key = group(l, i) << 40 |
-//     hash(segment) >> 24, group(l, i) = (l - (tau+1)) * (tau+1) + (i-1); equal keys form one
+//   * segment index for one tau: (key, g) entries sorted by key, key = group(l, i) << 40 | code,
+//     group(l, i) = (l - (tau+1)) * (tau+1) + (i-1), code = the segment's bytes when it has at
+//     most 5 (exact) or the top 40 bits of a mixed polynomial hash otherwise; equal keys form one
 //     inverted list L_l^i(w) whose members are in ascending g (Sec. 3.2);
 //   * bucket table: open-addressing hash table key -> (start, count) of the list.
 #pragma once
@@ -23,7 +24,10 @@ constexpr int kTauMax = 63;            // PJ_TAU_MAX
 constexpr int kHashBits = 40;          // hash bits kept in an index key
 constexpr uint64_t kEmptyKey = ~0ull;  // keys use at most 57 bits, so this never collides
 
-__host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 3) & ~3); }
+__host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 15) & ~15); }
+
+// Segments of at most kExactLen bytes are keyed by their raw bytes (exact, no byte guard).
+constexpr int kExactLen = 5;
 
 // Length-sorted device arena of one string set.
 struct DevSet {
@@ -51,6 +55,16 @@ struct DevIndex {
     uint64_t mask = 0;
 };
 
+// Per-threshold view of a multi-tau index (serving): the bucket table and list entries of the
+// index built for tau, and the divisor for tau+1.  Indexed by tau.
+struct IndexRef {
+    const uint4* table;
+    const uint32_t* vals;
+    uint64_t mask;
+    uint32_t div_m;     // ceil(2^21 / (tau + 1)), see Div
+    uint32_t present;   // 1 if an index for this tau exists
+};
+
 // One selected substring that found a non-empty list: candidates (vals[start + m], x, i, p).
 struct Hit {
     uint32_t gx;      // sorted position of the probe string in the probe set
@@ -67,11 +81,12 @@ struct ProbeParams {
     uint64_t threads;           // probe positions * nl * (tau+1)
     int nl;                     // lengths probed per string: tau+1 (self) or 2tau+1 (two sets)
     int self;                   // 1: self-join (l in [n-tau, n], y before x when l == n)
-    const int32_t* q_tau;       // per-probe tau (serving) or nullptr (uniform tau)
+    const int32_t* q_tau;       // per-probe tau by sorted position (mixed-tau batch) or nullptr
+    const IndexRef* refs;       // [kTauMax + 1] when q_tau is set
     // index side
     const int32_t* y_lenstart;  // to know which lengths are present
     const uint64_t* keys; const uint32_t* vals; const uint4* table; uint64_t mask;
-    int tau;
+    int tau;                    // uniform tau, or the largest tau of a mixed batch
     int ymin, ymax;             // indexed lengths present
     // output
     Hit* hits; uint64_t hit_cap;
@@ -85,7 +100,9 @@ struct VerifyParams {
     const uint32_t* vals;
     const Hit* hits; const unsigned long long* prefix;   // [nhits + 1] exclusive prefix of counts
     uint64_t nhits; uint64_t ncand;
-    int tau;
+    int tau;                                              // uniform tau or the batch's largest
+    const int32_t* q_tau;                                 // per-probe tau or nullptr
+    const IndexRef* refs;                                 // [kTauMax + 1] when q_tau is set
     uint64_t* out; uint64_t out_cap;                      // accepted (gx << 32 | gy)
     unsigned long long* counters;                         // [3] accepted, [4] cells, [5] guard misses
 };
@@ -110,15 +127,24 @@ hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, ui
 hipError_t launch_probe(const ProbeParams& P, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
+// batched path: bucket hits by slot (counts and cursor: 64 zeroed u32 each), then verify with
+// per-wave chunks (first: batched_chunks(ncand) u32 of scratch)
+hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
+                              uint32_t* counts, uint32_t* cursor, Hit* out, hipStream_t s);
+hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
+uint64_t batched_chunks(uint64_t ncand);
 hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self,
-                             uint64_t* out, uint64_t out_cap, unsigned long long* counters,
-                             hipStream_t s);
+                             const int32_t* q_tau, uint64_t* out, uint64_t out_cap,
+                             unsigned long long* counters, hipStream_t s);
 hipError_t launch_pairs_to_keys(const uint64_t* acc, uint64_t m, const int32_t* xperm,
                                 const int32_t* yperm, int self, int bbits, uint64_t* keys,
                                 hipStream_t s);
 hipError_t launch_unique_flags(const uint64_t* keys, uint64_t m, uint32_t* flags, hipStream_t s);
 hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, const uint32_t* pos,
                                 uint64_t m, int bbits, int32_t* a, int32_t* b, hipStream_t s);
+
+hipError_t launch_gather_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
+                             hipStream_t s);
 
 // Exclusive scans; out has n + 1 entries (out[n] = total).
 hipError_t scan_u32_to_u32(const uint32_t* in, uint32_t* out, uint64_t n, void* tmp,

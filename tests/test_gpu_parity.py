@@ -40,14 +40,18 @@ def test_table1_all_tau(golden):
         _same(P.pj_self_join(col, tau), O.self_join_bf(col, tau, 1), f"tau={tau}")
 
 
+MODES = [P.MODE_PLAIN, P.MODE_BATCHED]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("seed", range(8))
-def test_random_small_self_join(seed):
+def test_random_small_self_join(seed, mode):
     rng = np.random.default_rng(1000 + seed)
     alph = [b"ab", b"abc", b"abcd", b"abcdefgh"][seed % 4]
     col = W.random_small(rng, 400, alphabet=alph, lmin=0, lmax=16, dup_frac=0.4, kmax=3)
     for tau in range(0, 6):
-        _say("random self seed", seed, "tau", tau)
-        got = P.pj_self_join(col, tau)
+        _say("random self seed", seed, "tau", tau, "mode", mode)
+        got = P.pj_self_join(col, tau, mode=mode)
         _same(got, O.self_join_bf(col, tau, 8), f"seed={seed} tau={tau}")
 
 
@@ -74,17 +78,18 @@ def test_cfg1_full_exact_pairs_and_counts():
     assert st["selected"] == pj.selected
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("cfg,n,taus", [
     (2, 20_000, (1, 2, 3, 4)),
     (3, 8_000, (2, 4, 6, 8)),
     (4, 1_500, (8, 16, 32)),
 ])
-def test_scaled_configs_match_oracle(cfg, n, taus):
+def test_scaled_configs_match_oracle(cfg, n, taus, mode):
     col = W.CONFIGS[cfg](n)
     for tau in taus:
-        _say("cfg", cfg, "n", n, "tau", tau)
+        _say("cfg", cfg, "n", n, "tau", tau, "mode", mode)
         pj = O.self_join_pj(col, tau)
-        got = P.pj_self_join(col, tau)
+        got = P.pj_self_join(col, tau, mode=mode)
         st = P.pj_last_stats()
         _same(got, pj.pairs, f"cfg{cfg} tau={tau}")
         assert st["candidates"] == pj.candidates, (st["candidates"], pj.candidates)
@@ -178,3 +183,26 @@ def test_repeatable_runs_identical():
     a = P.pj_self_join(col, 3)
     b = P.pj_self_join(col, 3)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_query_mixed_tau_with_short_strings(seed):
+    """Per-query thresholds in one device pass, including strings shorter than tau+1 on both
+    sides (the direct path takes each query's own tau)."""
+    rng = np.random.default_rng(3000 + seed)
+    S = W.random_small(rng, 300, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.4)
+    Q = W.random_small(rng, 120, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.2)
+    taus = rng.integers(0, 7, size=Q.n).astype(np.int32)
+    idx = P.pj_build_index(S, 0, 6)
+    try:
+        got = P.pj_query(idx, Q, taus)
+    finally:
+        idx.free()
+    exp = []
+    for t in range(0, 7):
+        ids = np.nonzero(taus == t)[0]
+        if len(ids):
+            for a, b in O.join_bf(Q.subset(ids), S, t, 4).tolist():
+                exp.append((int(ids[a]), b))
+    exp = np.array(sorted(exp), dtype=np.int32).reshape(-1, 2)
+    _same(got, exp, f"mixed tau seed={seed}")

@@ -1,0 +1,119 @@
+"""Serving loop: each request's result is the same alone and in the mix (tolerance 0: the
+method is exact), admission by footprint, oversize rejection, draining on stop."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1111_7171_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+    assert torch.cuda.is_available()
+    S = W.cfg5_index(20_000)
+    idx = P.pj_build_index(S, 1, 8)
+    rng = np.random.default_rng(4242)
+    batches = [W.cfg5_batch(rng, S, mean=24) for _ in range(24)]
+    alone = [P.pj_query(idx, q, t) for q, t in batches]
+    yield S, idx, batches, alone
+    idx.free()
+
+
+def test_alone_equals_oracle(served):
+    S, idx, batches, alone = served
+    for (q, t), got in list(zip(batches, alone))[:3]:
+        exp = []
+        for tau in range(1, 9):
+            ids = np.nonzero(t == tau)[0]
+            if len(ids):
+                for a, b in O.join_pj(q.subset(ids), S, tau).pairs.tolist():
+                    exp.append((int(ids[a]), b))
+        exp = np.array(sorted(exp), dtype=np.int32).reshape(-1, 2)
+        assert np.array_equal(got, exp)
+
+
+def test_mix_equals_alone(served):
+    S, idx, batches, alone = served
+    with P.Server(idx, slots=3, max_batch_queries=80) as srv:
+        ids = [srv.submit(q, t) for q, t in batches]       # all at once: they get merged
+        res = [srv.wait(i) for i in ids]
+    merged = 0
+    for (pairs, info), exp in zip(res, alone):
+        assert np.array_equal(pairs, exp)
+        merged += info["batch_requests"] > 1
+        assert info["t_submit_ms"] <= info["t_admit_ms"] <= info["t_done_ms"]
+    _say("requests sharing a device batch:", merged)
+    assert merged > 0
+
+
+def test_concurrent_submitters(served):
+    S, idx, batches, alone = served
+    out = {}
+    with P.Server(idx, slots=2, max_batch_queries=64) as srv:
+        def client(k0):
+            for k in range(k0, len(batches), 3):
+                rid = srv.submit(*batches[k])
+                out[k] = srv.wait(rid)[0]
+        th = [threading.Thread(target=client, args=(k,)) for k in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    for k, exp in enumerate(alone):
+        assert np.array_equal(out[k], exp)
+
+
+def test_tiny_budget_admits_one_at_a_time(served):
+    S, idx, batches, alone = served
+    lib = P.load()
+    # footprints are reported per request; a budget just above the largest single one forces
+    # batches to run (mostly) alone
+    with P.Server(idx, slots=4, max_batch_queries=1000) as srv:
+        probe = srv.submit(*batches[0])
+        fp = srv.wait(probe)[1]["footprint_bytes"]
+    budget = int(fp * 3)
+    with P.Server(idx, slots=4, max_batch_queries=1000, mem_budget=budget) as srv:
+        ok_ids = []
+        for q, t in batches:
+            try:
+                ok_ids.append((srv.submit(q, t), q, t))
+            except P.PassJoinError as e:
+                assert e.code == P.PJ_ENOMEM
+                ok_ids.append((None, q, t))
+        for (rid, q, t), exp in zip(ok_ids, alone):
+            if rid is not None:
+                pairs, info = srv.wait(rid)
+                assert np.array_equal(pairs, exp)
+                assert info["footprint_bytes"] <= budget
+    assert lib is not None
+
+
+def test_oversize_request_rejected(served):
+    S, idx, batches, alone = served
+    with P.Server(idx, slots=1, max_batch_queries=10, mem_budget=1024) as srv:
+        with pytest.raises(P.PassJoinError) as ei:
+            srv.submit(*batches[0])
+        assert ei.value.code == P.PJ_ENOMEM
+        with pytest.raises(P.PassJoinError) as ei:
+            srv.submit(batches[0][0], np.full(batches[0][0].n, 9, np.int32))
+        assert ei.value.code in (P.PJ_ERANGE, P.PJ_ENOMEM)
+
+
+def test_stop_drains_pending(served):
+    S, idx, batches, alone = served
+    srv = P.Server(idx, slots=1, max_batch_queries=8)
+    ids = [srv.submit(q, t) for q, t in batches[:8]]
+    got = [srv.wait(i)[0] for i in ids[:2]]
+    srv.stop()
+    for g, e in zip(got, alone[:2]):
+        assert np.array_equal(g, e)
