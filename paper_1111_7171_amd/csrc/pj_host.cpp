@@ -410,9 +410,16 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     int64_t probe_first = 0;
     uint64_t bound = spec.q_tau ? spec.bound : selection_bound(P, Y, tau, self, &probe_first);
     int64_t nprobe = P.n - probe_first;
-    J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)std::max<uint64_t>(bound, 1));
+    // hit records: the Lemma 2 bound can be far above the real count (long segments rarely
+    // match), so start from a capped buffer and re-run the probe with the exact size if needed
+    uint64_t hit_cap = std::min<uint64_t>(std::max<uint64_t>(bound, 1), 1ull << 26);
     const bool entries = spec.q_tau ? spec.has_entries : (spec.X && spec.X->entries > 0);
     int t_probe0 = tm.mark();
+    unsigned long long c[8];
+    for (int attempt = 0; attempt < 2; ++attempt) {
+    J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)hit_cap);
+    if (attempt > 0)
+        hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
     if (nprobe > 0 && bound > 0 && entries) {
         ProbeParams pp{};
         pp.x_arena = P.sarena; pp.x_slen = P.slen; pp.x_lenstart = P.lenstart; pp.x_gbase = P.gbase;
@@ -429,24 +436,27 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         }
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
-        pp.hits = J.hits; pp.hit_cap = bound;
+        pp.hits = J.hits; pp.hit_cap = hit_cap;
         pp.counters = J.counters;
         int k0 = tm.mark();
         hip_check(launch_probe(pp, st), "probe");
         int k1 = tm.mark();
         J.kernel_marks.push_back({k0, k1, 0});
     }
-    unsigned long long c[8];
     hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
     hip_check(hipStreamSynchronize(st), "sync");
+    if (c[0] <= hit_cap) break;
+    hit_cap = c[0];
+    J.kernel_marks.clear();
+    }
     int t_probe1 = tm.mark();
     J.nhits = c[0];
     J.ncand = c[1];
     stats.selected += (int64_t)c[2];
     stats.hits += (int64_t)c[0];
     stats.candidates += (int64_t)c[1];
-    if (J.nhits > bound) throw Error(PJ_EDEVICE, "hit buffer overflow (%llu > %llu)",
-                                     (unsigned long long)J.nhits, (unsigned long long)bound);
+    if (J.nhits > hit_cap) throw Error(PJ_EDEVICE, "hit buffer overflow (%llu > %llu)",
+                                       (unsigned long long)J.nhits, (unsigned long long)hit_cap);
 
     const bool batched = J.mode != PJ_MODE_PLAIN;
     if (batched && J.nhits > 0) {
