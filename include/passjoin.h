@@ -96,6 +96,9 @@ typedef struct {
     double ms_probe_kernel;    /* device time of the probe kernel launches (hipEvents) */
     double ms_verify_kernel;   /* device time of the verification kernel launches (hipEvents) */
     int64_t verify_launches;   /* verification kernel launches */
+    double ms_list_kernel;     /* device time of the list-segment verification launches */
+    int64_t list_cells;        /* cells evaluated by the list-segment verification */
+    int64_t list_launches;     /* list-segment verification launches */
 } pj_stats;
 
 /* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with

@@ -61,7 +61,8 @@ class PjStats(C.Structure):
                [(k, C.c_double) for k in ("ms_upload", "ms_index", "ms_probe", "ms_verify",
                                           "ms_output", "ms_total", "ms_probe_kernel",
                                           "ms_verify_kernel")] + \
-               [("verify_launches", C.c_int64)]
+               [("verify_launches", C.c_int64), ("ms_list_kernel", C.c_double),
+                ("list_cells", C.c_int64), ("list_launches", C.c_int64)]
 
 
 class PjServerConfig(C.Structure):

@@ -62,6 +62,41 @@ __device__ inline T block_excl_scan(T v, T* s_wave, T* total)
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
+// Wave-private append buffer in LDS: lanes push items without touching global atomics; the
+// wave reserves space in the global output with one atomic per flush (a single-address device
+// atomic is serialised across all XCDs, so one per item would throttle the kernel).  `buf`
+// is this wave's region of CAP items; `fill` is wave-uniform.
+template <typename T, int CAP>
+struct WaveAppender {
+    T* buf;
+    int fill;
+
+    __device__ inline void flush(T* out, uint64_t cap, unsigned long long* counter)
+    {
+        if (fill == 0) return;
+        const int lane = threadIdx.x & 63;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned long long)fill);
+        base = __shfl(base, 0, 64);
+        for (int k = lane; k < fill; k += 64)
+            if (base + (uint64_t)k < cap) out[base + k] = buf[k];
+        fill = 0;
+    }
+
+    __device__ inline void push(bool flag, const T& item, T* out, uint64_t cap,
+                                unsigned long long* counter)
+    {
+        const uint64_t m = __ballot(flag);
+        if (m == 0) return;
+        const int k = __popcll(m);
+        if (fill + k > CAP) flush(out, cap, counter);
+        if (flag) buf[fill + __popcll(m & lanemask_lt())] = item;
+        fill += k;
+    }
+};
+
+constexpr int kAppendCap = 256;
+
 // ------------------------------------------------------------------------------------------
 // Device-wide exclusive scan (reduce -> scan partials -> apply), 2048 elements per block
 // ------------------------------------------------------------------------------------------
@@ -439,97 +474,92 @@ __global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restri
 // the members visited before x (self-join, l == |x|), and appends non-empty lookups as hits.
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
 {
+    __shared__ Hit s_hits[kWaves][kAppendCap];
     const int lane = threadIdx.x & 63;
-    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    WaveAppender<Hit, kAppendCap> app{s_hits[threadIdx.x >> 6], 0};
     const int T1 = P.tau + 1;
-    bool valid = t < P.threads;
-    uint64_t my_sel = 0;
-    int n = 0, l = 0, i = 0, lo = 1, hi = 0, tau = P.tau;
-    uint32_t gx = 0;
-    Seg sg{1, 0};
-    const uint8_t* x = nullptr;
-    const uint4* table = P.table;
-    const uint32_t* vals = P.vals;
-    uint64_t mask = P.mask;
-    if (valid) {
-        uint64_t per = (uint64_t)P.nl * T1;
-        gx = P.g_begin + (uint32_t)(t / per);
-        uint32_t rem = (uint32_t)(t % per);
-        i = (int)(rem % T1) + 1;
-        int dl = (int)(rem / T1);
-        n = P.x_slen[gx];
-        Div dv = div;
-        if (P.q_tau) {                       // mixed-tau batch: this probe string's own tau
-            tau = P.q_tau[gx];
-            const IndexRef ref = P.refs[tau];
-            table = ref.table;
-            vals = ref.vals;
-            mask = ref.mask;
-            dv.d = (uint32_t)(tau + 1);
-            dv.m = ref.div_m;
-        }
-        l = P.self ? n - dl : n - tau + dl;
-        const bool in_window = i <= tau + 1 && dl <= (P.self ? tau : 2 * tau) && l >= tau + 1;
-        // substrings selected for L_l^1 .. L_l^{tau+1}: the Lemma 2 count, whether or not
-        // strings of length l exist (Algorithm 1 selects for every l in the length window)
-        if (in_window && i == 1) {
-            const int d = n - l;
-            my_sel = (uint64_t)((tau * tau - d * d) / 2 + tau + 1);
-        }
-        valid = in_window && (l >= P.ymin) && (l <= P.ymax) &&
-                (P.y_lenstart[l + 1] > P.y_lenstart[l]);
+    uint64_t my_sel = 0, my_cand = 0;
+    // grid-stride over (probe string, length, slot) triples; the loop bound is block-uniform so
+    // every lane takes part in the wave-level appends
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock; t0 < P.threads;
+         t0 += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t t = t0 + threadIdx.x;
+        bool valid = t < P.threads;
+        int n = 0, l = 0, i = 0, lo = 1, hi = 0, tau = P.tau;
+        uint32_t gx = 0;
+        Seg sg{1, 0};
+        const uint8_t* x = nullptr;
+        const uint4* table = P.table;
+        const uint32_t* vals = P.vals;
+        uint64_t mask = P.mask;
         if (valid) {
-            sg = partition_seg(l, i, tau, dv);
-            multimatch_window(n, l, tau, i, sg, &lo, &hi);
-            x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
+            const uint64_t per = (uint64_t)P.nl * T1;
+            gx = P.g_begin + (uint32_t)(t / per);
+            const uint32_t rem = (uint32_t)(t % per);
+            i = (int)(rem % T1) + 1;
+            const int dl = (int)(rem / T1);
+            n = P.x_slen[gx];
+            Div dv = div;
+            if (P.q_tau) {                       // mixed-tau batch: this probe string's own tau
+                tau = P.q_tau[gx];
+                const IndexRef ref = P.refs[tau];
+                table = ref.table;
+                vals = ref.vals;
+                mask = ref.mask;
+                dv.d = (uint32_t)(tau + 1);
+                dv.m = ref.div_m;
+            }
+            l = P.self ? n - dl : n - tau + dl;
+            const bool in_window = i <= tau + 1 && dl <= (P.self ? tau : 2 * tau) && l >= tau + 1;
+            // substrings selected for L_l^1 .. L_l^{tau+1}: the Lemma 2 count, whether or not
+            // strings of length l exist (Algorithm 1 selects for every l in the length window)
+            if (in_window && i == 1) {
+                const int d = n - l;
+                my_sel += (uint64_t)((tau * tau - d * d) / 2 + tau + 1);
+            }
+            valid = in_window && (l >= P.ymin) && (l <= P.ymax) &&
+                    (P.y_lenstart[l + 1] > P.y_lenstart[l]);
+            if (valid) {
+                sg = partition_seg(l, i, tau, dv);
+                multimatch_window(n, l, tau, i, sg, &lo, &hi);
+                x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
+            }
         }
-    }
-    uint64_t my_cand = 0;
-    uint64_t h = 0, top = 0;
-    if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
-    for (int s = 0; s < T1; ++s) {
-        int p = lo + s;
-        bool active = valid && p <= hi;
-        if (__ballot(active) == 0) break;
-        uint32_t start = 0, count = 0;
-        if (active) {
-            const uint8_t* w = x + p - 1;
-            if (s == 0) h = seg_code(w, sg.len);
-            else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top);
-            uint64_t key = make_key(l, i, tau, sg.len, h);
-            if (table_lookup(table, mask, key, &start, &count)) {
-                if (P.self && l == n) {
-                    // keep members with g < gx (lists are ascending in g)
-                    uint32_t a = 0, b = count;
-                    while (a < b) {
-                        uint32_t m = (a + b) >> 1;
-                        if (vals[start + m] < gx) a = m + 1; else b = m;
+        uint64_t h = 0, top = 0;
+        if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
+        for (int s = 0; s < T1; ++s) {
+            const int p = lo + s;
+            const bool active = valid && p <= hi;
+            if (__ballot(active) == 0) break;
+            uint32_t start = 0, count = 0;
+            if (active) {
+                const uint8_t* w = x + p - 1;
+                if (s == 0) h = seg_code(w, sg.len);
+                else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top);
+                const uint64_t key = make_key(l, i, tau, sg.len, h);
+                if (table_lookup(table, mask, key, &start, &count)) {
+                    if (P.self && l == n) {
+                        // keep members with g < gx (lists are ascending in g)
+                        uint32_t a = 0, b = count;
+                        while (a < b) {
+                            const uint32_t m = (a + b) >> 1;
+                            if (vals[start + m] < gx) a = m + 1; else b = m;
+                        }
+                        count = a;
                     }
-                    count = a;
+                } else {
+                    count = 0;
                 }
-            } else {
-                count = 0;
             }
-        }
-        bool found = active && count > 0;
-        uint64_t fm = __ballot(found);
-        if (fm) {
-            int leader = __ffsll((unsigned long long)fm) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&P.counters[0], (unsigned long long)__popcll(fm));
-            base = __shfl(base, leader, 64);
-            if (found) {
-                uint64_t idx = base + (uint64_t)__popcll(fm & lanemask_lt());
-                if (idx < P.hit_cap) {
-                    Hit hh;
-                    hh.gx = gx; hh.start = start; hh.count = count;
-                    hh.meta = (uint32_t)(p - 1) | ((uint32_t)(i - 1) << 11) | ((uint32_t)l << 17);
-                    P.hits[idx] = hh;
-                }
-                my_cand += count;
-            }
+            const bool found = active && count > 0;
+            Hit hh;
+            hh.gx = gx; hh.start = start; hh.count = count;
+            hh.meta = (uint32_t)(p - 1) | ((uint32_t)(i - 1) << 11) | ((uint32_t)l << 17);
+            app.push(found, hh, P.hits, P.hit_cap, &P.counters[0]);
+            if (found) my_cand += count;
         }
     }
+    app.flush(P.hits, P.hit_cap, &P.counters[0]);
     my_cand = wave_sum(my_cand);
     my_sel = wave_sum(my_sel);
     if (lane == 0) {
@@ -651,55 +681,63 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
 constexpr int kWaveRounds = 16;
 constexpr uint64_t kWaveChunk = 64ull * kWaveRounds;
 
-// counts[i - 1] = hits of slot i
+// Bucket of a hit: lists with at least `big` candidates after all smaller ones, each part in
+// slot order.
+__device__ inline uint32_t hit_bucket(const Hit& v, uint32_t big)
+{
+    return ((v.count >= big) ? 64u : 0u) + ((v.meta >> 11) & 63u);
+}
+
+// counts[b] = hits of bucket b (128 buckets)
 __global__ __launch_bounds__(kBlock) void k_slot_hist(const Hit* __restrict__ hits,
                                                       const unsigned long long* __restrict__ nh_dev,
-                                                      uint32_t* __restrict__ counts)
+                                                      uint32_t big, uint32_t* __restrict__ counts)
 {
-    __shared__ uint32_t h[64];
-    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __shared__ uint32_t h[128];
+    if (threadIdx.x < 128) h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t nh = *nh_dev;
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < nh;
          k += (uint64_t)gridDim.x * kBlock)
-        atomicAdd(&h[(hits[k].meta >> 11) & 63u], 1u);
+        atomicAdd(&h[hit_bucket(hits[k], big)], 1u);
     __syncthreads();
-    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < 128 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
 }
 
 // Moves every hit into its slot's region (regions in slot order; order inside a region is
 // arbitrary, which changes nothing downstream: the result is sorted).  cursor[64] starts at 0.
 __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__ hits,
                                                          const unsigned long long* __restrict__ nh_dev,
+                                                         uint32_t big,
                                                          const uint32_t* __restrict__ counts,
                                                          uint32_t* __restrict__ cursor,
                                                          Hit* __restrict__ out)
 {
-    __shared__ uint32_t base[64];
+    __shared__ uint32_t base[128];
     if (threadIdx.x == 0) {
         uint32_t run = 0;
-        for (int k = 0; k < 64; ++k) {
+        for (int k = 0; k < 128; ++k) {
             base[k] = run;
             run += counts[k];
         }
     }
     __syncthreads();
-    __shared__ uint32_t cnt[64], res[64];
+    __shared__ uint32_t cnt[128], res[128];
     const uint64_t nh = *nh_dev;
     for (uint64_t k0 = (uint64_t)blockIdx.x * kBlock; k0 < nh; k0 += (uint64_t)gridDim.x * kBlock) {
         // one global reservation per (block, slot) per round; local ranks from LDS atomics
-        if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+        if (threadIdx.x < 128) cnt[threadIdx.x] = 0;
         __syncthreads();
         const uint64_t k = k0 + threadIdx.x;
         Hit v{};
         uint32_t sl = 0, rank = 0;
         if (k < nh) {
             v = hits[k];
-            sl = (v.meta >> 11) & 63u;
+            sl = hit_bucket(v, big);
             rank = atomicAdd(&cnt[sl], 1u);
         }
         __syncthreads();
-        if (threadIdx.x < 64 && cnt[threadIdx.x])
+        if (threadIdx.x < 128 && cnt[threadIdx.x])
             res[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
         __syncthreads();
         if (k < nh) out[base[sl] + res[sl] + rank] = v;
@@ -758,6 +796,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
                                                            const uint32_t* __restrict__ first,
                                                            uint64_t nchunks)
 {
+    __shared__ uint64_t s_acc[kWaves][kAppendCap];
+    WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
@@ -823,17 +863,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
                     }
                 }
             }
-            const uint64_t pm = __ballot(pass);
-            if (pm) {
-                const int leader = __ffsll((unsigned long long)pm) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(&V.counters[3], (unsigned long long)__popcll(pm));
-                base = __shfl(base, leader, 64);
-                if (pass) {
-                    const uint64_t idx = base + (uint64_t)__popcll(pm & lanemask_lt());
-                    if (idx < V.out_cap) V.out[idx] = ((uint64_t)gx << 32) | gy;
-                }
-            }
+            acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
             // the hit containing candidate g0 + 64 starts the next group
             const uint64_t nb = __ballot(rel <= 64);
             const int adv = __popcll(nb);
@@ -843,10 +873,182 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
             }
         }
     }
+    acc.flush(V.out, V.out_cap, &V.counters[3]);
     my_cells = wave_sum(my_cells);
     my_miss = wave_sum(my_miss);
     if (lane == 0) {
         if (my_cells) atomicAdd(&V.counters[4], (unsigned long long)my_cells);
+        if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// List-segment verification: a wave verifies up to 64 members of one inverted list against
+// the same probe substring, so the probe string, the partition and both band geometries are
+// wave-uniform and only the indexed string differs per lane.  Used for lists with at least
+// kBigList candidates; smaller lists go through k_verify_batched.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kSegChunk = 4;    // list segments (of 64 members) per wave chunk
+
+__global__ __launch_bounds__(kBlock) void k_seg_counts(const Hit* __restrict__ hits, uint64_t nbig,
+                                                       uint32_t* __restrict__ segs)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < nbig) segs[k] = (hits[k].count + 63u) >> 6;
+}
+
+// first[ch] = the list holding segment ch * kSegChunk (largest h with segp[h] <= it)
+__global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __restrict__ segp,
+                                                             uint64_t nbig, uint64_t nchunks,
+                                                             uint32_t* __restrict__ first)
+{
+    const uint64_t ch = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (ch >= nchunks) return;
+    const uint64_t s0 = ch * kSegChunk;
+    uint64_t a = 0, b = nbig - 1;
+    while (a < b) {
+        const uint64_t m = (a + b + 1) >> 1;
+        if (segp[m] <= s0) a = m; else b = m - 1;
+    }
+    first[ch] = (uint32_t)a;
+}
+
+template <int MAXW, typename LaneChars>
+__device__ inline int vsp_seg_any(bool yrows, const uint8_t* U, int lu, LaneChars V, int lv,
+                                  int t, int* cells)
+{
+    return yrows ? vsp_seg<MAXW, true>(U, lu, V, lv, t, cells)
+                 : vsp_seg<MAXW, false>(U, lu, V, lv, t, cells);
+}
+
+// exact band width for uniform t <= 8, else the width class GMAXW
+template <int GMAXW, typename LaneChars>
+__device__ inline int vsp_seg_dispatch(bool yrows, const uint8_t* U, int lu, LaneChars V,
+                                       int lv, int t, int* cells)
+{
+    switch (t) {
+    case 0: return vsp_seg_any<1>(yrows, U, lu, V, lv, t, cells);
+    case 1: return vsp_seg_any<2>(yrows, U, lu, V, lv, t, cells);
+    case 2: return vsp_seg_any<3>(yrows, U, lu, V, lv, t, cells);
+    case 3: return vsp_seg_any<4>(yrows, U, lu, V, lv, t, cells);
+    case 4: return vsp_seg_any<5>(yrows, U, lu, V, lv, t, cells);
+    case 5: return vsp_seg_any<6>(yrows, U, lu, V, lv, t, cells);
+    case 6: return vsp_seg_any<7>(yrows, U, lu, V, lv, t, cells);
+    case 7: return vsp_seg_any<8>(yrows, U, lu, V, lv, t, cells);
+    case 8: return vsp_seg_any<9>(yrows, U, lu, V, lv, t, cells);
+    default: return vsp_seg_any<GMAXW>(yrows, U, lu, V, lv, t, cells);
+    }
+}
+
+template <int GMAXW, int REGY>
+__global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
+                                                        const Hit* __restrict__ big,
+                                                        const uint32_t* __restrict__ segp,
+                                                        uint64_t nbig, uint64_t nseg,
+                                                        const uint32_t* __restrict__ first,
+                                                        uint64_t nchunks)
+{
+    __shared__ uint64_t s_acc[kWaves][kAppendCap];
+    WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    uint64_t my_cells = 0, my_miss = 0;
+    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
+        uint64_t sg_i = ch * kSegChunk;
+        const uint64_t sg_end = (sg_i + kSegChunk < nseg) ? sg_i + kSegChunk : nseg;
+        uint32_t h = __builtin_amdgcn_readfirstlane(first[ch]);
+        uint32_t sidx = __builtin_amdgcn_readfirstlane((uint32_t)(sg_i - segp[h]));
+        for (; sg_i < sg_end; ++sg_i) {
+            const Hit hit = big[h];
+            const uint32_t gx = __builtin_amdgcn_readfirstlane(hit.gx);
+            const uint32_t start = __builtin_amdgcn_readfirstlane(hit.start);
+            const uint32_t count = __builtin_amdgcn_readfirstlane(hit.count);
+            const uint32_t meta = __builtin_amdgcn_readfirstlane(hit.meta);
+            int tau = V.tau;
+            const uint32_t* vals = V.vals;
+            Div dv = div;
+            if (V.q_tau) {
+                tau = __builtin_amdgcn_readfirstlane(V.q_tau[gx]);
+                vals = V.refs[tau].vals;
+                dv.d = (uint32_t)(tau + 1);
+                dv.m = V.refs[tau].div_m;
+            }
+            const int p = (int)(meta & 2047u) + 1;
+            const int i = (int)((meta >> 11) & 63u) + 1;
+            const int l = (int)(meta >> 17);
+            const int n = __builtin_amdgcn_readfirstlane((int)V.x_slen[gx]);
+            const uint8_t* x = V.x_arena + V.x_gbase[n] + (int64_t)(gx - V.x_lenstart[n]) * stride_of(n);
+            const int64_t ybase = V.y_gbase[l] - (int64_t)V.y_lenstart[l] * stride_of(l);
+            const Seg sgm = partition_seg(l, i, tau, dv);
+            const uint32_t member = sidx * 64u + (uint32_t)lane;
+            const bool active = member < count;
+            bool pass = false;
+            uint32_t gy = 0;
+            if (active) {
+                gy = vals[start + member];
+                const uint8_t* y = V.y_arena + ybase + (int64_t)gy * stride_of(l);
+                // REGY > 0: the whole indexed string (at most REGY bytes, 16-byte aligned slot)
+                // goes to registers with wide loads; the DP then reads it at wave-uniform offsets
+                uint32_t yr[REGY > 0 ? REGY / 4 : 1];
+                if (REGY > 0) {
+                    const uint4* yq = reinterpret_cast<const uint4*>(y);
+#pragma unroll
+                    for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
+                        const uint4 v = (q * 16 < l) ? yq[q] : make_uint4(0u, 0u, 0u, 0u);
+                        yr[4 * q] = v.x; yr[4 * q + 1] = v.y; yr[4 * q + 2] = v.z; yr[4 * q + 3] = v.w;
+                    }
+                }
+                bool same = true;
+                if (sgm.len > kExactLen) {
+                    if (REGY > 0) {
+                        const RegChars yc{yr, sgm.p - 1};
+                        for (int k = 0; k < sgm.len; ++k) same &= ((int)x[p - 1 + k] == yc[k]);
+                    } else {
+                        for (int k = 0; k < sgm.len; ++k) same &= (x[p - 1 + k] == y[sgm.p - 1 + k]);
+                    }
+                }
+                if (!same) {
+                    my_miss += 1;
+                } else {
+                    // left parts: x[1, p-1] vs y[1, p_i-1], t = i-1; right parts after the segment
+                    const int tl = i - 1, tr = tau + 1 - i;
+                    const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
+                    int c1 = 0, dl;
+                    if (REGY > 0)
+                        dl = vsp_seg_dispatch<GMAXW>(sgm.p - 1 <= p - 1, x, p - 1, RegChars{yr, 0},
+                                                     sgm.p - 1, tl, &c1);
+                    else
+                        dl = vsp_seg_dispatch<GMAXW>(sgm.p - 1 <= p - 1, x, p - 1, GlobalChars{y},
+                                                     sgm.p - 1, tl, &c1);
+                    my_cells += c1;
+                    if (dl <= tl) {
+                        int c2 = 0, dr;
+                        if (REGY > 0)
+                            dr = vsp_seg_dispatch<GMAXW>(l - ry <= n - rx, x + rx, n - rx,
+                                                         RegChars{yr, ry}, l - ry, tr, &c2);
+                        else
+                            dr = vsp_seg_dispatch<GMAXW>(l - ry <= n - rx, x + rx, n - rx,
+                                                         GlobalChars{y + ry}, l - ry, tr, &c2);
+                        my_cells += c2;
+                        pass = dr <= tr;
+                    }
+                }
+            }
+            acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
+            ++sidx;
+            if (sidx * 64u >= count) {
+                ++h;
+                sidx = 0;
+            }
+        }
+    }
+    acc.flush(V.out, V.out_cap, &V.counters[3]);
+    my_cells = wave_sum(my_cells);
+    my_miss = wave_sum(my_miss);
+    if (lane == 0) {
+        if (my_cells) atomicAdd(&V.counters[7], (unsigned long long)my_cells);
         if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
     }
 }
@@ -1061,11 +1263,11 @@ hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hip
     return hipGetLastError();
 }
 
-hipError_t launch_probe(const ProbeParams& P, hipStream_t s)
+hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s)
 {
     if (P.threads == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_probe, dim3(blocks_for(P.threads)), dim3(kBlock), 0, s, P,
-                       make_div(P.tau + 1));
+    const uint64_t blocks = std::min<uint64_t>(blocks_for(P.threads), (uint64_t)max_blocks);
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(kBlock), 0, s, P, make_div(P.tau + 1));
     return hipGetLastError();
 }
 
@@ -1086,13 +1288,52 @@ static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint6
 uint64_t batched_chunks(uint64_t ncand) { return (ncand + kWaveChunk - 1) / kWaveChunk; }
 
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
-                              uint32_t* counts, uint32_t* cursor, Hit* out, hipStream_t s)
+                              uint32_t big, uint32_t* counts, uint32_t* cursor, Hit* out,
+                              hipStream_t s)
 {
     if (nh_cap == 0) return hipSuccess;
     unsigned grid = (unsigned)std::min<uint64_t>((nh_cap + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, counts);
-    hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, counts,
+    hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, counts);
+    hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, counts,
                        cursor, out);
+    return hipGetLastError();
+}
+
+template <int W>
+static void verify_segs_w(const VerifyParams& V, const Hit* big, const uint32_t* segp,
+                          uint64_t nbig, uint64_t nseg, const uint32_t* first, uint64_t nchunks,
+                          int grid, hipStream_t s)
+{
+    if (V.y_maxlen <= 64)
+        hipLaunchKernelGGL((k_verify_segs<W, 64>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks);
+    else
+        hipLaunchKernelGGL((k_verify_segs<W, 0>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks);
+}
+
+uint64_t seg_chunks(uint64_t nseg) { return (nseg + kSegChunk - 1) / kSegChunk; }
+
+hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipStream_t s)
+{
+    if (nbig == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_counts, dim3(blocks_for(nbig)), dim3(kBlock), 0, s, big, nbig, segs);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint32_t* segp,
+                              uint64_t nbig, uint64_t nseg, uint32_t* first, int grid,
+                              hipStream_t s)
+{
+    if (nbig == 0 || nseg == 0) return hipSuccess;
+    const uint64_t nchunks = seg_chunks(nseg);
+    hipLaunchKernelGGL(k_seg_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, segp,
+                       nbig, nchunks, first);
+    const int w = V.tau + 1;
+    if (w <= 9) verify_segs_w<9>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
+    else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
+    else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
+    else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
     return hipGetLastError();
 }
 

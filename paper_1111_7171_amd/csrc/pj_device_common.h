@@ -311,4 +311,117 @@ __device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int l
     return out;
 }
 
+// VerifyStringPair for a wave whose lanes share the probe string's part and the band geometry
+// (all lanes verify members of one inverted list against the same x): same results and cell
+// counts as vsp_global.  U points at the shared part (x's), V at the lane's own part (y's);
+// the part lengths lu, lv and t are wave-uniform.  YROWS tells which part gives the rows
+// (the shorter one; y's when equal), so the shared characters are either the row character
+// or the column window and live in scalar registers.
+// Characters of the lane's own part: from global memory, or from the lane's copy of its whole
+// string in registers (uniform position: the wave shares the part's offset and the row).
+struct GlobalChars {
+    const uint8_t* p;
+    __device__ inline int operator[](int k) const { return (int)p[k]; }
+};
+
+struct RegChars {
+    const uint32_t* r;   // the string's bytes, 4 per register (at most 64 bytes)
+    int off;             // part offset within the string (wave-uniform)
+    __device__ inline int operator[](int k) const
+    {
+        const int q = off + k;
+        return (int)((r[q >> 2] >> ((q & 3) * 8)) & 0xffu);
+    }
+};
+
+template <int MAXW, bool YROWS, typename LaneChars>
+__device__ inline int vsp_seg(const uint8_t* U, int lu, LaneChars V, int lv, int t, int* cells)
+{
+    const GlobalChars Ug{U};
+    const int nr = YROWS ? lv : lu;
+    const int nc = YROWS ? lu : lv;
+    const int delta = nc - nr;
+    *cells = 0;
+    if (delta > t) return t + 1;
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    const int W = a + b + 1;
+    const int INF = t + 1;
+    constexpr int BIG = 1 << 20;
+    int R[MAXW], w[MAXW], ek[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int j = k - a;
+        R[k] = (k < W && j >= 0 && j <= nc) ? (j < INF ? j : INF) : INF;
+        const int idx = k - a;
+        w[k] = ((unsigned)idx < (unsigned)nc) ? (YROWS ? Ug[idx] : V[idx]) : 256;
+        const int dd = delta + a - k;
+        ek[k] = dd < 0 ? -dd : dd;
+    }
+    int idx_in = MAXW - a;
+    int cin = ((unsigned)idx_in < (unsigned)nc) ? (YROWS ? Ug[idx_in] : V[idx_in]) : 256;
+    int ai = nr > 0 ? (YROWS ? V[0] : Ug[0]) : 256;
+    int ai_next = nr > 1 ? (YROWS ? V[1] : Ug[1]) : 256;
+    int ncell = 0;
+    int res = -1;
+    for (int i = 1; i <= nr; ++i) {
+        const int idx2 = idx_in + 1;
+        const int cin_next = ((unsigned)idx2 < (unsigned)nc) ? (YROWS ? Ug[idx2] : V[idx2]) : 256;
+        const int ai_next2 = (i + 1 < nr) ? (YROWS ? V[i + 1] : Ug[i + 1]) : 256;
+        const int j0 = i - a;
+        int left = INF;
+        int emin = BIG;
+        if (j0 >= 1 && j0 + W - 1 <= nc) {
+            // the whole band is inside the matrix (uniform test): no masking
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                if (k < W) {
+                    const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
+                    const int upk = (k + 1 < W) ? up : INF;
+                    const int d = (ai != w[k]) ? 1 : 0;
+                    const int v = min(min(upk, left) + 1, R[k] + d);
+                    emin = min(emin, v + ek[k]);
+                    R[k] = v;
+                    left = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                const int j = j0 + k;
+                const bool valid = (k < W) && j >= 0 && j <= nc;
+                const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
+                const int upk = (k + 1 < W) ? up : INF;
+                const int d = (ai != w[k]) ? 1 : 0;
+                int v = min(min(upk, left) + 1, R[k] + d);
+                v = (j == 0) ? i : v;
+                v = valid ? v : INF;
+                emin = min(emin, valid ? v + ek[k] : BIG);
+                R[k] = v;
+                left = v;
+            }
+        }
+        const int lo = max(1, j0), hi = min(nc, j0 + W - 1);
+        ncell += max(0, hi - lo + 1);
+        if (emin > t) {
+            res = t + 1;
+            break;
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
+        w[MAXW - 1] = cin;
+        cin = cin_next;
+        idx_in = idx2;
+        ai = ai_next;
+        ai_next = ai_next2;
+    }
+    *cells = ncell;
+    if (res >= 0) return res;
+    int out = INF;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k)
+        if (k == delta + a) out = R[k];
+    return min(out, INF);
+}
+
 }  // namespace pj

@@ -24,6 +24,11 @@
 
 namespace pj {
 
+// Inverted lists with at least this many candidates are verified a 64-member segment per wave.
+constexpr uint32_t kBigList = 32;
+// Below this many candidates the batched path verifies the hits in probe order, in one launch.
+constexpr uint64_t kBucketMinCandidates = 1ull << 20;
+
 // ------------------------------------------------------------------------------------------
 // Errors and per-thread state
 // ------------------------------------------------------------------------------------------
@@ -439,7 +444,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.hits = J.hits; pp.hit_cap = hit_cap;
         pp.counters = J.counters;
         int k0 = tm.mark();
-        hip_check(launch_probe(pp, st), "probe");
+        hip_check(launch_probe(pp, device_cus() * 8, st), "probe");
         int k1 = tm.mark();
         J.kernel_marks.push_back({k0, k1, 0});
     }
@@ -459,25 +464,55 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                                        (unsigned long long)J.nhits, (unsigned long long)hit_cap);
 
     const bool batched = J.mode != PJ_MODE_PLAIN;
-    if (batched && J.nhits > 0) {
-        // bucket the hits by slot so that waves see one (tau_l, tau_r)
-        uint32_t* sc = (uint32_t*)W.get("join.slotcnt", 128 * sizeof(uint32_t));
-        hip_check(hipMemsetAsync(sc, 0, 128 * sizeof(uint32_t), st), "memset");
+    // batched: hits bucketed into [lists with < kBigList candidates | the others], each part
+    // in slot order; small lists are verified candidate by candidate, big ones a 64-member
+    // segment per wave
+    uint64_t nsmall = J.nhits, nbig = 0, ncand_small = J.ncand, nseg = 0;
+    uint32_t* segp = nullptr;
+    // few candidates (a serving batch): the bucketing round trips would cost more than they save
+    uint64_t bucket_min = kBucketMinCandidates;
+    if (const char* e = getenv("PJ_BUCKET_MIN_CANDIDATES")) bucket_min = strtoull(e, nullptr, 10);
+    if (batched && J.nhits > 0 && J.ncand >= bucket_min) {
+        uint32_t* sc = (uint32_t*)W.get("join.slotcnt", 256 * sizeof(uint32_t));
+        hip_check(hipMemsetAsync(sc, 0, 256 * sizeof(uint32_t), st), "memset");
         Hit* sorted = (Hit*)W.get("join.hits2", sizeof(Hit) * (size_t)J.nhits);
-        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, sc, sc + 64, sorted, st),
-                  "slot_bucket");
+        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, kBigList, sc, sc + 128, sorted,
+                                     st), "slot_bucket");
         J.hits = sorted;
+        uint32_t hc[128];
+        hip_check(hipMemcpyAsync(hc, sc, sizeof hc, hipMemcpyDeviceToHost, st), "bucket counts");
+        hip_check(hipStreamSynchronize(st), "sync");
+        nsmall = 0;
+        for (int k = 0; k < 64; ++k) nsmall += hc[k];
+        nbig = J.nhits - nsmall;
     }
 
-    // candidate prefix sums
+    // candidate prefix sums of the (small) lists, list segments of the big ones
     J.prefix = (unsigned long long*)W.get("join.prefix",
-                                          sizeof(unsigned long long) * (size_t)(J.nhits + 1));
-    if (J.nhits > 0) {
-        uint32_t* counts = (uint32_t*)W.get("join.counts", sizeof(uint32_t) * (size_t)J.nhits);
-        hip_check(launch_hit_counts(J.hits, J.nhits, counts, st), "hit_counts");
-        size_t sb = scan_tmp_bytes(J.nhits);
+                                          sizeof(unsigned long long) * (size_t)(nsmall + 1));
+    if (nsmall > 0) {
+        uint32_t* counts = (uint32_t*)W.get("join.counts", sizeof(uint32_t) * (size_t)nsmall);
+        hip_check(launch_hit_counts(J.hits, nsmall, counts, st), "hit_counts");
+        size_t sb = scan_tmp_bytes(nsmall);
         void* stmp = W.get("scan.tmp", sb);
-        hip_check(scan_u32_to_u64(counts, J.prefix, J.nhits, stmp, sb, st), "scan(prefix)");
+        hip_check(scan_u32_to_u64(counts, J.prefix, nsmall, stmp, sb, st), "scan(prefix)");
+    }
+    if (nbig > 0) {
+        uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
+        segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + 1));
+        hip_check(launch_seg_counts(J.hits + nsmall, nbig, segs, st), "seg_counts");
+        size_t sb = scan_tmp_bytes(nbig);
+        void* stmp = W.get("scan.tmp2", sb);
+        hip_check(scan_u32_to_u32(segs, segp, nbig, stmp, sb, st), "scan(segs)");
+        uint32_t ns = 0;
+        unsigned long long cs = 0;
+        hip_check(hipMemcpyAsync(&ns, segp + nbig, sizeof ns, hipMemcpyDeviceToHost, st), "nseg");
+        if (nsmall > 0)
+            hip_check(hipMemcpyAsync(&cs, J.prefix + nsmall, sizeof cs, hipMemcpyDeviceToHost, st),
+                      "ncand small");
+        hip_check(hipStreamSynchronize(st), "sync");
+        nseg = ns;
+        ncand_small = cs;
     }
 
     // verify (+ short path); rerun once with an exact buffer when the first guess overflows
@@ -485,6 +520,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     for (int attempt = 0; attempt < 2; ++attempt) {
         J.out = (uint64_t*)W.get("join.out", sizeof(uint64_t) * (size_t)cap);
         hip_check(hipMemsetAsync(J.counters + 3, 0, 5 * sizeof(unsigned long long), st), "memset");
+        J.kernel_marks.erase(std::remove_if(J.kernel_marks.begin(), J.kernel_marks.end(),
+                                            [](const JoinScratch::Mark& m) { return m.kind != 0; }),
+                             J.kernel_marks.end());
         if (J.ncand > 0) {
             VerifyParams vp{};
             vp.x_arena = P.sarena; vp.x_slen = P.slen; vp.x_lenstart = P.lenstart;
@@ -494,28 +532,42 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.q_tau = spec.q_tau;
             vp.refs = spec.refs;
             vp.hits = J.hits; vp.prefix = J.prefix;
-            vp.nhits = J.nhits; vp.ncand = J.ncand;
+            vp.nhits = nsmall; vp.ncand = ncand_small;
             vp.tau = tau;
+            vp.y_maxlen = Y.lmax;
             vp.out = J.out; vp.out_cap = cap;
             vp.counters = J.counters;
-            int k0 = 0;
+            int k0 = tm.mark();
             if (batched) {
-                const uint64_t nchunks = batched_chunks(J.ncand);
-                uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
-                // persistent: enough waves to fill the chip, each walking its chunks
-                const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
-                const int grid = (int)((waves + 3) / 4);
-                k0 = tm.mark();
-                hip_check(launch_verify_batched(vp, first, grid, st), "verify_batched");
+                if (ncand_small > 0) {
+                    const uint64_t nchunks = batched_chunks(ncand_small);
+                    uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
+                    // persistent: enough waves to fill the chip, each walking its chunks
+                    const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
+                    hip_check(launch_verify_batched(vp, first, (int)((waves + 3) / 4), st),
+                              "verify_batched");
+                    stats.verify_launches += 1;
+                }
+                if (nseg > 0) {
+                    const uint64_t nchunks = seg_chunks(nseg);
+                    uint32_t* first = (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)nchunks);
+                    const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
+                    const int s0 = tm.mark();
+                    hip_check(launch_verify_segs(vp, J.hits + nsmall, segp, nbig, nseg, first,
+                                                 (int)((waves + 3) / 4), st), "verify_segs");
+                    const int s1 = tm.mark();
+                    J.kernel_marks.push_back({s0, s1, 2});
+                    stats.verify_launches += 1;
+                    stats.list_launches += 1;
+                }
             } else {
                 const uint64_t nchunks = (J.ncand + 1023) / 1024;
                 const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 16);
-                k0 = tm.mark();
                 hip_check(launch_verify(vp, grid, st), "verify");
+                stats.verify_launches += 1;
             }
             int k1 = tm.mark();
             J.kernel_marks.push_back({k0, k1, 1});
-            stats.verify_launches += 1;
         }
         hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, spec.q_tau, J.out, cap, J.counters,
                                     st), "short_path");
@@ -527,7 +579,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     int t_verify1 = tm.mark();
     J.naccepted = c[3];
     stats.accepted += (int64_t)c[3];
-    stats.cells += (int64_t)c[4];
+    stats.cells += (int64_t)(c[4] + c[7]);
+    stats.list_cells += (int64_t)c[7];
     stats.side_pairs += (int64_t)c[6];
     J.guard_misses = c[5];
     stats.ms_probe += tm.ms(t_probe0, t_probe1);
@@ -535,7 +588,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     for (const auto& km : J.kernel_marks) {
         double v = tm.ms(km.a, km.b);
         if (km.kind == 0) stats.ms_probe_kernel += v;
-        else stats.ms_verify_kernel += v;
+        else if (km.kind == 1) stats.ms_verify_kernel += v;
+        else stats.ms_list_kernel += v;
     }
     J.kernel_marks.clear();
 }

@@ -101,10 +101,11 @@ struct VerifyParams {
     const Hit* hits; const unsigned long long* prefix;   // [nhits + 1] exclusive prefix of counts
     uint64_t nhits; uint64_t ncand;
     int tau;                                              // uniform tau or the batch's largest
+    int y_maxlen;                                         // longest indexed string
     const int32_t* q_tau;                                 // per-probe tau or nullptr
     const IndexRef* refs;                                 // [kTauMax + 1] when q_tau is set
     uint64_t* out; uint64_t out_cap;                      // accepted (gx << 32 | gy)
-    unsigned long long* counters;                         // [3] accepted, [4] cells, [5] guard misses
+    unsigned long long* counters;    // [3] accepted, [4] cells, [5] guard misses, [7] list-segment cells
 };
 
 // ---- launchers (pj_device.hip) ----
@@ -124,13 +125,21 @@ hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid,
 hipError_t launch_clear_table(uint4* table, uint64_t slots, hipStream_t s);
 hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
                               uint32_t E, uint4* table, uint64_t mask, hipStream_t s);
-hipError_t launch_probe(const ProbeParams& P, hipStream_t s);
+hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
 // batched path: bucket hits by slot (counts and cursor: 64 zeroed u32 each), then verify with
 // per-wave chunks (first: batched_chunks(ncand) u32 of scratch)
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
-                              uint32_t* counts, uint32_t* cursor, Hit* out, hipStream_t s);
+                              uint32_t big, uint32_t* counts, uint32_t* cursor, Hit* out,
+                              hipStream_t s);
+// list-segment verification of the lists with >= big candidates (hits big[0 .. nbig), segp =
+// exclusive scan of ceil(count / 64), nseg segments; first: seg_chunks(nseg) u32 of scratch)
+hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipStream_t s);
+hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint32_t* segp,
+                              uint64_t nbig, uint64_t nseg, uint32_t* first, int grid,
+                              hipStream_t s);
+uint64_t seg_chunks(uint64_t nseg);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
 uint64_t batched_chunks(uint64_t ncand);
 hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self,

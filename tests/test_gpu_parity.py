@@ -78,13 +78,17 @@ def test_cfg1_full_exact_pairs_and_counts():
     assert st["selected"] == pj.selected
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", MODES + ["bucketed"])
 @pytest.mark.parametrize("cfg,n,taus", [
     (2, 20_000, (1, 2, 3, 4)),
     (3, 8_000, (2, 4, 6, 8)),
     (4, 1_500, (8, 16, 32)),
 ])
-def test_scaled_configs_match_oracle(cfg, n, taus, mode):
+def test_scaled_configs_match_oracle(cfg, n, taus, mode, monkeypatch):
+    if mode == "bucketed":
+        # the batched path's slot bucketing and list-segment kernel at any candidate count
+        monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
+        mode = P.MODE_BATCHED
     col = W.CONFIGS[cfg](n)
     for tau in taus:
         _say("cfg", cfg, "n", n, "tau", tau, "mode", mode)
