@@ -914,31 +914,38 @@ __global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __r
     first[ch] = (uint32_t)a;
 }
 
-template <int MAXW, typename LaneChars>
-__device__ inline int vsp_seg_any(bool yrows, const uint8_t* U, int lu, LaneChars V, int lv,
-                                  int t, int* cells)
+template <int MAXW, bool EXACT, typename LaneChars>
+__device__ inline int vsp_seg_any(bool yrows, LdsChars U, int lu, LaneChars V, int lv, int t,
+                                  BandLanes BL, int* cells)
 {
-    return yrows ? vsp_seg<MAXW, true>(U, lu, V, lv, t, cells)
-                 : vsp_seg<MAXW, false>(U, lu, V, lv, t, cells);
+    return yrows ? vsp_seg<MAXW, EXACT, true>(U, lu, V, lv, t, BL, cells)
+                 : vsp_seg<MAXW, EXACT, false>(U, lu, V, lv, t, BL, cells);
 }
 
 // exact band width for uniform t <= 8, else the width class GMAXW
 template <int GMAXW, typename LaneChars>
-__device__ inline int vsp_seg_dispatch(bool yrows, const uint8_t* U, int lu, LaneChars V,
-                                       int lv, int t, int* cells)
+__device__ inline int vsp_seg_dispatch(bool yrows, LdsChars U, int lu, LaneChars V, int lv,
+                                       int t, BandLanes BL, int* cells)
 {
     switch (t) {
-    case 0: return vsp_seg_any<1>(yrows, U, lu, V, lv, t, cells);
-    case 1: return vsp_seg_any<2>(yrows, U, lu, V, lv, t, cells);
-    case 2: return vsp_seg_any<3>(yrows, U, lu, V, lv, t, cells);
-    case 3: return vsp_seg_any<4>(yrows, U, lu, V, lv, t, cells);
-    case 4: return vsp_seg_any<5>(yrows, U, lu, V, lv, t, cells);
-    case 5: return vsp_seg_any<6>(yrows, U, lu, V, lv, t, cells);
-    case 6: return vsp_seg_any<7>(yrows, U, lu, V, lv, t, cells);
-    case 7: return vsp_seg_any<8>(yrows, U, lu, V, lv, t, cells);
-    case 8: return vsp_seg_any<9>(yrows, U, lu, V, lv, t, cells);
-    default: return vsp_seg_any<GMAXW>(yrows, U, lu, V, lv, t, cells);
+    case 0: return vsp_seg_any<1, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 1: return vsp_seg_any<2, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 2: return vsp_seg_any<3, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 3: return vsp_seg_any<4, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 4: return vsp_seg_any<5, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 5: return vsp_seg_any<6, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 6: return vsp_seg_any<7, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 7: return vsp_seg_any<8, true>(yrows, U, lu, V, lv, t, BL, cells);
+    case 8: return vsp_seg_any<9, true>(yrows, U, lu, V, lv, t, BL, cells);
+    default: return vsp_seg_any<GMAXW, false>(yrows, U, lu, V, lv, t, BL, cells);
     }
+}
+
+// a wave-uniform load through the scalar cache (read-only data)
+template <typename T>
+__device__ inline T uniform_load(const T* p)
+{
+    return *(const __attribute__((address_space(4))) T*)p;
 }
 
 template <int GMAXW, int REGY>
@@ -950,98 +957,127 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         uint64_t nchunks)
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
+    __shared__ uint32_t s_x[kWaves][(kLenMax + 4) / 4];   // the current probe string
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    uint32_t* sx = s_x[threadIdx.x >> 6];
+    const __attribute__((address_space(3))) uint8_t* xl8 =
+        (const __attribute__((address_space(3))) uint8_t*)(sx);
+    // wave id as a scalar, so that everything derived from it is known to be wave-uniform
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves +
+                          (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
     uint64_t my_cells = 0, my_miss = 0;
     for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
         uint64_t sg_i = ch * kSegChunk;
         const uint64_t sg_end = (sg_i + kSegChunk < nseg) ? sg_i + kSegChunk : nseg;
-        uint32_t h = __builtin_amdgcn_readfirstlane(first[ch]);
-        uint32_t sidx = __builtin_amdgcn_readfirstlane((uint32_t)(sg_i - segp[h]));
-        for (; sg_i < sg_end; ++sg_i) {
-            const Hit hit = big[h];
-            const uint32_t gx = __builtin_amdgcn_readfirstlane(hit.gx);
-            const uint32_t start = __builtin_amdgcn_readfirstlane(hit.start);
-            const uint32_t count = __builtin_amdgcn_readfirstlane(hit.count);
-            const uint32_t meta = __builtin_amdgcn_readfirstlane(hit.meta);
+        uint32_t h = uniform_load(first + ch);
+        uint32_t sidx = (uint32_t)(sg_i - uniform_load(segp + h));
+        while (sg_i < sg_end) {
+            // everything about the hit is wave-uniform: probe string, slot, both parts
+            const uint32_t* hw = reinterpret_cast<const uint32_t*>(big + h);
+            const uint32_t gx = uniform_load(hw), start = uniform_load(hw + 1);
+            const uint32_t count = uniform_load(hw + 2), meta = uniform_load(hw + 3);
             int tau = V.tau;
             const uint32_t* vals = V.vals;
             Div dv = div;
             if (V.q_tau) {
-                tau = __builtin_amdgcn_readfirstlane(V.q_tau[gx]);
-                vals = V.refs[tau].vals;
+                tau = uniform_load(V.q_tau + gx);
+                const IndexRef* rf = V.refs + tau;
+                vals = uniform_load(&rf->vals);
                 dv.d = (uint32_t)(tau + 1);
-                dv.m = V.refs[tau].div_m;
+                dv.m = uniform_load(&rf->div_m);
             }
             const int p = (int)(meta & 2047u) + 1;
             const int i = (int)((meta >> 11) & 63u) + 1;
             const int l = (int)(meta >> 17);
             const int n = __builtin_amdgcn_readfirstlane((int)V.x_slen[gx]);
-            const uint8_t* x = V.x_arena + V.x_gbase[n] + (int64_t)(gx - V.x_lenstart[n]) * stride_of(n);
-            const int64_t ybase = V.y_gbase[l] - (int64_t)V.y_lenstart[l] * stride_of(l);
+            const uint8_t* x = V.x_arena + uniform_load(V.x_gbase + n) +
+                               (int64_t)(gx - (uint32_t)uniform_load(V.x_lenstart + n)) * stride_of(n);
+            const int64_t ybase = uniform_load(V.y_gbase + l) -
+                                  (int64_t)uniform_load(V.y_lenstart + l) * stride_of(l);
             const Seg sgm = partition_seg(l, i, tau, dv);
-            const uint32_t member = sidx * 64u + (uint32_t)lane;
-            const bool active = member < count;
-            bool pass = false;
-            uint32_t gy = 0;
-            if (active) {
-                gy = vals[start + member];
-                const uint8_t* y = V.y_arena + ybase + (int64_t)gy * stride_of(l);
+            // stage x in the wave's LDS buffer (its slot is 16-byte aligned); the previous
+            // hit's reads were issued before these writes, and LDS requests of a wave complete
+            // in order
+            {
+                const uint32_t* xw = reinterpret_cast<const uint32_t*>(x);
+                for (int q = lane; q < ((n + 3) >> 2); q += 64) sx[q] = xw[q];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // left parts: x[1, p-1] vs y[1, p_i-1] with t = i-1; right parts after the segment
+            // with t = tau+1-i (Algorithm 3)
+            const int tl = i - 1, tr = tau + 1 - i;
+            const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
+            const BandLanes bl = band_lanes(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane);
+            const BandLanes br = band_lanes(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane);
+            const uint32_t hsegs = (count + 63u) >> 6;
+            const uint64_t left_in_chunk = sg_end - sg_i;
+            const uint32_t s_stop = (uint64_t)(hsegs - sidx) < left_in_chunk
+                                        ? hsegs : sidx + (uint32_t)left_in_chunk;
+            for (; sidx < s_stop; ++sidx, ++sg_i) {
+                const uint32_t member = sidx * 64u + (uint32_t)lane;
+                uint32_t gy = 0;
+                const uint8_t* y = V.y_arena;
                 // REGY > 0: the whole indexed string (at most REGY bytes, 16-byte aligned slot)
-                // goes to registers with wide loads; the DP then reads it at wave-uniform offsets
+                // goes to registers with wide loads and is read at wave-uniform offsets
                 uint32_t yr[REGY > 0 ? REGY / 4 : 1];
-                if (REGY > 0) {
-                    const uint4* yq = reinterpret_cast<const uint4*>(y);
-#pragma unroll
-                    for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
-                        const uint4 v = (q * 16 < l) ? yq[q] : make_uint4(0u, 0u, 0u, 0u);
-                        yr[4 * q] = v.x; yr[4 * q + 1] = v.y; yr[4 * q + 2] = v.z; yr[4 * q + 3] = v.w;
-                    }
-                }
-                bool same = true;
-                if (sgm.len > kExactLen) {
+                bool ok = false;
+                if (member < count) {
+                    gy = vals[start + member];
+                    y = V.y_arena + ybase + (int64_t)gy * stride_of(l);
                     if (REGY > 0) {
-                        const RegChars yc{yr, sgm.p - 1};
-                        for (int k = 0; k < sgm.len; ++k) same &= ((int)x[p - 1 + k] == yc[k]);
-                    } else {
-                        for (int k = 0; k < sgm.len; ++k) same &= (x[p - 1 + k] == y[sgm.p - 1 + k]);
+                        const uint4* yq = reinterpret_cast<const uint4*>(y);
+#pragma unroll
+                        for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
+                            const uint4 v = (q * 16 < l) ? yq[q] : make_uint4(0u, 0u, 0u, 0u);
+                            yr[4 * q] = v.x; yr[4 * q + 1] = v.y;
+                            yr[4 * q + 2] = v.z; yr[4 * q + 3] = v.w;
+                        }
+                    }
+                    ok = true;
+                    if (sgm.len > kExactLen) {
+                        // hashed key: compare the segment bytes before extension verification,
+                        // which skips the segment
+                        const LdsChars xs{xl8 + (p - 1)};
+                        if (REGY > 0) {
+                            const RegChars yc{yr, sgm.p - 1};
+                            for (int k = 0; k < sgm.len; ++k) ok &= (xs[k] == yc[k]);
+                        } else {
+                            for (int k = 0; k < sgm.len; ++k) ok &= (xs[k] == (int)y[sgm.p - 1 + k]);
+                        }
+                        my_miss += ok ? 0 : 1;
                     }
                 }
-                if (!same) {
-                    my_miss += 1;
-                } else {
-                    // left parts: x[1, p-1] vs y[1, p_i-1], t = i-1; right parts after the segment
-                    const int tl = i - 1, tr = tau + 1 - i;
-                    const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
-                    int c1 = 0, dl;
-                    if (REGY > 0)
-                        dl = vsp_seg_dispatch<GMAXW>(sgm.p - 1 <= p - 1, x, p - 1, RegChars{yr, 0},
-                                                     sgm.p - 1, tl, &c1);
-                    else
-                        dl = vsp_seg_dispatch<GMAXW>(sgm.p - 1 <= p - 1, x, p - 1, GlobalChars{y},
-                                                     sgm.p - 1, tl, &c1);
-                    my_cells += c1;
-                    if (dl <= tl) {
-                        int c2 = 0, dr;
+                // part 0: left parts, part 1: right parts (only where the left passed).  The
+                // part's band set-up is selected here, with the whole wave active.
+#pragma nounroll
+                for (int part = 0; part < 2; ++part) {
+                    BandLanes bd = part ? br : bl;
+                    asm volatile("" : "+v"(bd.r0), "+v"(bd.ek), "+v"(bd.w0));
+                    if (__builtin_amdgcn_ballot_w64(ok) == 0) break;
+                    if (ok) {
+                        const int xo = part ? rx : 0, xl = part ? n - rx : p - 1;
+                        const int yo = part ? ry : 0, yl = part ? l - ry : sgm.p - 1;
+                        const int tt = part ? tr : tl;
+                        int c = 0, d;
                         if (REGY > 0)
-                            dr = vsp_seg_dispatch<GMAXW>(l - ry <= n - rx, x + rx, n - rx,
-                                                         RegChars{yr, ry}, l - ry, tr, &c2);
+                            d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
+                                                        RegChars{yr, yo}, yl, tt, bd, &c);
                         else
-                            dr = vsp_seg_dispatch<GMAXW>(l - ry <= n - rx, x + rx, n - rx,
-                                                         GlobalChars{y + ry}, l - ry, tr, &c2);
-                        my_cells += c2;
-                        pass = dr <= tr;
+                            d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
+                                                        GlobalChars{y + yo}, yl, tt, bd, &c);
+                        my_cells += (uint64_t)c;
+                        ok = d <= tt;
                     }
                 }
+                const bool pass = ok;
+                acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
             }
-            acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
-            ++sidx;
-            if (sidx * 64u >= count) {
-                ++h;
-                sidx = 0;
-            }
+            ++h;
+            sidx = 0;
         }
     }
     acc.flush(V.out, V.out_cap, &V.counters[3]);

@@ -313,19 +313,36 @@ __device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int l
 
 // VerifyStringPair for a wave whose lanes share the probe string's part and the band geometry
 // (all lanes verify members of one inverted list against the same x): same results and cell
-// counts as vsp_global.  U points at the shared part (x's), V at the lane's own part (y's);
-// the part lengths lu, lv and t are wave-uniform.  YROWS tells which part gives the rows
-// (the shorter one; y's when equal), so the shared characters are either the row character
-// or the column window and live in scalar registers.
-// Characters of the lane's own part: from global memory, or from the lane's copy of its whole
-// string in registers (uniform position: the wave shares the part's offset and the row).
+// counts as vsp_global.  U reads the shared part (x's) at wave-uniform positions, V the lane's
+// own part (y's); the part lengths lu, lv and t are wave-uniform, so the band bounds, the
+// interior/edge decision of each row and the row's cell count are all scalar work, and the
+// lanes differ only in the cell values and in the row where they stop.  YROWS tells which part
+// gives the rows (the shorter one; y's when equal): with YROWS the column window holds shared
+// characters (scalar registers), otherwise the row character is the shared one.
+
+// Bytes of a string read at wave-uniform positions through the scalar cache (loads only).
+// A string's slot is 16-byte aligned and a multiple of 16 bytes long, so the aligned dword
+// around any byte of the string lies inside the slot.
+struct UniformChars {
+    const uint8_t* p;
+    __device__ inline int operator[](int k) const
+    {
+        const uintptr_t ad = (uintptr_t)(p + k);
+        const uint32_t w =
+            *(const __attribute__((address_space(4))) uint32_t*)(ad & ~(uintptr_t)3);
+        return (int)((w >> ((ad & 3u) * 8u)) & 0xffu);
+    }
+};
+
 struct GlobalChars {
     const uint8_t* p;
     __device__ inline int operator[](int k) const { return (int)p[k]; }
 };
 
+// The lane's whole string in registers, 4 bytes each (at most 64 bytes), read at a
+// wave-uniform position (the wave shares the part's offset and the row).
 struct RegChars {
-    const uint32_t* r;   // the string's bytes, 4 per register (at most 64 bytes)
+    const uint32_t* r;
     int off;             // part offset within the string (wave-uniform)
     __device__ inline int operator[](int k) const
     {
@@ -334,10 +351,60 @@ struct RegChars {
     }
 };
 
-template <int MAXW, bool YROWS, typename LaneChars>
-__device__ inline int vsp_seg(const uint8_t* U, int lu, LaneChars V, int lv, int t, int* cells)
+// Bytes of the probe string staged in the wave's LDS buffer, read at wave-uniform positions
+// (a broadcast read; no bank conflicts).
+struct LdsChars {
+    const __attribute__((address_space(3))) uint8_t* p;
+    __device__ inline int operator[](int k) const { return (int)p[k]; }
+};
+
+// The row loop exits on a wave vote, so the row index, the band bounds and the shared
+// characters stay wave-uniform, and every row runs the same unmasked recurrence:
+//  * cells left of column 0 start at BIG and only ever see BIG or larger inputs;
+//  * column 0 needs no special case: from M(0,0) = 0 the recurrence gives M(i,0) = i;
+//  * cells right of column nc are never an input of a cell inside the matrix, and their
+//    expected distance exceeds that of cell (i, nc), which is in the band whenever they are,
+//    so they change neither a row's stop test nor the result;
+//  * the band's outer neighbours (left of index 0, above index W-1) read as BIG.
+// Values are not saturated at t+1: min(v, t+1) commutes with the recurrence, so stop rows
+// and verdicts are those of the saturated form.  The expected distance M + |delta + a - k|
+// never decreases along a step of the recurrence, so once a row has no cell with expected
+// distance <= t no later row has one: a lane is live exactly while its current row passes,
+// and it stops at its first failing row.
+// EXACT: MAXW == t + 1, so only the last band index can lie outside the band (W >= MAXW - 1).
+// Row 0, the expected-distance offsets |kfin - k| and (rows from y) the first column window of
+// one part's band, one band index k per lane.  Computed while the whole wave is active: the
+// verification reads entry k back from lane k with readlane, which also reads lanes that are
+// inactive at that point.
+struct BandLanes {
+    int r0, ek, w0;
+};
+
+__device__ inline BandLanes band_lanes(LdsChars U, int lu, int lv, int t, int lane)
 {
-    const GlobalChars Ug{U};
+    const bool yrows = lv <= lu;
+    const int nr = yrows ? lv : lu;
+    const int nc = yrows ? lu : lv;
+    const int delta = nc - nr;                   // > t: the part fails without a DP
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    const int kfin = delta + a;
+    const int jl = lane - a;
+    BandLanes B;
+    B.r0 = ((unsigned)jl <= (unsigned)min(nc, b)) ? jl : (1 << 20);
+    B.ek = kfin - lane < 0 ? lane - kfin : kfin - lane;
+    B.w0 = (yrows && (unsigned)jl < (unsigned)nc) ? U[jl] : 256;
+    // define the three values here, with every lane active, so that they are not recomputed
+    // later inside a branch that only some lanes take
+    asm volatile("" : "+v"(B.r0), "+v"(B.ek), "+v"(B.w0));
+    return B;
+}
+
+template <int MAXW, bool EXACT, bool YROWS, typename LaneChars>
+__device__ inline int vsp_seg(LdsChars U, int lu, LaneChars V, int lv, int t, BandLanes BL,
+                              int* cells)
+{
+    static_assert(MAXW <= 64, "one band index per lane");
     const int nr = YROWS ? lv : lu;
     const int nc = YROWS ? lu : lv;
     const int delta = nc - nr;
@@ -346,82 +413,73 @@ __device__ inline int vsp_seg(const uint8_t* U, int lu, LaneChars V, int lv, int
     const int a = (t - delta) >> 1;
     const int b = (t + delta) >> 1;
     const int W = a + b + 1;
-    const int INF = t + 1;
+    const int kfin = delta + a;                  // band index of the last cell (nr, nc)
     constexpr int BIG = 1 << 20;
     int R[MAXW], w[MAXW], ek[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) {
-        const int j = k - a;
-        R[k] = (k < W && j >= 0 && j <= nc) ? (j < INF ? j : INF) : INF;
-        const int idx = k - a;
-        w[k] = ((unsigned)idx < (unsigned)nc) ? (YROWS ? Ug[idx] : V[idx]) : 256;
-        const int dd = delta + a - k;
-        ek[k] = dd < 0 ? -dd : dd;
-    }
-    int idx_in = MAXW - a;
-    int cin = ((unsigned)idx_in < (unsigned)nc) ? (YROWS ? Ug[idx_in] : V[idx_in]) : 256;
-    int ai = nr > 0 ? (YROWS ? V[0] : Ug[0]) : 256;
-    int ai_next = nr > 1 ? (YROWS ? V[1] : Ug[1]) : 256;
-    int ncell = 0;
-    int res = -1;
-    for (int i = 1; i <= nr; ++i) {
-        const int idx2 = idx_in + 1;
-        const int cin_next = ((unsigned)idx2 < (unsigned)nc) ? (YROWS ? Ug[idx2] : V[idx2]) : 256;
-        const int ai_next2 = (i + 1 < nr) ? (YROWS ? V[i + 1] : Ug[i + 1]) : 256;
-        const int j0 = i - a;
-        int left = INF;
-        int emin = BIG;
-        if (j0 >= 1 && j0 + W - 1 <= nc) {
-            // the whole band is inside the matrix (uniform test): no masking
-#pragma unroll
-            for (int k = 0; k < MAXW; ++k) {
-                if (k < W) {
-                    const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
-                    const int upk = (k + 1 < W) ? up : INF;
-                    const int d = (ai != w[k]) ? 1 : 0;
-                    const int v = min(min(upk, left) + 1, R[k] + d);
-                    emin = min(emin, v + ek[k]);
-                    R[k] = v;
-                    left = v;
-                }
-            }
+        R[k] = __builtin_amdgcn_readlane(BL.r0, k);
+        ek[k] = __builtin_amdgcn_readlane(BL.ek, k);
+        if (YROWS) {
+            w[k] = __builtin_amdgcn_readlane(BL.w0, k);
         } else {
+            const int idx = k - a;
+            w[k] = ((unsigned)idx < (unsigned)nc) ? V[idx] : 256;
+        }
+    }
+    int idx_in = MAXW - a;                       // column character entering after row 1
+    int ai_pre = (!YROWS && nr > 0) ? U[0] : 256;
+    int cum = 0;                                 // recurrence cells of rows 1..i (uniform)
+    int stop_cells = 0;
+    bool live = true;
+    for (int i = 1; i <= nr; ++i) {
+        // row character: the lane's own (registers) or the shared one, read a row ahead
+        int ai, ai_next = 256;
+        if (YROWS) {
+            ai = V[i - 1];
+        } else {
+            ai = ai_pre;
+            if (i < nr) ai_next = U[i];
+        }
+        int cin = 256;                           // column character entering after the row
+        if ((unsigned)idx_in < (unsigned)nc)
+            cin = YROWS ? __builtin_amdgcn_readfirstlane(U[idx_in]) : V[idx_in];
+        int left = BIG;
+        int e[MAXW];
 #pragma unroll
-            for (int k = 0; k < MAXW; ++k) {
-                const int j = j0 + k;
-                const bool valid = (k < W) && j >= 0 && j <= nc;
-                const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
-                const int upk = (k + 1 < W) ? up : INF;
-                const int d = (ai != w[k]) ? 1 : 0;
-                int v = min(min(upk, left) + 1, R[k] + d);
-                v = (j == 0) ? i : v;
-                v = valid ? v : INF;
-                emin = min(emin, valid ? v + ek[k] : BIG);
-                R[k] = v;
-                left = v;
-            }
+        for (int k = 0; k < MAXW; ++k) {
+            const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : BIG;
+            // min(up + 1, left + 1, diag + d) as min(up, left, diag - [match]) + 1
+            const int dg = R[k] - ((ai == w[k]) ? 1 : 0);
+            int v = min(min(up, left), dg) + 1;
+            if (!EXACT || k == MAXW - 1) v = (k < W) ? v : BIG;
+            e[k] = v + ek[k];
+            R[k] = v;
+            left = v;
         }
-        const int lo = max(1, j0), hi = min(nc, j0 + W - 1);
-        ncell += max(0, hi - lo + 1);
-        if (emin > t) {
-            res = t + 1;
-            break;
-        }
+        int emin = e[0];
+#pragma unroll
+        for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(e[k], e[k + 1]));
+        if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
+        const bool any = emin <= t;
+        const int j0 = i - a;
+        cum += max(0, min(nc, j0 + W - 1) - max(1, j0) + 1);
+        if (live && !any) stop_cells = cum;
+        live = any;
+        if (__builtin_amdgcn_ballot_w64(any) == 0) break;
 #pragma unroll
         for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
         w[MAXW - 1] = cin;
-        cin = cin_next;
-        idx_in = idx2;
-        ai = ai_next;
-        ai_next = ai_next2;
+        ++idx_in;
+        ai_pre = ai_next;
     }
-    *cells = ncell;
-    if (res >= 0) return res;
-    int out = INF;
+    *cells = live ? cum : stop_cells;
+    if (!live) return t + 1;
+    int out = BIG;
 #pragma unroll
     for (int k = 0; k < MAXW; ++k)
-        if (k == delta + a) out = R[k];
-    return min(out, INF);
+        if (k == kfin) out = R[k];
+    return min(out, t + 1);
 }
 
 }  // namespace pj
