@@ -196,6 +196,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-n", type=int, default=1_000_000)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip autotuning the launch parameters (built-in defaults)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (default: a fresh file in the temp directory)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -228,11 +232,24 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes x 3")
 
+    # autotuning (outside the timed region): launch parameters per (GPU, tau, length bucket),
+    # searched on this workload; the timed joins read them from the cache file
+    tuning = None
+    cache = None
+    if not args.no_tune and args.mode != P.MODE_PLAIN:
+        import tempfile
+        cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="pj_tune_"), "tune.txt")
+        tuning = {}
+        for t in taus:
+            r = P.pj_tune(col, t, tune_cache=cache)
+            tuning[str(t)] = r
+            log(f"tuned tau={t}: {r}")
+
     def step(collect):
         outs = []
         for t in taus:
             r = P.pj_self_join((chars, offs), t, mode=args.mode, outputs_on_device=True,
-                               stream=stream)
+                               stream=stream, tune_cache=cache)
             st = P.pj_last_stats()
             outs.append(r)
             if collect is not None:
@@ -317,6 +334,7 @@ def main():
             "share_of_verify_time": list_ms / max(verify_ms, 1e-9),
         },
         "kernel_source_sha": sha,
+        "tuning": tuning,
     }
     if not args.no_serve:
         line["serving"] = serving_bench(P, W, args.serve_n, args.serve_seconds, args.serve_slots)

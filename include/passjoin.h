@@ -147,6 +147,8 @@ typedef struct {
     int32_t slots;              /* device batches in flight at once, >= 1 */
     int32_t max_batch_queries;  /* queries merged into one device batch, >= 1 */
     int64_t mem_budget_bytes;   /* bound on the summed footprint estimates in flight; 0 = none */
+    const char* tune_cache;     /* autotune cache file read by the batches (see pj_tune); NULL =
+                                   none.  The string is copied by pj_server_start. */
 } pj_server_config;
 
 /* Timestamps (ms on the server's steady clock since pj_server_start) and admission data. */
@@ -159,7 +161,7 @@ typedef struct {
     int32_t slot;               /* slot that ran it */
 } pj_request_info;
 
-/* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0}. */
+/* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0, NULL}. */
 int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server** out);
 
 /* Submits a request: Q (host memory, copied) with one threshold per query in the index's
@@ -173,6 +175,32 @@ int pj_server_wait(pj_server* srv, int64_t request, pj_pairs* out, pj_request_in
 
 /* Stops admitting, finishes the work in flight and queued, then frees the server. */
 int pj_server_stop(pj_server* srv);
+
+/* Autotuning of the batched path's launch parameters.  None of them changes a result (the pairs
+ * and all counters of pj_stats stay the same); they decide how the candidates of Algorithm 1 are
+ * spread over the GPU: the persistent verification grid (waves per compute unit), the list
+ * segments (64 candidates each) a wave takes at a time, the candidate count from which an
+ * inverted list is verified a wave at a time instead of candidate by candidate, and the probe
+ * grid (blocks per compute unit). */
+typedef struct {
+    int32_t verify_waves_per_cu;   /* 8, 16, 32, 64 or 128 (default 32) */
+    int32_t seg_chunk;             /* 1, 2, 4, 8, 16 or 32 (default 4) */
+    int32_t big_list;              /* 16, 32, 64 or 128 (default 32) */
+    int32_t probe_blocks_per_cu;   /* 4, 8 or 16 (default 8) */
+    int32_t len_bucket;            /* key: bit length of the rounded mean string length */
+    int32_t trials;                /* settings measured */
+    double ms_default;             /* probe + verification kernel time, built-in defaults */
+    double ms_best;                /* the same for the chosen setting */
+} pj_tune_result;
+
+/* Searches the launch parameters for the self-join of S (host memory) at tau by coordinate
+ * descent, timing the probe and verification kernels (best of two runs per setting), and
+ * records the best setting under (this GPU's architecture, tau, length bucket of S's mean
+ * length).  The record is kept for the rest of the process; when opt->tune_cache names a file
+ * it is also merged into that file (plain text, one setting per line), which later calls with
+ * the same tune_cache read.  opt->inputs_on_device must be 0.  Each trial runs the full
+ * self-join, so the cost is about 35 joins of S.  Returns PJ_OK or a PJ_E* code. */
+int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_result* out);
 
 /* Releases pairs (host or device memory as recorded in on_device) and zeroes the struct. */
 void pj_pairs_free(pj_pairs* pairs);

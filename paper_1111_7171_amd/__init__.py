@@ -22,6 +22,7 @@ __all__ = [
     "PassJoinError", "load", "pj_self_join", "pj_join", "pj_build_index", "pj_query",
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
     "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX", "Server", "Index",
+    "pj_tune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,7 +68,14 @@ class PjStats(C.Structure):
 
 class PjServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_batch_queries", C.c_int32),
-                ("mem_budget_bytes", C.c_int64)]
+                ("mem_budget_bytes", C.c_int64), ("tune_cache", C.c_char_p)]
+
+
+class PjTuneResult(C.Structure):
+    _fields_ = [("verify_waves_per_cu", C.c_int32), ("seg_chunk", C.c_int32),
+                ("big_list", C.c_int32), ("probe_blocks_per_cu", C.c_int32),
+                ("len_bucket", C.c_int32), ("trials", C.c_int32),
+                ("ms_default", C.c_double), ("ms_best", C.c_double)]
 
 
 class PjRequestInfo(C.Structure):
@@ -118,6 +126,8 @@ def load():
         lib.pj_server_wait.restype = C.c_int
         lib.pj_server_stop.argtypes = [C.c_void_p]
         lib.pj_server_stop.restype = C.c_int
+        lib.pj_tune.argtypes = [sp, C.c_int32, op, C.POINTER(PjTuneResult)]
+        lib.pj_tune.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -267,6 +277,21 @@ def pj_join(R, S, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = 
     return _take_pairs(raw, outputs_on_device)
 
 
+def pj_tune(strings, tau: int, *, tune_cache: str | None = None, mem_budget: int = 0,
+            stream=None) -> dict:
+    """Autotunes the batched path's launch parameters on the self-join of `strings` (host
+    memory) at tau; the setting is kept for this process and, with tune_cache, merged into that
+    file.  Returns the chosen setting and its timing."""
+    lib = load()
+    s = _Marshalled(strings)
+    if s.on_device:
+        raise PassJoinError(PJ_EINVAL, "pj_tune takes host strings")
+    o = _options(False, False, MODE_BATCHED, mem_budget, stream, tune_cache)
+    r = PjTuneResult()
+    _check(lib.pj_tune(C.byref(s.s), int(tau), C.byref(o), C.byref(r)))
+    return {k: getattr(r, k) for k, _ in PjTuneResult._fields_}
+
+
 class Index:
     """A device-resident index (pj_build_index); released by free() or garbage collection."""
 
@@ -329,9 +354,10 @@ class Server:
     wait(id) returns the request's (q, s) pairs and its timing info."""
 
     def __init__(self, index: Index, slots: int = 2, max_batch_queries: int = 256,
-                 mem_budget: int = 0):
+                 mem_budget: int = 0, tune_cache: str | None = None):
         self.index = index          # keeps the index alive while the server runs
-        cfg = PjServerConfig(slots, max_batch_queries, int(mem_budget))
+        cfg = PjServerConfig(slots, max_batch_queries, int(mem_budget),
+                             tune_cache.encode() if tune_cache else None)
         h = C.c_void_p()
         _check(load().pj_server_start(index.handle, C.byref(cfg), C.byref(h)))
         self.handle = h

@@ -889,8 +889,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
 // kBigList candidates; smaller lists go through k_verify_batched.
 // ------------------------------------------------------------------------------------------
 
-constexpr int kSegChunk = 4;    // list segments (of 64 members) per wave chunk
-
 __global__ __launch_bounds__(kBlock) void k_seg_counts(const Hit* __restrict__ hits, uint64_t nbig,
                                                        uint32_t* __restrict__ segs)
 {
@@ -898,14 +896,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_counts(const Hit* __restrict__ h
     if (k < nbig) segs[k] = (hits[k].count + 63u) >> 6;
 }
 
-// first[ch] = the list holding segment ch * kSegChunk (largest h with segp[h] <= it)
+// first[ch] = the list holding segment ch * chunk (largest h with segp[h] <= it)
 __global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __restrict__ segp,
                                                              uint64_t nbig, uint64_t nchunks,
+                                                             uint32_t chunk,
                                                              uint32_t* __restrict__ first)
 {
     const uint64_t ch = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (ch >= nchunks) return;
-    const uint64_t s0 = ch * kSegChunk;
+    const uint64_t s0 = ch * chunk;
     uint64_t a = 0, b = nbig - 1;
     while (a < b) {
         const uint64_t m = (a + b + 1) >> 1;
@@ -954,7 +953,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         const uint32_t* __restrict__ segp,
                                                         uint64_t nbig, uint64_t nseg,
                                                         const uint32_t* __restrict__ first,
-                                                        uint64_t nchunks)
+                                                        uint64_t nchunks, uint32_t seg_chunk)
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
     __shared__ uint32_t s_x[kWaves][(kLenMax + 4) / 4];   // the current probe string
@@ -969,8 +968,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
     const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
     uint64_t my_cells = 0, my_miss = 0;
     for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
-        uint64_t sg_i = ch * kSegChunk;
-        const uint64_t sg_end = (sg_i + kSegChunk < nseg) ? sg_i + kSegChunk : nseg;
+        uint64_t sg_i = ch * seg_chunk;
+        const uint64_t sg_end = (sg_i + seg_chunk < nseg) ? sg_i + seg_chunk : nseg;
         uint32_t h = uniform_load(first + ch);
         uint32_t sidx = (uint32_t)(sg_i - uniform_load(segp + h));
         while (sg_i < sg_end) {
@@ -1338,17 +1337,17 @@ hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev,
 template <int W>
 static void verify_segs_w(const VerifyParams& V, const Hit* big, const uint32_t* segp,
                           uint64_t nbig, uint64_t nseg, const uint32_t* first, uint64_t nchunks,
-                          int grid, hipStream_t s)
+                          uint32_t chunk, int grid, hipStream_t s)
 {
     if (V.y_maxlen <= 64)
         hipLaunchKernelGGL((k_verify_segs<W, 64>), dim3(grid), dim3(kBlock), 0, s, V,
-                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks);
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
     else
         hipLaunchKernelGGL((k_verify_segs<W, 0>), dim3(grid), dim3(kBlock), 0, s, V,
-                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks);
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
 }
 
-uint64_t seg_chunks(uint64_t nseg) { return (nseg + kSegChunk - 1) / kSegChunk; }
+uint64_t seg_chunks(uint64_t nseg, int chunk) { return (nseg + (uint64_t)chunk - 1) / (uint64_t)chunk; }
 
 hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipStream_t s)
 {
@@ -1358,18 +1357,20 @@ hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipS
 }
 
 hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint32_t* segp,
-                              uint64_t nbig, uint64_t nseg, uint32_t* first, int grid,
+                              uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk, int grid,
                               hipStream_t s)
 {
     if (nbig == 0 || nseg == 0) return hipSuccess;
-    const uint64_t nchunks = seg_chunks(nseg);
+    if (chunk < 1 || grid < 1) return hipErrorInvalidValue;
+    const uint64_t nchunks = seg_chunks(nseg, chunk);
+    const uint32_t c = (uint32_t)chunk;
     hipLaunchKernelGGL(k_seg_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, segp,
-                       nbig, nchunks, first);
+                       nbig, nchunks, c, first);
     const int w = V.tau + 1;
-    if (w <= 9) verify_segs_w<9>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
-    else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
-    else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
-    else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, grid, s);
+    if (w <= 9) verify_segs_w<9>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
+    else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
+    else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
+    else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
     return hipGetLastError();
 }
 

@@ -25,7 +25,6 @@
 namespace pj {
 
 // Inverted lists with at least this many candidates are verified a 64-member segment per wave.
-constexpr uint32_t kBigList = 32;
 // Below this many candidates the batched path verifies the hits in probe order, in one launch.
 constexpr uint64_t kBucketMinCandidates = 1ull << 20;
 
@@ -444,7 +443,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.hits = J.hits; pp.hit_cap = hit_cap;
         pp.counters = J.counters;
         int k0 = tm.mark();
-        hip_check(launch_probe(pp, device_cus() * 8, st), "probe");
+        hip_check(launch_probe(pp, device_cus() * J.tp.probe_blocks_per_cu, st), "probe");
         int k1 = tm.mark();
         J.kernel_marks.push_back({k0, k1, 0});
     }
@@ -464,7 +463,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                                        (unsigned long long)J.nhits, (unsigned long long)hit_cap);
 
     const bool batched = J.mode != PJ_MODE_PLAIN;
-    // batched: hits bucketed into [lists with < kBigList candidates | the others], each part
+    // batched: hits bucketed into [lists with < big_list candidates | the others], each part
     // in slot order; small lists are verified candidate by candidate, big ones a 64-member
     // segment per wave
     uint64_t nsmall = J.nhits, nbig = 0, ncand_small = J.ncand, nseg = 0;
@@ -476,8 +475,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         uint32_t* sc = (uint32_t*)W.get("join.slotcnt", 256 * sizeof(uint32_t));
         hip_check(hipMemsetAsync(sc, 0, 256 * sizeof(uint32_t), st), "memset");
         Hit* sorted = (Hit*)W.get("join.hits2", sizeof(Hit) * (size_t)J.nhits);
-        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, kBigList, sc, sc + 128, sorted,
-                                     st), "slot_bucket");
+        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, (uint32_t)J.tp.big_list, sc,
+                                     sc + 128, sorted, st), "slot_bucket");
         J.hits = sorted;
         uint32_t hc[128];
         hip_check(hipMemcpyAsync(hc, sc, sizeof hc, hipMemcpyDeviceToHost, st), "bucket counts");
@@ -543,18 +542,21 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     const uint64_t nchunks = batched_chunks(ncand_small);
                     uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
                     // persistent: enough waves to fill the chip, each walking its chunks
-                    const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
+                    const uint64_t waves = std::min<uint64_t>(
+                        nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
                     hip_check(launch_verify_batched(vp, first, (int)((waves + 3) / 4), st),
                               "verify_batched");
                     stats.verify_launches += 1;
                 }
                 if (nseg > 0) {
-                    const uint64_t nchunks = seg_chunks(nseg);
+                    const uint64_t nchunks = seg_chunks(nseg, J.tp.seg_chunk);
                     uint32_t* first = (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)nchunks);
-                    const uint64_t waves = std::min<uint64_t>(nchunks, (uint64_t)device_cus() * 32);
+                    const uint64_t waves = std::min<uint64_t>(
+                        nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
                     const int s0 = tm.mark();
                     hip_check(launch_verify_segs(vp, J.hits + nsmall, segp, nbig, nseg, first,
-                                                 (int)((waves + 3) / 4), st), "verify_segs");
+                                                 J.tp.seg_chunk, (int)((waves + 3) / 4), st),
+                              "verify_segs");
                     const int s1 = tm.mark();
                     J.kernel_marks.push_back({s0, s1, 2});
                     stats.verify_launches += 1;
@@ -717,8 +719,17 @@ static int guarded(pj_pairs* out, F&& f)
     }
 }
 
+static double mean_length(const DevSet& D)
+{
+    if (D.n == 0) return 0.0;
+    double sum = 0.0;
+    for (int l = std::max(D.lmin, 0); l <= D.lmax; ++l)
+        sum += (double)l * (double)(D.h_lenstart[l + 1] - D.h_lenstart[l]);
+    return sum / (double)D.n;
+}
+
 static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
-                      pj_pairs* out, bool self)
+                      pj_pairs* out, bool self, const TuneParams* force = nullptr)
 {
     if (!out) throw Error(PJ_EINVAL, "null output");
     zero_pairs(out);
@@ -749,6 +760,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     t_stats.index_entries = X.entries;
     JoinScratch J;
     J.mode = opt ? opt->mode : PJ_MODE_AUTO;
+    J.tp = force ? *force : tune_lookup(opt ? opt->tune_cache : nullptr, tau, mean_length(P));
     ProbeSpec spec;
     spec.self = self;
     spec.tau = tau;
@@ -765,6 +777,12 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     t_stats.ms_output = tm.ms(e3, e4);
     t_stats.ms_total = std::chrono::duration<double, std::milli>(
                            std::chrono::steady_clock::now() - t0).count();
+}
+
+int self_join_with(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out,
+                   const TuneParams* force)
+{
+    return guarded(out, [&] { join_impl(nullptr, S, tau, opt, out, true, force); });
 }
 
 }  // namespace pj

@@ -62,8 +62,23 @@ struct Timer {
     double ms(int a, int b);
 };
 
+// Launch parameters of the batched path that do not change results (chosen by the autotuner,
+// pj_tune.cpp; these are the built-in defaults).
+struct TuneParams {
+    int verify_waves_per_cu = 32;   // persistent grid of the verification kernels
+    int seg_chunk = 4;              // list segments (64 members each) per wave chunk
+    int big_list = 32;              // lists with at least this many candidates: list-segment kernel
+    int probe_blocks_per_cu = 8;    // grid of the probe kernel
+};
+
+bool tune_params_valid(const TuneParams& p);
+// Parameters for a call: the autotune table entry for (this GPU, tau, length bucket of the
+// probe set's mean length), read from the cache file when one is named, else the defaults.
+TuneParams tune_lookup(const char* cache, int tau, double mean_len);
+
 struct JoinScratch {
     int mode = PJ_MODE_AUTO;
+    TuneParams tp;
     unsigned long long* counters = nullptr;
     Hit* hits = nullptr;
     unsigned long long* prefix = nullptr;
@@ -100,10 +115,15 @@ void emit_output(const int32_t* da, const int32_t* db, uint64_t M, bool to_devic
 
 void validate_host_strings(const pj_strings* S, const char* what);
 void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* taus,
-                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st);
+                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st,
+                     const char* tune_cache);
 int64_t query_footprint(const pj_index* idx, int n, int tau);
 void index_taus(const pj_index* idx, int* lo, int* hi);
 void release_thread_workspace();
+
+// pj_self_join with the launch parameters given (the autotuner's trial runs)
+int self_join_with(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out,
+                   const TuneParams* force);
 
 extern thread_local std::string t_last_error;
 extern thread_local pj_stats t_stats;

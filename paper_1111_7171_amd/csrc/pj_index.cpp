@@ -73,7 +73,8 @@ int64_t query_selections(const pj_index* idx, int n, int tau);
 // index in one device pass: probe, verify and the short-string path take each query's own
 // threshold and per-tau index.  Appends (q << 32 | s) sorted by (q, s).
 void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* taus,
-                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st)
+                     std::vector<uint64_t>& pairs, pj_stats& stats, hipStream_t st,
+                     const char* tune_cache)
 {
     if (Q->n == 0) return;
     Workspace& W = thread_workspace();
@@ -100,6 +101,8 @@ void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* ta
     spec.has_entries = idx->has_entries;
     JoinScratch J;
     J.mode = PJ_MODE_BATCHED;
+    J.tp = tune_lookup(tune_cache, tmax, Q->n ? (double)(Q->offsets[Q->n] - Q->offsets[0]) / (double)Q->n
+                                             : 0.0);
     Timer tm(st);
     run_candidates(P, idx->S, spec, J, stats, tm, st);
     int32_t *da = nullptr, *db = nullptr;
@@ -237,7 +240,7 @@ int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, cons
         to_host(Q, on_dev, H);
         if (on_dev) validate_host_strings(&H.view, "Q");
         std::vector<uint64_t> pairs;
-        run_query_batch(idx, &H.view, taus, pairs, t_stats, st);
+        run_query_batch(idx, &H.view, taus, pairs, t_stats, st, opt ? opt->tune_cache : nullptr);
         uint64_t M = pairs.size();
         std::vector<int32_t> a(M), b(M);
         for (uint64_t k = 0; k < M; ++k) {

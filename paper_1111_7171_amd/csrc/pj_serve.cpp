@@ -57,6 +57,7 @@ struct Slot {
 struct pj_server {
     const pj_index* idx = nullptr;
     pj_server_config cfg{};
+    std::string tune_cache;              // owned copy of cfg.tune_cache
     int tau_min = 0, tau_max = -1;
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
@@ -103,7 +104,8 @@ static void run_batch(pj_server* S, Slot& slot, Batch& B)
     int status = PJ_OK;
     std::string err;
     try {
-        run_query_batch(S->idx, &Q, taus.data(), pairs, st, slot.stream);
+        run_query_batch(S->idx, &Q, taus.data(), pairs, st, slot.stream,
+                        S->tune_cache.empty() ? nullptr : S->tune_cache.c_str());
     } catch (const Error& e) {
         status = e.code;
         err = e.msg;
@@ -206,7 +208,7 @@ int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server*
         if (!out) throw Error(PJ_EINVAL, "null output");
         *out = nullptr;
         if (!idx) throw Error(PJ_EINVAL, "null index");
-        pj_server_config c{2, 256, 0};
+        pj_server_config c{2, 256, 0, nullptr};
         if (cfg) c = *cfg;
         if (c.slots < 1 || c.slots > 64) throw Error(PJ_EINVAL, "slots must be in [1, 64]");
         if (c.max_batch_queries < 1) throw Error(PJ_EINVAL, "max_batch_queries must be >= 1");
@@ -214,6 +216,8 @@ int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server*
         std::unique_ptr<pj_server> S(new pj_server());
         S->idx = idx;
         S->cfg = c;
+        if (c.tune_cache) S->tune_cache = c.tune_cache;
+        S->cfg.tune_cache = nullptr;
         index_taus(idx, &S->tau_min, &S->tau_max);
         S->t0 = std::chrono::steady_clock::now();
         hip_check(hipGetDevice(&S->device), "hipGetDevice");

@@ -69,3 +69,18 @@ def test_null_arguments_rejected():
     lib.pj_index_free(None)
     lib.pj_pairs_free(None)
     lib.pj_pairs_free(C.byref(raw))
+
+
+def test_tune_rejects_invalid_arguments_on_host():
+    lib = P.load()
+    ok = (np.frombuffer(b"abcabc", np.uint8), np.array([0, 3, 6], np.int32))
+    assert _err(P.pj_tune, ok, -1) == P.PJ_EINVAL
+    assert _err(P.pj_tune, ok, 64) == P.PJ_EINVAL
+    assert _err(P.pj_tune, (ok[0], np.array([0, 4, 3], np.int32)), 1) == P.PJ_EINVAL
+    s = P.PjStrings(0, None, None)
+    assert lib.pj_tune(C.byref(s), 1, None, None) == P.PJ_EINVAL
+    o = P.PjOptions()
+    o.inputs_on_device = 1
+    r = P.PjTuneResult()
+    assert lib.pj_tune(C.byref(s), 1, C.byref(o), C.byref(r)) == P.PJ_EINVAL
+    assert "host" in P.pj_last_error()
