@@ -183,8 +183,8 @@ int pj_server_stop(pj_server* srv);
  * inverted list is verified a wave at a time instead of candidate by candidate, and the probe
  * grid (blocks per compute unit). */
 typedef struct {
-    int32_t verify_waves_per_cu;   /* 8, 16, 32, 64 or 128 (default 32) */
-    int32_t seg_chunk;             /* 1, 2, 4, 8, 16 or 32 (default 4) */
+    int32_t verify_waves_per_cu;   /* 8, 16, 32, 64, 128 or 256 (default 32) */
+    int32_t seg_chunk;             /* 1, 2, 4, 8, 16, 32, 64 or 128 (default 4) */
     int32_t big_list;              /* 16, 32, 64 or 128 (default 32) */
     int32_t probe_blocks_per_cu;   /* 4, 8 or 16 (default 8) */
     int32_t len_bucket;            /* key: bit length of the rounded mean string length */
@@ -199,7 +199,7 @@ typedef struct {
  * length).  The record is kept for the rest of the process; when opt->tune_cache names a file
  * it is also merged into that file (plain text, one setting per line), which later calls with
  * the same tune_cache read.  opt->inputs_on_device must be 0.  Each trial runs the full
- * self-join, so the cost is about 35 joins of S.  Returns PJ_OK or a PJ_E* code. */
+ * self-join, so the cost is about 40 joins of S.  Returns PJ_OK or a PJ_E* code. */
 int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_result* out);
 
 /* Releases pairs (host or device memory as recorded in on_device) and zeroes the struct. */

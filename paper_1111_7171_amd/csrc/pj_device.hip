@@ -957,9 +957,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
     __shared__ uint32_t s_x[kWaves][(kLenMax + 4) / 4];   // the current probe string
+    __shared__ uint32_t s_q[kWaves][128];                 // left-part survivors (gy)
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     uint32_t* sx = s_x[threadIdx.x >> 6];
+    uint32_t* sq = s_q[threadIdx.x >> 6];
     const __attribute__((address_space(3))) uint8_t* xl8 =
         (const __attribute__((address_space(3))) uint8_t*)(sx);
     // wave id as a scalar, so that everything derived from it is known to be wave-uniform
@@ -1016,64 +1018,91 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             const uint64_t left_in_chunk = sg_end - sg_i;
             const uint32_t s_stop = (uint64_t)(hsegs - sidx) < left_in_chunk
                                         ? hsegs : sidx + (uint32_t)left_in_chunk;
-            for (; sidx < s_stop; ++sidx, ++sg_i) {
+            // REGY > 0: the whole indexed string (at most REGY bytes, 16-byte aligned slot) goes
+            // to registers with wide loads and is read at wave-uniform offsets
+            auto load_y = [&](uint32_t g, uint32_t* yr) -> const uint8_t* {
+                const uint8_t* y = V.y_arena + ybase + (int64_t)g * stride_of(l);
+                if (REGY > 0) {
+                    const uint4* yq = reinterpret_cast<const uint4*>(y);
+#pragma unroll
+                    for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
+                        const uint4 v = (q * 16 < l) ? yq[q] : make_uint4(0u, 0u, 0u, 0u);
+                        yr[4 * q] = v.x; yr[4 * q + 1] = v.y;
+                        yr[4 * q + 2] = v.z; yr[4 * q + 3] = v.w;
+                    }
+                }
+                return y;
+            };
+            // Two phases per hit: the left parts of each 64-member segment, then the right parts
+            // of the survivors, taken 64 at a time from a wave-private queue, so that a wave's
+            // right-part rows are not spent on lanes whose left part already failed.  Each
+            // iteration runs one band DP: a left step (next segment) or a right batch (64 queued
+            // survivors, or the rest once the segments are done).
+            uint32_t qn = 0;    // queued survivors (wave-uniform)
+            for (;;) {
+                const bool right = qn >= 64 || (sidx >= s_stop && qn > 0);
+                if (!right && sidx >= s_stop) break;
+                const uint32_t k = right ? (qn < 64 ? qn : 64) : 0;
+                if (right) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                // the part's band set-up, selected with the whole wave active
+                BandLanes bd = right ? br : bl;
+                asm volatile("" : "+v"(bd.r0), "+v"(bd.ek), "+v"(bd.w0));
                 const uint32_t member = sidx * 64u + (uint32_t)lane;
                 uint32_t gy = 0;
-                const uint8_t* y = V.y_arena;
-                // REGY > 0: the whole indexed string (at most REGY bytes, 16-byte aligned slot)
-                // goes to registers with wide loads and is read at wave-uniform offsets
                 uint32_t yr[REGY > 0 ? REGY / 4 : 1];
-                bool ok = false;
-                if (member < count) {
-                    gy = vals[start + member];
-                    y = V.y_arena + ybase + (int64_t)gy * stride_of(l);
-                    if (REGY > 0) {
-                        const uint4* yq = reinterpret_cast<const uint4*>(y);
-#pragma unroll
-                        for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
-                            const uint4 v = (q * 16 < l) ? yq[q] : make_uint4(0u, 0u, 0u, 0u);
-                            yr[4 * q] = v.x; yr[4 * q + 1] = v.y;
-                            yr[4 * q + 2] = v.z; yr[4 * q + 3] = v.w;
-                        }
-                    }
-                    ok = true;
-                    if (sgm.len > kExactLen) {
+                const uint8_t* y = V.y_arena;
+                bool ok = right ? (uint32_t)lane < k : member < count;
+                if (ok) {
+                    gy = right ? sq[lane] : vals[start + member];
+                    y = load_y(gy, yr);
+                    if (!right && sgm.len > kExactLen) {
                         // hashed key: compare the segment bytes before extension verification,
                         // which skips the segment
                         const LdsChars xs{xl8 + (p - 1)};
                         if (REGY > 0) {
                             const RegChars yc{yr, sgm.p - 1};
-                            for (int k = 0; k < sgm.len; ++k) ok &= (xs[k] == yc[k]);
+                            for (int q = 0; q < sgm.len; ++q) ok &= (xs[q] == yc[q]);
                         } else {
-                            for (int k = 0; k < sgm.len; ++k) ok &= (xs[k] == (int)y[sgm.p - 1 + k]);
+                            for (int q = 0; q < sgm.len; ++q) ok &= (xs[q] == (int)y[sgm.p - 1 + q]);
                         }
                         my_miss += ok ? 0 : 1;
                     }
                 }
-                // part 0: left parts, part 1: right parts (only where the left passed).  The
-                // part's band set-up is selected here, with the whole wave active.
-#pragma nounroll
-                for (int part = 0; part < 2; ++part) {
-                    BandLanes bd = part ? br : bl;
-                    asm volatile("" : "+v"(bd.r0), "+v"(bd.ek), "+v"(bd.w0));
-                    if (__builtin_amdgcn_ballot_w64(ok) == 0) break;
-                    if (ok) {
-                        const int xo = part ? rx : 0, xl = part ? n - rx : p - 1;
-                        const int yo = part ? ry : 0, yl = part ? l - ry : sgm.p - 1;
-                        const int tt = part ? tr : tl;
-                        int c = 0, d;
-                        if (REGY > 0)
-                            d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
-                                                        RegChars{yr, yo}, yl, tt, bd, &c);
-                        else
-                            d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
-                                                        GlobalChars{y + yo}, yl, tt, bd, &c);
-                        my_cells += (uint64_t)c;
-                        ok = d <= tt;
-                    }
+                if (ok) {
+                    const int xo = right ? rx : 0, xl = right ? n - rx : p - 1;
+                    const int yo = right ? ry : 0, yl = right ? l - ry : sgm.p - 1;
+                    const int tt = right ? tr : tl;
+                    int c = 0, d;
+                    if (REGY > 0)
+                        d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
+                                                    RegChars{yr, yo}, yl, tt, bd, &c);
+                    else
+                        d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
+                                                    GlobalChars{y + yo}, yl, tt, bd, &c);
+                    my_cells += (uint64_t)c;
+                    ok = d <= tt;
                 }
-                const bool pass = ok;
-                acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
+                if (right) {
+                    acc.push(ok, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
+                    const uint32_t rest = qn - k;
+                    uint32_t v = 0;
+                    if ((uint32_t)lane < rest) v = sq[64 + lane];
+                    if ((uint32_t)lane < rest) sq[lane] = v;
+                    qn = rest;
+                } else {
+                    const uint64_t surv = __builtin_amdgcn_ballot_w64(ok);
+                    if (ok)
+                        sq[qn + __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(surv >> 32),
+                                    __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] = gy;
+                    qn += (uint32_t)__builtin_popcountll(surv);
+                    ++sidx;
+                    ++sg_i;
+                }
             }
             ++h;
             sidx = 0;

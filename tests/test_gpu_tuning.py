@@ -43,8 +43,8 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     cache = str(tmp_path / "tune.txt")
     _say("pj_tune cfg2 n=20000 tau=3")
     r = P.pj_tune(col, 3, tune_cache=cache)
-    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128)
-    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32)
+    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128, 256)
+    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128)
     assert r["big_list"] in (16, 32, 64, 128)
     assert r["probe_blocks_per_cu"] in (4, 8, 16)
     assert r["len_bucket"] == _len_bucket(col)
@@ -67,7 +67,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert sorted(t for _, t, _, _, _ in _read_cache(cache)) == [2, 3]
 
 
-@pytest.mark.parametrize("params", [(8, 1, 16, 4), (128, 32, 128, 16), (16, 2, 64, 8)])
+@pytest.mark.parametrize("params", [(8, 1, 16, 4), (256, 128, 128, 16), (16, 2, 64, 8)])
 def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     # the list-segment kernel at these sizes needs the slot bucketing forced on
     monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
