@@ -149,6 +149,9 @@ typedef struct {
     int64_t mem_budget_bytes;   /* bound on the summed footprint estimates in flight; 0 = none */
     const char* tune_cache;     /* autotune cache file read by the batches (see pj_tune); NULL =
                                    none.  The string is copied by pj_server_start. */
+    int32_t eager;              /* 0: each slot replays one captured hipGraph of the device phases
+                                   per batch (batches that exceed its fixed capacities run
+                                   uncaptured); 1: every batch runs uncaptured */
 } pj_server_config;
 
 /* Timestamps (ms on the server's steady clock since pj_server_start) and admission data. */
@@ -161,7 +164,7 @@ typedef struct {
     int32_t slot;               /* slot that ran it */
 } pj_request_info;
 
-/* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0, NULL}. */
+/* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0, NULL, 0}. */
 int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server** out);
 
 /* Submits a request: Q (host memory, copied) with one threshold per query in the index's

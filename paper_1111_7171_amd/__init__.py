@@ -68,7 +68,8 @@ class PjStats(C.Structure):
 
 class PjServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_batch_queries", C.c_int32),
-                ("mem_budget_bytes", C.c_int64), ("tune_cache", C.c_char_p)]
+                ("mem_budget_bytes", C.c_int64), ("tune_cache", C.c_char_p),
+                ("eager", C.c_int32)]
 
 
 class PjTuneResult(C.Structure):
@@ -354,10 +355,10 @@ class Server:
     wait(id) returns the request's (q, s) pairs and its timing info."""
 
     def __init__(self, index: Index, slots: int = 2, max_batch_queries: int = 256,
-                 mem_budget: int = 0, tune_cache: str | None = None):
+                 mem_budget: int = 0, tune_cache: str | None = None, eager: bool = False):
         self.index = index          # keeps the index alive while the server runs
         cfg = PjServerConfig(slots, max_batch_queries, int(mem_budget),
-                             tune_cache.encode() if tune_cache else None)
+                             tune_cache.encode() if tune_cache else None, 1 if eager else 0)
         h = C.c_void_p()
         _check(load().pj_server_start(index.handle, C.byref(cfg), C.byref(h)))
         self.handle = h

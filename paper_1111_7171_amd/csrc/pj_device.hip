@@ -478,13 +478,15 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
     const int lane = threadIdx.x & 63;
     WaveAppender<Hit, kAppendCap> app{s_hits[threadIdx.x >> 6], 0};
     const int T1 = P.tau + 1;
+    const uint64_t nthreads = P.nx_dev ? (uint64_t)*P.nx_dev * (uint64_t)P.nl * (uint64_t)T1
+                                       : P.threads;
     uint64_t my_sel = 0, my_cand = 0;
     // grid-stride over (probe string, length, slot) triples; the loop bound is block-uniform so
     // every lane takes part in the wave-level appends
-    for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock; t0 < P.threads;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock; t0 < nthreads;
          t0 += (uint64_t)gridDim.x * kBlock) {
         const uint64_t t = t0 + threadIdx.x;
-        bool valid = t < P.threads;
+        bool valid = t < nthreads;
         int n = 0, l = 0, i = 0, lo = 1, hi = 0, tau = P.tau;
         uint32_t gx = 0;
         Seg sg{1, 0};
@@ -803,16 +805,19 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
     uint64_t my_cells = 0, my_miss = 0;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
+    const uint64_t nhits = V.dev_counts ? V.dev_counts[0] : V.nhits;
+    const uint64_t ncand = V.dev_counts ? V.dev_counts[1] : V.ncand;
+    const uint64_t nch = V.dev_counts ? V.dev_counts[2] : nchunks;
+    for (uint64_t ch = wave; ch < nch; ch += nwaves) {
         const uint64_t c0 = ch * kWaveChunk;
-        const uint64_t cend = (c0 + kWaveChunk < V.ncand) ? c0 + kWaveChunk : V.ncand;
+        const uint64_t cend = (c0 + kWaveChunk < ncand) ? c0 + kWaveChunk : ncand;
         uint64_t h = first[ch];
         unsigned long long hstart = V.prefix[h];
         for (uint64_t g0 = c0; g0 < cend; g0 += 64) {
             // end offsets of hits h .. h + 63; a boundary at relative position r means the
             // candidates from r on belong to later hits
             const uint64_t hk = h + (uint64_t)lane;
-            const unsigned long long bk = (hk < V.nhits) ? V.prefix[hk + 1] : ~0ull;
+            const unsigned long long bk = (hk < nhits) ? V.prefix[hk + 1] : ~0ull;
             const uint64_t rel = bk - g0;                      // >= 1
             const uint64_t M = wave_or64(rel < 64 ? (1ull << rel) : 0ull);
             const int off = __popcll(M & le_mask);
@@ -1459,6 +1464,175 @@ hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self
     else if (w <= 17) short_w<17>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
     else if (w <= 33) short_w<33>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
     else short_w<64>(P, Y, tau, self, q_tau, y_first, cnt, out, out_cap, counters, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Captured query batches: the sizes of a batch live in device memory, so one instantiated graph
+// of these launches serves every batch of a serving slot.
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int n, unsigned long long v)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = v;
+}
+
+// One block: exclusive prefix of the hits' candidate counts, then the batch's sizes.  An
+// overflow (more hits than the buffer holds, or more wave chunks than the chunk table holds)
+// sets a flag and leaves nothing to verify; the host then runs the batch without the graph.
+__global__ __launch_bounds__(kBlock) void k_batch_prefix(const Hit* __restrict__ hits,
+                                                         const unsigned long long* __restrict__ counters,
+                                                         uint64_t hit_cap,
+                                                         unsigned long long* __restrict__ prefix,
+                                                         unsigned long long* __restrict__ bc,
+                                                         uint64_t chunk_cap)
+{
+    __shared__ unsigned long long s_w[kWaves];
+    uint64_t nh = counters[0];
+    unsigned long long flags = 0;
+    if (nh > hit_cap) {
+        flags |= 1;
+        nh = 0;
+    }
+    unsigned long long carry = 0;
+    for (uint64_t b = 0; b < nh; b += kBlock) {
+        const uint64_t k = b + threadIdx.x;
+        const unsigned long long v = k < nh ? (unsigned long long)hits[k].count : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan(v, s_w, &tot);
+        if (k < nh) prefix[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        prefix[nh] = carry;
+        uint64_t nch = (carry + kWaveChunk - 1) / kWaveChunk;
+        if (nch > chunk_cap) {
+            flags |= 2;
+            nch = 0;
+        }
+        bc[0] = nh;
+        bc[1] = (flags & 2) ? 0ull : carry;
+        bc[2] = nch;
+        bc[3] = flags;
+    }
+}
+
+// first[ch] for a captured batch (grid-stride; sizes from bc)
+__global__ __launch_bounds__(kBlock) void k_chunk_starts_dev(const unsigned long long* __restrict__ prefix,
+                                                             const unsigned long long* __restrict__ bc,
+                                                             uint32_t* __restrict__ first)
+{
+    const uint64_t nh = bc[0], nch = bc[2];
+    for (uint64_t ch = (uint64_t)blockIdx.x * kBlock + threadIdx.x; ch < nch;
+         ch += (uint64_t)gridDim.x * kBlock) {
+        const unsigned long long c0 = ch * kWaveChunk;
+        uint64_t a = 0, b = nh - 1;
+        while (a < b) {
+            const uint64_t m = (a + b + 1) >> 1;
+            if (prefix[m] <= c0) a = m; else b = m - 1;
+        }
+        first[ch] = (uint32_t)a;
+    }
+}
+
+// One block: the batch's accepted (gx, gy) become (query id << 32 | indexed id) keys, sorted in
+// LDS (bitonic), deduplicated and compacted in order.  More than kGraphSortCap accepted pairs,
+// or more than the accepted buffer held, sets a flag and outputs nothing.
+__global__ __launch_bounds__(kBlock) void k_batch_dedupe(const uint64_t* __restrict__ acc,
+                                                         const unsigned long long* __restrict__ counters,
+                                                         uint64_t acc_cap,
+                                                         const int32_t* __restrict__ xperm,
+                                                         const int32_t* __restrict__ yperm,
+                                                         unsigned long long* __restrict__ bc,
+                                                         uint64_t* __restrict__ out,
+                                                         uint32_t* __restrict__ out_n)
+{
+    __shared__ uint64_t s_k[kGraphSortCap];
+    __shared__ uint32_t s_w[kWaves];
+    const uint64_t m = counters[3];
+    if (m > acc_cap || m > (uint64_t)kGraphSortCap) {
+        if (threadIdx.x == 0) {
+            bc[3] |= (m > acc_cap ? 4ull : 0ull) | 8ull;
+            *out_n = 0;
+        }
+        return;
+    }
+    uint32_t N = 1;
+    while (N < (uint32_t)m) N <<= 1;
+    for (uint32_t k = threadIdx.x; k < N; k += kBlock) {
+        uint64_t key = ~0ull;
+        if (k < (uint32_t)m) {
+            const uint64_t v = acc[k];
+            const uint32_t a = (uint32_t)xperm[v >> 32];
+            const uint32_t b = (uint32_t)yperm[v & 0xffffffffu];
+            key = ((uint64_t)a << 32) | b;
+        }
+        s_k[k] = key;
+    }
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= N; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < N; i += kBlock) {
+                const uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = s_k[i], b = s_k[ixj];
+                    const bool up = (i & kk) == 0;
+                    if ((a > b) == up) {
+                        s_k[i] = b;
+                        s_k[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < N; base += kBlock) {
+        const uint32_t k = base + threadIdx.x;
+        const uint32_t f = (k < (uint32_t)m && (k == 0 || s_k[k] != s_k[k - 1])) ? 1u : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(f, s_w, &tot);
+        if (f) out[carry + ex] = s_k[k];
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *out_n = carry;
+}
+
+template <int W>
+static void graph_verify_short(const GraphBatch& G, hipStream_t s)
+{
+    verify_batched_w<W>(G.verify, G.first, 0, G.verify_grid, s);
+    if (G.y_count) {
+        const ProbeParams& P = G.probe;
+        const unsigned grid = G.y_count < 65536 ? G.y_count : 65536;
+        hipLaunchKernelGGL((k_short<W>), dim3(grid), dim3(kBlock), 0, s, P.x_arena, P.x_slen,
+                           P.x_lenstart, P.x_gbase, kLenMax, G.y_arena, G.y_slen, G.y_lenstart,
+                           G.y_gbase, G.y_first, G.y_count, P.tau, 0, P.q_tau, G.verify.out,
+                           G.verify.out_cap, G.verify.counters);
+    }
+}
+
+hipError_t launch_graph_batch(const GraphBatch& G, hipStream_t s)
+{
+    if (!G.probe.nx_dev || !G.verify.dev_counts || G.probe_grid < 1 || G.verify_grid < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, G.probe.counters, 8, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, G.bcounts, 4, 0ull);
+    hipLaunchKernelGGL(k_probe, dim3(G.probe_grid), dim3(kBlock), 0, s, G.probe,
+                       make_div(G.probe.tau + 1));
+    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(kBlock), 0, s, G.probe.hits,
+                       G.probe.counters, G.probe.hit_cap,
+                       const_cast<unsigned long long*>(G.verify.prefix), G.bcounts, G.chunk_cap);
+    hipLaunchKernelGGL(k_chunk_starts_dev, dim3(64), dim3(kBlock), 0, s, G.verify.prefix,
+                       G.bcounts, G.first);
+    const int w = G.verify.tau + 1;
+    if (w <= 9) graph_verify_short<9>(G, s);
+    else if (w <= 17) graph_verify_short<17>(G, s);
+    else if (w <= 33) graph_verify_short<33>(G, s);
+    else graph_verify_short<64>(G, s);
+    hipLaunchKernelGGL(k_batch_dedupe, dim3(1), dim3(kBlock), 0, s, G.verify.out,
+                       G.verify.counters, G.verify.out_cap, G.xperm, G.yperm, G.bcounts, G.out,
+                       G.out_n);
     return hipGetLastError();
 }
 

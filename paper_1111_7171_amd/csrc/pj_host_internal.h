@@ -119,6 +119,22 @@ void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* ta
                      const char* tune_cache);
 int64_t query_footprint(const pj_index* idx, int n, int tau);
 void index_taus(const pj_index* idx, int* lo, int* hi);
+const DevSet& index_set(const pj_index* idx);
+const IndexRef* index_refs(const pj_index* idx);
+bool index_has_entries(const pj_index* idx);
+int64_t query_selections(const pj_index* idx, int n, int tau);
+
+// A serving slot's captured query pipeline (pj_graph.cpp): fixed-capacity device buffers, one
+// instantiated hipGraph of the device phases, pinned staging for the batch and its result.
+struct GraphPlan;
+GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t st,
+                             const char* tune_cache);
+void graph_plan_destroy(GraphPlan* g);
+// Runs one batch through the graph; false when the batch does not fit the plan's capacities or
+// a device-side capacity overflowed (the caller then runs it with run_query_batch).  pairs get
+// (query << 32 | indexed id), sorted.
+bool graph_plan_run(GraphPlan* g, const pj_strings* Q, const int32_t* taus,
+                    std::vector<uint64_t>& pairs, pj_stats& stats);
 void release_thread_workspace();
 
 // pj_self_join with the launch parameters given (the autotuner's trial runs)

@@ -32,6 +32,8 @@ namespace pj {
 void validate_host_strings(const pj_strings* S, const char* what);
 
 const DevSet& index_set(const pj_index* idx) { return idx->S; }
+const IndexRef* index_refs(const pj_index* idx) { return idx->refs; }
+bool index_has_entries(const pj_index* idx) { return idx->has_entries; }
 const DevIndex& index_for(const pj_index* idx, int tau) { return idx->X[tau - idx->tau_min]; }
 void index_taus(const pj_index* idx, int* lo, int* hi)
 {

@@ -91,6 +91,8 @@ struct ProbeParams {
     // output
     Hit* hits; uint64_t hit_cap;
     unsigned long long* counters;   // [0] hits, [1] candidates, [2] selected
+    // device-resident probe count (captured batches): threads = *nx_dev * nl * (tau + 1)
+    const uint32_t* nx_dev;
 };
 
 struct VerifyParams {
@@ -106,6 +108,9 @@ struct VerifyParams {
     const IndexRef* refs;                                 // [kTauMax + 1] when q_tau is set
     uint64_t* out; uint64_t out_cap;                      // accepted (gx << 32 | gy)
     unsigned long long* counters;    // [3] accepted, [4] cells, [5] guard misses, [7] list-segment cells
+    // device-resident sizes (captured batches): [0] hits, [1] candidates, [2] wave chunks;
+    // when set they replace nhits, ncand and the launch's chunk count
+    const unsigned long long* dev_counts;
 };
 
 // ---- launchers (pj_device.hip) ----
@@ -143,6 +148,28 @@ hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint3
 uint64_t seg_chunks(uint64_t nseg, int chunk);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
 uint64_t batched_chunks(uint64_t ncand);
+// A captured query batch: every size is read from device memory, so one instantiated graph
+// serves every batch.  counters: [0] hits [1] candidates [2] selected [3] accepted [4] cells
+// [5] guard misses [6] side pairs [7] unused; bcounts: [0] hits [1] candidates [2] wave chunks
+// [3] overflow flags (1 hits, 2 chunks, 4 accepted, 8 sort); out: the batch's sorted distinct
+// (query id << 32 | indexed id) pairs, out_n their number.
+struct GraphBatch {
+    ProbeParams probe;          // nx_dev set; hits/hit_cap/counters set
+    int probe_grid;
+    VerifyParams verify;        // dev_counts = bcounts; prefix/out/out_cap/counters set
+    int verify_grid;
+    unsigned long long* bcounts;
+    uint32_t* first; uint64_t chunk_cap;
+    // short side path (indexed strings shorter than tau_max + 1), y_count == 0: none
+    uint32_t y_first, y_count;
+    const uint8_t* y_arena; const uint16_t* y_slen; const int32_t* y_lenstart;
+    const int64_t* y_gbase;
+    // output
+    const int32_t* xperm; const int32_t* yperm;
+    uint64_t* out; uint32_t* out_n;
+};
+constexpr int kGraphSortCap = 8192;     // accepted pairs a captured batch can sort
+hipError_t launch_graph_batch(const GraphBatch& G, hipStream_t s);
 hipError_t launch_short_path(const DevSet& P, const DevSet& Y, int tau, int self,
                              const int32_t* q_tau, uint64_t* out, uint64_t out_cap,
                              unsigned long long* counters, hipStream_t s);

@@ -50,6 +50,8 @@ struct Slot {
     std::thread th;
     std::unique_ptr<Batch> job;     // guarded by Server::mu
     bool busy = false;
+    GraphPlan* plan = nullptr;      // captured pipeline (worker thread only)
+    bool plan_failed = false;
 };
 
 }  // namespace pj
@@ -103,9 +105,24 @@ static void run_batch(pj_server* S, Slot& slot, Batch& B)
     pj_stats st{};
     int status = PJ_OK;
     std::string err;
+    const char* tc = S->tune_cache.empty() ? nullptr : S->tune_cache.c_str();
     try {
-        run_query_batch(S->idx, &Q, taus.data(), pairs, st, slot.stream,
-                        S->tune_cache.empty() ? nullptr : S->tune_cache.c_str());
+        bool done = false;
+        if (!S->cfg.eager) {
+            if (!slot.plan && !slot.plan_failed) {
+                try {
+                    slot.plan = graph_plan_create(S->idx, S->cfg.max_batch_queries, slot.stream, tc);
+                } catch (const Error&) {
+                    slot.plan_failed = true;      // this slot runs its batches uncaptured
+                }
+            }
+            if (slot.plan) done = graph_plan_run(slot.plan, &Q, taus.data(), pairs, st);
+        }
+        if (!done) {
+            pairs.clear();
+            st = pj_stats{};
+            run_query_batch(S->idx, &Q, taus.data(), pairs, st, slot.stream, tc);
+        }
     } catch (const Error& e) {
         status = e.code;
         err = e.msg;
@@ -152,6 +169,10 @@ static void worker_main(pj_server* S, Slot* slot)
         }
         S->cv_done.notify_all();
         S->cv_sched.notify_all();
+    }
+    if (slot->plan) {
+        graph_plan_destroy(slot->plan);
+        slot->plan = nullptr;
     }
     release_thread_workspace();
 }
@@ -208,7 +229,7 @@ int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server*
         if (!out) throw Error(PJ_EINVAL, "null output");
         *out = nullptr;
         if (!idx) throw Error(PJ_EINVAL, "null index");
-        pj_server_config c{2, 256, 0, nullptr};
+        pj_server_config c{2, 256, 0, nullptr, 0};
         if (cfg) c = *cfg;
         if (c.slots < 1 || c.slots > 64) throw Error(PJ_EINVAL, "slots must be in [1, 64]");
         if (c.max_batch_queries < 1) throw Error(PJ_EINVAL, "max_batch_queries must be >= 1");

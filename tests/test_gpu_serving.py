@@ -117,3 +117,42 @@ def test_stop_drains_pending(served):
     srv.stop()
     for g, e in zip(got, alone[:2]):
         assert np.array_equal(g, e)
+
+
+def test_captured_and_uncaptured_batches_agree(served):
+    """Each slot replays one captured graph per batch; the uncaptured path (eager=True) gives
+    the same pairs for the same merged batches."""
+    S, idx, batches, alone = served
+    for eager in (False, True):
+        with P.Server(idx, slots=2, max_batch_queries=64, eager=eager) as srv:
+            ids = [srv.submit(q, t) for q, t in batches]
+            res = [srv.wait(i) for i in ids]
+        for (pairs, _), exp in zip(res, alone):
+            assert np.array_equal(pairs, exp), f"eager={eager}"
+
+
+def test_captured_batch_falls_back_on_overflow():
+    """A batch with more accepted pairs than the captured pipeline can sort, and a request
+    with more queries than the plan holds, run uncaptured and still give the exact result."""
+    rng = np.random.default_rng(77)
+    hot = b"abcdefghij"
+    strs = [hot] * 300 + [bytes(rng.integers(97, 123, size=int(rng.integers(5, 30))).astype(np.uint8))
+                          for _ in range(2000)]
+    S = W.from_list(strs)
+    idx = P.pj_build_index(S, 1, 3)
+    try:
+        Q = W.from_list([hot] * 40)               # 40 x 300 pairs > the sort capacity
+        T = np.ones(40, np.int32)
+        exp = P.pj_query(idx, Q, T)
+        assert len(exp) == 12000
+        big = W.from_list([bytes(rng.integers(97, 123, size=12).astype(np.uint8))
+                           for _ in range(50)] + [hot])
+        TB = rng.integers(1, 4, size=big.n).astype(np.int32)
+        exp_big = P.pj_query(idx, big, TB)
+        with P.Server(idx, slots=1, max_batch_queries=40) as srv:
+            got, _ = srv.wait(srv.submit(Q, T))
+            got_big, _ = srv.wait(srv.submit(big, TB))   # 51 queries > 40
+        assert np.array_equal(got, exp)
+        assert np.array_equal(got_big, exp_big)
+    finally:
+        idx.free()
