@@ -87,11 +87,13 @@ def cpu_baseline(col, taus):
                       " (time includes the oracle's index build)"}
 
 
-def serving_bench(P, W, n_index: int, seconds: float, slots: int):
+def serving_bench(P, W, n_index: int, seconds: float, slots: int, compare_eager: bool = True):
     """Open-loop serving: batches of Poisson(64) queries (tau U{1..8}, lengths U{10..120}, half
     edited copies of indexed strings) arrive as a Poisson process against a resident index of
     n_index strings.  The arrival rate is fixed at 50% and 80% of the closed-loop saturation
-    throughput measured first.  Latency = submit -> pairs in host memory (server clock)."""
+    throughput measured first.  Latency = submit -> pairs in host memory (server clock), split
+    into the wait for a slot (submit -> admit) and the batch's service time (admit -> done).
+    The uncaptured path is also measured at 50% of the captured saturation rate."""
     import threading
 
     import numpy as np
@@ -105,6 +107,66 @@ def serving_bench(P, W, n_index: int, seconds: float, slots: int):
     pool = [W.cfg5_batch(rng, S) for _ in range(256)]
     out = {"index_strings": n_index, "index_build_s": round(build_s, 3),
            "index_device_bytes": info["device_bytes"], "slots": slots}
+
+    def open_loop(srv, lam, seed, label):
+        ids, lock = [], threading.Lock()
+        stop = threading.Event()
+        lats, waits, svcs, nq, batch_sizes = [], [], [], [0], []
+
+        def collector():
+            j = 0
+            while True:
+                with lock:
+                    have = j < len(ids)
+                if not have:
+                    if stop.is_set():
+                        with lock:
+                            if j >= len(ids):
+                                return
+                    time.sleep(0.0005)
+                    continue
+                rid, m = ids[j]
+                _, inf = srv.wait(rid)
+                lats.append(inf["t_done_ms"] - inf["t_submit_ms"])
+                waits.append(inf["t_admit_ms"] - inf["t_submit_ms"])
+                svcs.append(inf["t_done_ms"] - inf["t_admit_ms"])
+                batch_sizes.append(inf["batch_requests"])
+                nq[0] += m
+                j += 1
+
+        th = threading.Thread(target=collector)
+        th.start()
+        arr = np.random.default_rng(seed)
+        t0 = time.perf_counter()
+        t_next = t0
+        k = 0
+        while t_next - t0 < seconds:
+            now = time.perf_counter()
+            if now < t_next:
+                time.sleep(min(t_next - now, 0.002))
+                continue
+            q, t = pool[k % len(pool)]
+            rid = srv.submit(q, t)
+            with lock:
+                ids.append((rid, q.n))
+            k += 1
+            t_next += arr.exponential(1.0 / lam)
+        stop.set()
+        th.join()
+        wall = time.perf_counter() - t0
+        L, Wt, Sv = np.array(lats), np.array(waits), np.array(svcs)
+        pc = lambda a, q: round(float(np.percentile(a, q)), 3)
+        rec = {
+            "lambda_batches_per_s": round(lam, 2), "batches": len(L),
+            "p50_ms": pc(L, 50), "p99_ms": pc(L, 99), "p999_ms": pc(L, 99.9),
+            "queue_wait_p50_ms": pc(Wt, 50), "queue_wait_p99_ms": pc(Wt, 99),
+            "service_p50_ms": pc(Sv, 50), "service_p99_ms": pc(Sv, 99),
+            "batches_per_s": round(len(L) / wall, 2), "queries_per_s": round(nq[0] / wall, 1),
+            "mean_requests_per_device_batch": round(float(np.mean(batch_sizes)), 2),
+        }
+        log("serving", label, rec)
+        return rec
+
     with P.Server(idx, slots=slots, max_batch_queries=512, mem_budget=8 << 30) as srv:
         for k in range(8):                                   # warm the slots' scratch
             srv.wait(srv.submit(*pool[k]))
@@ -122,61 +184,19 @@ def serving_bench(P, W, n_index: int, seconds: float, slots: int):
         out["saturation_batches_per_s"] = round(sat, 2)
         levels = []
         for frac in (0.5, 0.8):
-            lam = frac * sat
-            ids, lock = [], threading.Lock()
-            stop = threading.Event()
-            lats, nq, batch_sizes = [], [0], []
-
-            def collector():
-                j = 0
-                while True:
-                    with lock:
-                        have = j < len(ids)
-                    if not have:
-                        if stop.is_set():
-                            with lock:
-                                if j >= len(ids):
-                                    return
-                        time.sleep(0.0005)
-                        continue
-                    rid, m = ids[j]
-                    _, inf = srv.wait(rid)
-                    lats.append(inf["t_done_ms"] - inf["t_submit_ms"])
-                    batch_sizes.append(inf["batch_requests"])
-                    nq[0] += m
-                    j += 1
-
-            th = threading.Thread(target=collector)
-            th.start()
-            arr = np.random.default_rng(int(frac * 100))
-            t0 = time.perf_counter()
-            t_next = t0
-            k = 0
-            while t_next - t0 < seconds:
-                now = time.perf_counter()
-                if now < t_next:
-                    time.sleep(min(t_next - now, 0.002))
-                    continue
-                q, t = pool[k % len(pool)]
-                rid = srv.submit(q, t)
-                with lock:
-                    ids.append((rid, q.n))
-                k += 1
-                t_next += arr.exponential(1.0 / lam)
-            stop.set()
-            th.join()
-            wall = time.perf_counter() - t0
-            L = np.array(lats)
-            levels.append({
-                "load": frac, "lambda_batches_per_s": round(lam, 2), "batches": len(L),
-                "p50_ms": round(float(np.percentile(L, 50)), 3),
-                "p99_ms": round(float(np.percentile(L, 99)), 3),
-                "p999_ms": round(float(np.percentile(L, 99.9)), 3),
-                "batches_per_s": round(len(L) / wall, 2), "queries_per_s": round(nq[0] / wall, 1),
-                "mean_requests_per_device_batch": round(float(np.mean(batch_sizes)), 2),
-            })
-            log("serving", levels[-1])
+            rec = open_loop(srv, frac * sat, int(frac * 100), f"captured {frac}")
+            rec["load"] = frac
+            levels.append(rec)
         out["levels"] = levels
+    if compare_eager:
+        # the same arrival rate (50% of the captured saturation) with uncaptured batches
+        with P.Server(idx, slots=slots, max_batch_queries=512, mem_budget=8 << 30,
+                      eager=True) as srv:
+            for k in range(8):
+                srv.wait(srv.submit(*pool[k]))
+            rec = open_loop(srv, 0.5 * sat, 50, "uncaptured 0.5")
+            rec["load_of_captured_saturation"] = 0.5
+            out["uncaptured"] = rec
     idx.free()
     return out
 
@@ -199,7 +219,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning the launch parameters (built-in defaults)")
     ap.add_argument("--tune-cache", default=None,
-                    help="autotune cache file (default: a fresh file in the temp directory)")
+                    help="autotune cache file (written when tuning; with --no-tune it is only "
+                         "read).  Default: a fresh file in the temp directory")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,7 +256,7 @@ def main():
     # autotuning (outside the timed region): launch parameters per (GPU, tau, length bucket),
     # searched on this workload; the timed joins read them from the cache file
     tuning = None
-    cache = None
+    cache = args.tune_cache if args.mode != P.MODE_PLAIN else None
     if not args.no_tune and args.mode != P.MODE_PLAIN:
         import tempfile
         cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="pj_tune_"), "tune.txt")

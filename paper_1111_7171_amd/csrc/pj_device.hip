@@ -1623,7 +1623,7 @@ hipError_t launch_graph_batch(const GraphBatch& G, hipStream_t s)
     hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(kBlock), 0, s, G.probe.hits,
                        G.probe.counters, G.probe.hit_cap,
                        const_cast<unsigned long long*>(G.verify.prefix), G.bcounts, G.chunk_cap);
-    hipLaunchKernelGGL(k_chunk_starts_dev, dim3(64), dim3(kBlock), 0, s, G.verify.prefix,
+    hipLaunchKernelGGL(k_chunk_starts_dev, dim3(8), dim3(kBlock), 0, s, G.verify.prefix,
                        G.bcounts, G.first);
     const int w = G.verify.tau + 1;
     if (w <= 9) graph_verify_short<9>(G, s);

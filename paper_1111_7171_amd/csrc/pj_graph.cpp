@@ -116,7 +116,11 @@ GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t s
     pp.hit_cap = g->hcap;
     pp.counters = counters;
     pp.nx_dev = (const uint32_t*)g->d_tables;
-    G.probe_grid = device_cus() * tp.probe_blocks_per_cu;
+    // grids sized for the plan's capacity (a serving batch is small; idle blocks of a
+    // chip-wide grid would still cost every batch their launch)
+    const uint64_t probe_threads = (uint64_t)Q * (uint64_t)pp.nl * (uint64_t)(g->tau_max + 1);
+    G.probe_grid = (int)std::min<uint64_t>((uint64_t)device_cus() * tp.probe_blocks_per_cu,
+                                           (probe_threads + 255) / 256);
     if (!index_has_entries(idx)) pp.ymax = -1;        // nothing indexed: the probe finds no list
     VerifyParams& vp = G.verify;
     vp.x_arena = pp.x_arena; vp.x_slen = pp.x_slen; vp.x_lenstart = pp.x_lenstart;
@@ -133,7 +137,7 @@ GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t s
     vp.counters = counters;
     G.bcounts = counters + 8;
     vp.dev_counts = G.bcounts;
-    G.verify_grid = std::max(1, device_cus() * tp.verify_waves_per_cu / 4);
+    G.verify_grid = std::max(1, std::min(device_cus() * tp.verify_waves_per_cu / 4, 256));
     G.first = first;
     G.chunk_cap = g->chunk_cap;
     // indexed strings shorter than tau_max + 1 go through the side path
