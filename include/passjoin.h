@@ -182,14 +182,15 @@ int pj_server_stop(pj_server* srv);
 /* Autotuning of the batched path's launch parameters.  None of them changes a result (the pairs
  * and all counters of pj_stats stay the same); they decide how the candidates of Algorithm 1 are
  * spread over the GPU: the persistent verification grid (waves per compute unit), the list
- * segments (64 candidates each) a wave takes at a time, the candidate count from which an
- * inverted list is verified a wave at a time instead of candidate by candidate, and the probe
- * grid (blocks per compute unit). */
+ * segments (64 candidates per lane slot) a wave takes at a time, the candidate count from which
+ * an inverted list is verified a wave at a time instead of candidate by candidate, the probe
+ * grid (blocks per compute unit), and how many members of one list each lane verifies at once. */
 typedef struct {
     int32_t verify_waves_per_cu;   /* 8, 16, 32, 64, 128 or 256 (default 32) */
     int32_t seg_chunk;             /* 1, 2, 4, 8, 16, 32, 64 or 128 (default 4) */
     int32_t big_list;              /* 16, 32, 64 or 128 (default 32) */
     int32_t probe_blocks_per_cu;   /* 4, 8 or 16 (default 8) */
+    int32_t lane_cands;            /* list-segment candidates per lane: 1 or 2 (default 2) */
     int32_t len_bucket;            /* key: bit length of the rounded mean string length */
     int32_t trials;                /* settings measured */
     double ms_default;             /* probe + verification kernel time, built-in defaults */
@@ -197,12 +198,13 @@ typedef struct {
 } pj_tune_result;
 
 /* Searches the launch parameters for the self-join of S (host memory) at tau by coordinate
- * descent, timing the probe and verification kernels (best of two runs per setting), and
+ * descent (repeated until a pass changes nothing, at most 3 passes), timing the probe and
+ * verification kernels (best of two runs per setting), and
  * records the best setting under (this GPU's architecture, tau, length bucket of S's mean
  * length).  The record is kept for the rest of the process; when opt->tune_cache names a file
  * it is also merged into that file (plain text, one setting per line), which later calls with
  * the same tune_cache read.  opt->inputs_on_device must be 0.  Each trial runs the full
- * self-join, so the cost is about 40 joins of S.  Returns PJ_OK or a PJ_E* code. */
+ * self-join, so the cost is about 40-100 joins of S.  Returns PJ_OK or a PJ_E* code. */
 int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_result* out);
 
 /* Releases pairs (host or device memory as recorded in on_device) and zeroes the struct. */

@@ -895,10 +895,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
 // ------------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_seg_counts(const Hit* __restrict__ hits, uint64_t nbig,
-                                                       uint32_t* __restrict__ segs)
+                                                       uint32_t members, uint32_t* __restrict__ segs)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k < nbig) segs[k] = (hits[k].count + 63u) >> 6;
+    if (k < nbig) segs[k] = (hits[k].count + members - 1u) / members;
 }
 
 // first[ch] = the list holding segment ch * chunk (largest h with segp[h] <= it)
@@ -918,31 +918,41 @@ __global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __r
     first[ch] = (uint32_t)a;
 }
 
-template <int MAXW, bool EXACT, typename LaneChars>
-__device__ inline int vsp_seg_any(bool yrows, LdsChars U, int lu, LaneChars V, int lv, int t,
-                                  BandLanes BL, int* cells)
+template <int MAXW, bool EXACT, int NC, typename LaneChars>
+__device__ inline void vsp_seg_any(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
+                                   int lv, int t, BandLanes BL, const bool (&act)[NC],
+                                   int (&cells)[NC], int (&res)[NC])
 {
-    return yrows ? vsp_seg<MAXW, EXACT, true>(U, lu, V, lv, t, BL, cells)
-                 : vsp_seg<MAXW, EXACT, false>(U, lu, V, lv, t, BL, cells);
+    if (yrows) vsp_seg<MAXW, EXACT, true, NC>(U, lu, V, lv, t, BL, act, cells, res);
+    else vsp_seg<MAXW, EXACT, false, NC>(U, lu, V, lv, t, BL, act, cells, res);
 }
 
-// exact band width for uniform t <= 8, else the width class GMAXW
-template <int GMAXW, typename LaneChars>
-__device__ inline int vsp_seg_dispatch(bool yrows, LdsChars U, int lu, LaneChars V, int lv,
-                                       int t, BandLanes BL, int* cells)
+// exact band width for uniform t < min(9, GMAXW), else the width class GMAXW
+template <int GMAXW, int NC, typename LaneChars>
+__device__ inline void vsp_seg_dispatch(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
+                                        int lv, int t, BandLanes BL, const bool (&act)[NC],
+                                        int (&cells)[NC], int (&res)[NC])
 {
+#define PJ_SEG_CASE(T)                                                                      \
+    case T:                                                                                 \
+        if constexpr (T + 1 <= GMAXW)                                                       \
+            vsp_seg_any<T + 1, true, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);      \
+        else                                                                                \
+            vsp_seg_any<GMAXW, false, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);     \
+        break;
     switch (t) {
-    case 0: return vsp_seg_any<1, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 1: return vsp_seg_any<2, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 2: return vsp_seg_any<3, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 3: return vsp_seg_any<4, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 4: return vsp_seg_any<5, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 5: return vsp_seg_any<6, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 6: return vsp_seg_any<7, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 7: return vsp_seg_any<8, true>(yrows, U, lu, V, lv, t, BL, cells);
-    case 8: return vsp_seg_any<9, true>(yrows, U, lu, V, lv, t, BL, cells);
-    default: return vsp_seg_any<GMAXW, false>(yrows, U, lu, V, lv, t, BL, cells);
+    PJ_SEG_CASE(0)
+    PJ_SEG_CASE(1)
+    PJ_SEG_CASE(2)
+    PJ_SEG_CASE(3)
+    PJ_SEG_CASE(4)
+    PJ_SEG_CASE(5)
+    PJ_SEG_CASE(6)
+    PJ_SEG_CASE(7)
+    PJ_SEG_CASE(8)
+    default: vsp_seg_any<GMAXW, false, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res); break;
     }
+#undef PJ_SEG_CASE
 }
 
 // a wave-uniform load through the scalar cache (read-only data)
@@ -952,7 +962,7 @@ __device__ inline T uniform_load(const T* p)
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
-template <int GMAXW, int REGY>
+template <int GMAXW, int REGY, int NCT>
 __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         const Hit* __restrict__ big,
                                                         const uint32_t* __restrict__ segp,
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
     __shared__ uint32_t s_x[kWaves][(kLenMax + 4) / 4];   // the current probe string
-    __shared__ uint32_t s_q[kWaves][128];                 // left-part survivors (gy)
+    __shared__ uint32_t s_q[kWaves][256];                 // left-part survivors (gy)
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     uint32_t* sx = s_x[threadIdx.x >> 6];
@@ -1019,7 +1029,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
             const BandLanes bl = band_lanes(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane);
             const BandLanes br = band_lanes(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane);
-            const uint32_t hsegs = (count + 63u) >> 6;
+            // NC candidates per lane: a list segment has 64 * NC members
+            constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
+            constexpr uint32_t SEG = 64u * NC;
+            const uint32_t hsegs = (count + SEG - 1) / SEG;
             const uint64_t left_in_chunk = sg_end - sg_i;
             const uint32_t s_stop = (uint64_t)(hsegs - sidx) < left_in_chunk
                                         ? hsegs : sidx + (uint32_t)left_in_chunk;
@@ -1038,16 +1051,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                 }
                 return y;
             };
-            // Two phases per hit: the left parts of each 64-member segment, then the right parts
-            // of the survivors, taken 64 at a time from a wave-private queue, so that a wave's
+            // Two phases per hit: the left parts of each segment, then the right parts of the
+            // survivors, taken SEG at a time from a wave-private queue, so that a wave's
             // right-part rows are not spent on lanes whose left part already failed.  Each
-            // iteration runs one band DP: a left step (next segment) or a right batch (64 queued
+            // iteration runs one band DP: a left step (next segment) or a right batch (SEG queued
             // survivors, or the rest once the segments are done).
             uint32_t qn = 0;    // queued survivors (wave-uniform)
             for (;;) {
-                const bool right = qn >= 64 || (sidx >= s_stop && qn > 0);
+                const bool right = qn >= SEG || (sidx >= s_stop && qn > 0);
                 if (!right && sidx >= s_stop) break;
-                const uint32_t k = right ? (qn < 64 ? qn : 64) : 0;
+                const uint32_t k = right ? (qn < SEG ? qn : SEG) : 0;
                 if (right) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -1056,55 +1069,93 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                 // the part's band set-up, selected with the whole wave active
                 BandLanes bd = right ? br : bl;
                 asm volatile("" : "+v"(bd.r0), "+v"(bd.ek), "+v"(bd.w0));
-                const uint32_t member = sidx * 64u + (uint32_t)lane;
-                uint32_t gy = 0;
-                uint32_t yr[REGY > 0 ? REGY / 4 : 1];
-                const uint8_t* y = V.y_arena;
-                bool ok = right ? (uint32_t)lane < k : member < count;
-                if (ok) {
-                    gy = right ? sq[lane] : vals[start + member];
-                    y = load_y(gy, yr);
-                    if (!right && sgm.len > kExactLen) {
-                        // hashed key: compare the segment bytes before extension verification,
-                        // which skips the segment
-                        const LdsChars xs{xl8 + (p - 1)};
-                        if (REGY > 0) {
-                            const RegChars yc{yr, sgm.p - 1};
-                            for (int q = 0; q < sgm.len; ++q) ok &= (xs[q] == yc[q]);
-                        } else {
-                            for (int q = 0; q < sgm.len; ++q) ok &= (xs[q] == (int)y[sgm.p - 1 + q]);
+                uint32_t gy[NC];
+                uint32_t yr[NC][REGY > 0 ? REGY / 4 : 1];
+                const uint8_t* y[NC];
+                bool ok[NC];
+                bool anyok = false;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
+                    const uint32_t member = sidx * SEG + slot;
+                    ok[c] = right ? slot < k : member < count;
+                    gy[c] = 0;
+                    y[c] = V.y_arena;
+                    if (ok[c]) {
+                        if (right) gy[c] = sq[slot];
+                        else gy[c] = vals[start + member];
+                        y[c] = load_y(gy[c], yr[c]);
+                        if (!right && sgm.len > kExactLen) {
+                            // hashed key: compare the segment bytes before extension
+                            // verification, which skips the segment
+                            const LdsChars xs{xl8 + (p - 1)};
+                            bool same = true;
+                            if (REGY > 0) {
+                                const RegChars yc{yr[c], sgm.p - 1};
+                                for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
+                            } else {
+                                for (int q = 0; q < sgm.len; ++q)
+                                    same &= (xs[q] == (int)y[c][sgm.p - 1 + q]);
+                            }
+                            my_miss += same ? 0 : 1;
+                            ok[c] = same;
                         }
-                        my_miss += ok ? 0 : 1;
                     }
+                    anyok = anyok || ok[c];
                 }
-                if (ok) {
+                if (anyok) {
                     const int xo = right ? rx : 0, xl = right ? n - rx : p - 1;
                     const int yo = right ? ry : 0, yl = right ? l - ry : sgm.p - 1;
                     const int tt = right ? tr : tl;
-                    int c = 0, d;
-                    if (REGY > 0)
-                        d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
-                                                    RegChars{yr, yo}, yl, tt, bd, &c);
-                    else
-                        d = vsp_seg_dispatch<GMAXW>(yl <= xl, LdsChars{xl8 + xo}, xl,
-                                                    GlobalChars{y + yo}, yl, tt, bd, &c);
-                    my_cells += (uint64_t)c;
-                    ok = d <= tt;
+                    int cl[NC], d[NC];
+                    if (REGY > 0) {
+                        RegChars vc[NC];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) vc[c] = RegChars{yr[c], yo};
+                        vsp_seg_dispatch<GMAXW, NC>(yl <= xl, LdsChars{xl8 + xo}, xl, vc, yl, tt,
+                                                    bd, ok, cl, d);
+                    } else {
+                        GlobalChars vc[NC];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) vc[c] = GlobalChars{y[c] + yo};
+                        vsp_seg_dispatch<GMAXW, NC>(yl <= xl, LdsChars{xl8 + xo}, xl, vc, yl, tt,
+                                                    bd, ok, cl, d);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        my_cells += (uint64_t)cl[c];
+                        ok[c] = ok[c] && d[c] <= tt;
+                    }
                 }
                 if (right) {
-                    acc.push(ok, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        acc.push(ok[c], ((uint64_t)gx << 32) | gy[c], V.out, V.out_cap,
+                                 &V.counters[3]);
+                    // move the rest of the queue to its front (all reads before the writes)
                     const uint32_t rest = qn - k;
-                    uint32_t v = 0;
-                    if ((uint32_t)lane < rest) v = sq[64 + lane];
-                    if ((uint32_t)lane < rest) sq[lane] = v;
+                    uint32_t mv[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
+                        mv[c] = slot < rest ? sq[SEG + slot] : 0u;
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
+                        if (slot < rest) sq[slot] = mv[c];
+                    }
                     qn = rest;
                 } else {
-                    const uint64_t surv = __builtin_amdgcn_ballot_w64(ok);
-                    if (ok)
-                        sq[qn + __builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(surv >> 32),
-                                    __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] = gy;
-                    qn += (uint32_t)__builtin_popcountll(surv);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const uint64_t surv = __builtin_amdgcn_ballot_w64(ok[c]);
+                        if (ok[c])
+                            sq[qn + __builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(surv >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] = gy[c];
+                        qn += (uint32_t)__builtin_popcountll(surv);
+                    }
                     ++sidx;
                     ++sg_i;
                 }
@@ -1368,43 +1419,71 @@ hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev,
     return hipGetLastError();
 }
 
+template <int W, int NC>
+static void verify_segs_wn(const VerifyParams& V, const Hit* big, const uint32_t* segp,
+                           uint64_t nbig, uint64_t nseg, const uint32_t* first, uint64_t nchunks,
+                           uint32_t chunk, int grid, hipStream_t s)
+{
+    if (V.y_maxlen <= 48)
+        hipLaunchKernelGGL((k_verify_segs<W, 48, NC>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
+    else if (V.y_maxlen <= 64)
+        hipLaunchKernelGGL((k_verify_segs<W, 64, NC>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
+    else
+        hipLaunchKernelGGL((k_verify_segs<W, 0, 1>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
+}
+
 template <int W>
 static void verify_segs_w(const VerifyParams& V, const Hit* big, const uint32_t* segp,
                           uint64_t nbig, uint64_t nseg, const uint32_t* first, uint64_t nchunks,
-                          uint32_t chunk, int grid, hipStream_t s)
+                          uint32_t chunk, int lane_cands, int grid, hipStream_t s)
 {
-    if (V.y_maxlen <= 64)
-        hipLaunchKernelGGL((k_verify_segs<W, 64>), dim3(grid), dim3(kBlock), 0, s, V,
-                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
-    else
-        hipLaunchKernelGGL((k_verify_segs<W, 0>), dim3(grid), dim3(kBlock), 0, s, V,
-                           make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
+    if constexpr (W <= 9) {
+        if (lane_cands == 2) {
+            verify_segs_wn<W, 2>(V, big, segp, nbig, nseg, first, nchunks, chunk, grid, s);
+            return;
+        }
+    }
+    verify_segs_wn<W, 1>(V, big, segp, nbig, nseg, first, nchunks, chunk, grid, s);
 }
 
 uint64_t seg_chunks(uint64_t nseg, int chunk) { return (nseg + (uint64_t)chunk - 1) / (uint64_t)chunk; }
 
-hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipStream_t s)
+// members per list segment: 64 per candidate a lane takes (two per lane only when the indexed
+// strings fit in registers and the band is at most 9 wide)
+int seg_members(int y_maxlen, int tau, int lane_cands)
+{
+    return (lane_cands == 2 && y_maxlen <= 64 && tau + 1 <= 9) ? 128 : 64;
+}
+
+hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, int members, uint32_t* segs,
+                             hipStream_t s)
 {
     if (nbig == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_counts, dim3(blocks_for(nbig)), dim3(kBlock), 0, s, big, nbig, segs);
+    hipLaunchKernelGGL(k_seg_counts, dim3(blocks_for(nbig)), dim3(kBlock), 0, s, big, nbig,
+                       (uint32_t)members, segs);
     return hipGetLastError();
 }
 
 hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint32_t* segp,
-                              uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk, int grid,
-                              hipStream_t s)
+                              uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk,
+                              int lane_cands, int grid, hipStream_t s)
 {
     if (nbig == 0 || nseg == 0) return hipSuccess;
-    if (chunk < 1 || grid < 1) return hipErrorInvalidValue;
+    if (chunk < 1 || grid < 1 || lane_cands < 1 || lane_cands > 2) return hipErrorInvalidValue;
     const uint64_t nchunks = seg_chunks(nseg, chunk);
     const uint32_t c = (uint32_t)chunk;
     hipLaunchKernelGGL(k_seg_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, segp,
                        nbig, nchunks, c, first);
     const int w = V.tau + 1;
-    if (w <= 9) verify_segs_w<9>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
-    else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
-    else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
-    else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, c, grid, s);
+    const int lc = lane_cands;
+    if (w <= 5) verify_segs_w<5>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
+    else if (w <= 9) verify_segs_w<9>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
+    else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
+    else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
+    else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
     return hipGetLastError();
 }
 

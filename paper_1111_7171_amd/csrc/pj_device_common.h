@@ -400,86 +400,130 @@ __device__ inline BandLanes band_lanes(LdsChars U, int lu, int lv, int t, int la
     return B;
 }
 
-template <int MAXW, bool EXACT, bool YROWS, typename LaneChars>
-__device__ inline int vsp_seg(LdsChars U, int lu, LaneChars V, int lv, int t, BandLanes BL,
-                              int* cells)
+// NC candidates per lane (members of the same list, so the same probe-string part and band):
+// the scalar work of a row (band bounds, shared characters, cell count, loop control) is shared
+// by all of them.  A candidate with act[c] false is dead from the start (cells 0, result t+1).
+template <int MAXW, bool EXACT, bool YROWS, int NC, typename LaneChars>
+__device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int lv, int t,
+                               BandLanes BL, const bool (&act)[NC], int (&cells)[NC],
+                               int (&res)[NC])
 {
     static_assert(MAXW <= 64, "one band index per lane");
     const int nr = YROWS ? lv : lu;
     const int nc = YROWS ? lu : lv;
     const int delta = nc - nr;
-    *cells = 0;
-    if (delta > t) return t + 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        cells[c] = 0;
+        res[c] = t + 1;
+    }
+    if (delta > t) return;
     const int a = (t - delta) >> 1;
     const int b = (t + delta) >> 1;
     const int W = a + b + 1;
     const int kfin = delta + a;                  // band index of the last cell (nr, nc)
     constexpr int BIG = 1 << 20;
-    int R[MAXW], w[MAXW], ek[MAXW];
+    constexpr int NW = YROWS ? 1 : NC;           // column windows: shared (YROWS) or per candidate
+    int R[NC][MAXW], w[NW][MAXW], ek[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) {
-        R[k] = __builtin_amdgcn_readlane(BL.r0, k);
+        const int r0 = __builtin_amdgcn_readlane(BL.r0, k);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) R[c][k] = r0;
         ek[k] = __builtin_amdgcn_readlane(BL.ek, k);
         if (YROWS) {
-            w[k] = __builtin_amdgcn_readlane(BL.w0, k);
+            w[0][k] = __builtin_amdgcn_readlane(BL.w0, k);
         } else {
             const int idx = k - a;
-            w[k] = ((unsigned)idx < (unsigned)nc) ? V[idx] : 256;
+#pragma unroll
+            for (int c = 0; c < NW; ++c)
+                w[c][k] = ((unsigned)idx < (unsigned)nc) ? V[c][idx] : 256;
         }
     }
     int idx_in = MAXW - a;                       // column character entering after row 1
     int ai_pre = (!YROWS && nr > 0) ? U[0] : 256;
     int cum = 0;                                 // recurrence cells of rows 1..i (uniform)
-    int stop_cells = 0;
-    bool live = true;
+    int stop_cells[NC];
+    bool live[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        stop_cells[c] = 0;
+        live[c] = act[c];
+    }
     for (int i = 1; i <= nr; ++i) {
-        // row character: the lane's own (registers) or the shared one, read a row ahead
-        int ai, ai_next = 256;
+        // row characters: the lanes' own (registers) or the shared one, read a row ahead
+        int ai[NC], ai_next = 256;
         if (YROWS) {
-            ai = V[i - 1];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ai[c] = V[c][i - 1];
         } else {
-            ai = ai_pre;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ai[c] = ai_pre;
             if (i < nr) ai_next = U[i];
         }
-        int cin = 256;                           // column character entering after the row
-        if ((unsigned)idx_in < (unsigned)nc)
-            cin = YROWS ? __builtin_amdgcn_readfirstlane(U[idx_in]) : V[idx_in];
-        int left = BIG;
-        int e[MAXW];
+        int cin[NW];                             // column characters entering after the row
+        const bool cin_ok = (unsigned)idx_in < (unsigned)nc;
+        if (YROWS) {
+            cin[0] = cin_ok ? __builtin_amdgcn_readfirstlane(U[idx_in]) : 256;
+        } else {
 #pragma unroll
-        for (int k = 0; k < MAXW; ++k) {
-            const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : BIG;
-            // min(up + 1, left + 1, diag + d) as min(up, left, diag - [match]) + 1
-            const int dg = R[k] - ((ai == w[k]) ? 1 : 0);
-            int v = min(min(up, left), dg) + 1;
-            if (!EXACT || k == MAXW - 1) v = (k < W) ? v : BIG;
-            e[k] = v + ek[k];
-            R[k] = v;
-            left = v;
+            for (int c = 0; c < NW; ++c) cin[c] = cin_ok ? V[c][idx_in] : 256;
         }
-        int emin = e[0];
+        bool anyc[NC];
 #pragma unroll
-        for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(e[k], e[k + 1]));
-        if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
-        const bool any = emin <= t;
+        for (int c = 0; c < NC; ++c) {
+            const int* wc = w[YROWS ? 0 : c];
+            int left = BIG;
+            int e[MAXW];
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                const int up = (k + 1 < MAXW) ? R[c][(k + 1) < MAXW ? k + 1 : k] : BIG;
+                // min(up + 1, left + 1, diag + d) as min(up, left, diag - [match]) + 1
+                const int dg = R[c][k] - ((ai[c] == wc[k]) ? 1 : 0);
+                int v = min(min(up, left), dg) + 1;
+                if (!EXACT || k == MAXW - 1) v = (k < W) ? v : BIG;
+                e[k] = v + ek[k];
+                R[c][k] = v;
+                left = v;
+            }
+            int emin = e[0];
+#pragma unroll
+            for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(e[k], e[k + 1]));
+            if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
+            anyc[c] = emin <= t;
+        }
         const int j0 = i - a;
         cum += max(0, min(nc, j0 + W - 1) - max(1, j0) + 1);
-        if (live && !any) stop_cells = cum;
-        live = any;
-        if (__builtin_amdgcn_ballot_w64(any) == 0) break;
+        bool anylive = false;
 #pragma unroll
-        for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
-        w[MAXW - 1] = cin;
+        for (int c = 0; c < NC; ++c) {
+            const bool now = live[c] && anyc[c];
+            if (live[c] && !now) stop_cells[c] = cum;
+            live[c] = now;
+            anylive = anylive || now;
+        }
+        if (__builtin_amdgcn_ballot_w64(anylive) == 0) break;
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+#pragma unroll
+            for (int k = 0; k + 1 < MAXW; ++k) w[c][k] = w[c][k + 1];
+            w[c][MAXW - 1] = cin[c];
+        }
         ++idx_in;
         ai_pre = ai_next;
     }
-    *cells = live ? cum : stop_cells;
-    if (!live) return t + 1;
-    int out = BIG;
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k)
-        if (k == kfin) out = R[k];
-    return min(out, t + 1);
+    for (int c = 0; c < NC; ++c) {
+        if (!act[c]) continue;
+        cells[c] = live[c] ? cum : stop_cells[c];
+        if (live[c]) {
+            int out = BIG;
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k)
+                if (k == kfin) out = R[c][k];
+            res[c] = min(out, t + 1);
+        }
+    }
 }
 
 }  // namespace pj

@@ -499,7 +499,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     if (nbig > 0) {
         uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
         segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + 1));
-        hip_check(launch_seg_counts(J.hits + nsmall, nbig, segs, st), "seg_counts");
+        hip_check(launch_seg_counts(J.hits + nsmall, nbig,
+                                    seg_members(Y.lmax, tau, J.tp.lane_cands), segs, st),
+                  "seg_counts");
         size_t sb = scan_tmp_bytes(nbig);
         void* stmp = W.get("scan.tmp2", sb);
         hip_check(scan_u32_to_u32(segs, segp, nbig, stmp, sb, st), "scan(segs)");
@@ -555,7 +557,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                         nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
                     const int s0 = tm.mark();
                     hip_check(launch_verify_segs(vp, J.hits + nsmall, segp, nbig, nseg, first,
-                                                 J.tp.seg_chunk, (int)((waves + 3) / 4), st),
+                                                 J.tp.seg_chunk, J.tp.lane_cands,
+                                                 (int)((waves + 3) / 4), st),
                               "verify_segs");
                     const int s1 = tm.mark();
                     J.kernel_marks.push_back({s0, s1, 2});

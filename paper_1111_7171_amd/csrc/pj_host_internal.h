@@ -69,6 +69,7 @@ struct TuneParams {
     int seg_chunk = 4;              // list segments (64 members each) per wave chunk
     int big_list = 32;              // lists with at least this many candidates: list-segment kernel
     int probe_blocks_per_cu = 8;    // grid of the probe kernel
+    int lane_cands = 2;             // list-segment candidates per lane (1 or 2)
 };
 
 bool tune_params_valid(const TuneParams& p);

@@ -139,12 +139,15 @@ hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev,
                               uint32_t big, uint32_t* counts, uint32_t* cursor, Hit* out,
                               hipStream_t s);
 // list-segment verification of the lists with >= big candidates (hits big[0 .. nbig), segp =
-// exclusive scan of ceil(count / 64), nseg segments, `chunk` segments per wave chunk; first:
+// exclusive scan of ceil(count / seg_members), nseg segments, `chunk` segments per wave chunk; first:
 // seg_chunks(nseg, chunk) u32 of scratch)
-hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, uint32_t* segs, hipStream_t s);
+// list segments of `members` candidates each (seg_members: what k_verify_segs expects)
+int seg_members(int y_maxlen, int tau, int lane_cands);
+hipError_t launch_seg_counts(const Hit* big, uint64_t nbig, int members, uint32_t* segs,
+                             hipStream_t s);
 hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint32_t* segp,
-                              uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk, int grid,
-                              hipStream_t s);
+                              uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk,
+                              int lane_cands, int grid, hipStream_t s);
 uint64_t seg_chunks(uint64_t nseg, int chunk);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
 uint64_t batched_chunks(uint64_t ncand);

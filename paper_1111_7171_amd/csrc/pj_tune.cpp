@@ -8,9 +8,9 @@
 // events; the result goes to an in-process table and, when pj_options.tune_cache names a file,
 // to that file, which later calls read back.  The file is plain text:
 //
-//   # passjoin tune cache v1: arch tau len_bucket verify_waves_per_cu seg_chunk big_list
-//   #   probe_blocks_per_cu ms
-//   gfx950 4 4 32 4 32 8 112.300
+//   # passjoin tune cache v2: arch tau len_bucket verify_waves_per_cu seg_chunk big_list
+//   #   probe_blocks_per_cu lane_cands ms
+//   gfx950 4 4 32 4 32 8 2 112.300
 //
 // Unknown or out-of-range lines are ignored.  A file that changes on disk is read again.
 #include <sys/stat.h>
@@ -51,6 +51,7 @@ const int kWavesOpts[] = {8, 16, 32, 64, 128, 256};
 const int kChunkOpts[] = {1, 2, 4, 8, 16, 32, 64, 128};
 const int kBigOpts[] = {16, 32, 64, 128};
 const int kProbeOpts[] = {4, 8, 16};
+const int kLaneOpts[] = {1, 2};
 
 template <size_t N>
 bool in(const int (&opts)[N], int v)
@@ -102,8 +103,9 @@ void parse_file(const char* path, std::map<Key, Entry>& table)
         char arch[128];
         int tau, lb;
         Entry e;
-        if (sscanf(line, "%127s %d %d %d %d %d %d %lf", arch, &tau, &lb, &e.p.verify_waves_per_cu,
-                   &e.p.seg_chunk, &e.p.big_list, &e.p.probe_blocks_per_cu, &e.ms) != 8)
+        if (sscanf(line, "%127s %d %d %d %d %d %d %d %lf", arch, &tau, &lb,
+                   &e.p.verify_waves_per_cu, &e.p.seg_chunk, &e.p.big_list,
+                   &e.p.probe_blocks_per_cu, &e.p.lane_cands, &e.ms) != 9)
             continue;
         if (tau < 0 || tau > kTauMax || lb < 0 || lb > 12 || !tune_params_valid(e.p)) continue;
         table[Key(arch, tau, lb)] = e;
@@ -132,13 +134,13 @@ void write_file(const char* path, const std::map<Key, Entry>& table)
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = fopen(tmp.c_str(), "w");
     if (!f) throw Error(PJ_EINVAL, "cannot write tune cache %s", path);
-    fprintf(f, "# passjoin tune cache v1: arch tau len_bucket verify_waves_per_cu seg_chunk "
-               "big_list probe_blocks_per_cu ms\n");
+    fprintf(f, "# passjoin tune cache v2: arch tau len_bucket verify_waves_per_cu seg_chunk "
+               "big_list probe_blocks_per_cu lane_cands ms\n");
     for (const auto& kv : table) {
         const Entry& e = kv.second;
-        fprintf(f, "%s %d %d %d %d %d %d %.3f\n", std::get<0>(kv.first).c_str(),
+        fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", std::get<0>(kv.first).c_str(),
                 std::get<1>(kv.first), std::get<2>(kv.first), e.p.verify_waves_per_cu,
-                e.p.seg_chunk, e.p.big_list, e.p.probe_blocks_per_cu, e.ms);
+                e.p.seg_chunk, e.p.big_list, e.p.probe_blocks_per_cu, e.p.lane_cands, e.ms);
     }
     if (fclose(f) != 0 || rename(tmp.c_str(), path) != 0)
         throw Error(PJ_EINVAL, "cannot write tune cache %s", path);
@@ -154,7 +156,8 @@ double mean_length(const pj_strings* S)
 bool tune_params_valid(const TuneParams& p)
 {
     return in(kWavesOpts, p.verify_waves_per_cu) && in(kChunkOpts, p.seg_chunk) &&
-           in(kBigOpts, p.big_list) && in(kProbeOpts, p.probe_blocks_per_cu);
+           in(kBigOpts, p.big_list) && in(kProbeOpts, p.probe_blocks_per_cu) &&
+           in(kLaneOpts, p.lane_cands);
 }
 
 TuneParams tune_lookup(const char* cache, int tau, double mean_len)
@@ -211,24 +214,42 @@ int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_res
         (void)measure(cur);                  // warm-up: allocations, code objects, caches
         const double ms_default = measure(cur);
         double ms_best = ms_default;
+        // measured settings, so a later pass does not time one again
+        std::map<std::tuple<int, int, int, int, int>, double> seen;
+        auto key_of = [](const TuneParams& p) {
+            return std::make_tuple(p.verify_waves_per_cu, p.seg_chunk, p.big_list,
+                                   p.probe_blocks_per_cu, p.lane_cands);
+        };
+        seen[key_of(cur)] = ms_default;
+        bool changed = false;
         auto descend = [&](int TuneParams::*field, const int* opts, size_t nopts) {
             for (size_t i = 0; i < nopts; ++i) {
                 if (opts[i] == cur.*field) continue;
                 TuneParams cand = cur;
                 cand.*field = opts[i];
-                const double ms = measure(cand);
+                const auto k = key_of(cand);
+                const auto it = seen.find(k);
+                const double ms = it != seen.end() ? it->second : (seen[k] = measure(cand));
                 if (ms < ms_best) {
                     ms_best = ms;
                     cur = cand;
+                    changed = true;
                 }
             }
         };
-        descend(&TuneParams::big_list, kBigOpts, sizeof kBigOpts / sizeof kBigOpts[0]);
-        descend(&TuneParams::seg_chunk, kChunkOpts, sizeof kChunkOpts / sizeof kChunkOpts[0]);
-        descend(&TuneParams::verify_waves_per_cu, kWavesOpts,
-                sizeof kWavesOpts / sizeof kWavesOpts[0]);
-        descend(&TuneParams::probe_blocks_per_cu, kProbeOpts,
-                sizeof kProbeOpts / sizeof kProbeOpts[0]);
+        // coordinate descent, repeated until a whole pass changes nothing (at most 3 passes):
+        // the parameters interact (e.g. the best lanes-per-candidate depends on the grid)
+        for (int pass = 0; pass < 3; ++pass) {
+            changed = false;
+            descend(&TuneParams::big_list, kBigOpts, sizeof kBigOpts / sizeof kBigOpts[0]);
+            descend(&TuneParams::seg_chunk, kChunkOpts, sizeof kChunkOpts / sizeof kChunkOpts[0]);
+            descend(&TuneParams::verify_waves_per_cu, kWavesOpts,
+                    sizeof kWavesOpts / sizeof kWavesOpts[0]);
+            descend(&TuneParams::lane_cands, kLaneOpts, sizeof kLaneOpts / sizeof kLaneOpts[0]);
+            descend(&TuneParams::probe_blocks_per_cu, kProbeOpts,
+                    sizeof kProbeOpts / sizeof kProbeOpts[0]);
+            if (!changed) break;
+        }
 
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -245,6 +266,7 @@ int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_res
         out->seg_chunk = cur.seg_chunk;
         out->big_list = cur.big_list;
         out->probe_blocks_per_cu = cur.probe_blocks_per_cu;
+        out->lane_cands = cur.lane_cands;
         out->len_bucket = std::get<2>(key);
         out->trials = trials;
         out->ms_default = ms_default;

@@ -26,7 +26,7 @@ def _read_cache(path):
         if line.startswith("#"):
             continue
         f = line.split()
-        rows.append((f[0], int(f[1]), int(f[2]), tuple(int(v) for v in f[3:7]), float(f[7])))
+        rows.append((f[0], int(f[1]), int(f[2]), tuple(int(v) for v in f[3:8]), float(f[8])))
     return rows
 
 
@@ -47,6 +47,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128)
     assert r["big_list"] in (16, 32, 64, 128)
     assert r["probe_blocks_per_cu"] in (4, 8, 16)
+    assert r["lane_cands"] in (1, 2)
     assert r["len_bucket"] == _len_bucket(col)
     assert r["trials"] >= 10 and 0 < r["ms_best"] <= r["ms_default"]
     rows = _read_cache(cache)
@@ -54,7 +55,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     arch, tau, lb, params, ms = rows[0]
     assert arch.startswith("gfx") and tau == 3 and lb == r["len_bucket"]
     assert params == (r["verify_waves_per_cu"], r["seg_chunk"], r["big_list"],
-                      r["probe_blocks_per_cu"])
+                      r["probe_blocks_per_cu"], r["lane_cands"])
     plain = P.pj_self_join(col, 3)
     st0 = P.pj_last_stats()
     tuned = P.pj_self_join(col, 3, tune_cache=cache)
@@ -67,7 +68,8 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert sorted(t for _, t, _, _, _ in _read_cache(cache)) == [2, 3]
 
 
-@pytest.mark.parametrize("params", [(8, 1, 16, 4), (256, 128, 128, 16), (16, 2, 64, 8)])
+@pytest.mark.parametrize("params", [(8, 1, 16, 4, 1), (256, 128, 128, 16, 2), (16, 2, 64, 8, 2),
+                                    (32, 4, 32, 8, 1)])
 def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     # the list-segment kernel at these sizes needs the slot bucketing forced on
     monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
@@ -78,7 +80,7 @@ def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     arch = _read_cache(cache)[0][0]
     lb = _len_bucket(col)
     with open(cache, "w") as f:
-        f.write("# passjoin tune cache v1\n")
+        f.write("# passjoin tune cache v2\n")
         for tau in (1, 2, 3, 4):
             f.write(f"{arch} {tau} {lb} {' '.join(map(str, params))} 1.0\n")
     for tau in (1, 2, 3, 4):
@@ -97,7 +99,7 @@ def test_server_reads_tune_cache(tmp_path):
     Q, taus = W.cfg5_batch(rng, S, mean=64)
     cache = str(tmp_path / "tune.txt")
     with open(cache, "w") as f:
-        f.write("# passjoin tune cache v1\nnot-a-gpu 1 1 8 1 16 4 1.0\nbroken line\n")
+        f.write("# passjoin tune cache v2\nnot-a-gpu 1 1 8 1 16 4 2 1.0\nbroken line\n")
     idx = P.pj_build_index(S, 1, 8)
     try:
         exp = P.pj_query(idx, Q, taus)
