@@ -690,10 +690,15 @@ __device__ inline uint32_t hit_bucket(const Hit& v, uint32_t big)
     return ((v.count >= big) ? 64u : 0u) + ((v.meta >> 11) & 63u);
 }
 
-// counts[b] = hits of bucket b (128 buckets)
+// Bucketing of the hits in two passes without global atomics: bb[b * G + blk] = hits of
+// bucket b that block blk meets in its grid-stride walk (G blocks, 128 buckets); after an
+// exclusive scan of bb (bucket-major), the scatter pass walks the same hits in the same order
+// and places each at its block's offset in its bucket plus a rank from LDS counters.  The
+// regions come out in bucket order; order inside a region changes nothing downstream (the
+// result is sorted).
 __global__ __launch_bounds__(kBlock) void k_slot_hist(const Hit* __restrict__ hits,
                                                       const unsigned long long* __restrict__ nh_dev,
-                                                      uint32_t big, uint32_t* __restrict__ counts)
+                                                      uint32_t big, uint32_t* __restrict__ bb)
 {
     __shared__ uint32_t h[128];
     if (threadIdx.x < 128) h[threadIdx.x] = 0;
@@ -703,31 +708,19 @@ __global__ __launch_bounds__(kBlock) void k_slot_hist(const Hit* __restrict__ hi
          k += (uint64_t)gridDim.x * kBlock)
         atomicAdd(&h[hit_bucket(hits[k], big)], 1u);
     __syncthreads();
-    if (threadIdx.x < 128 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < 128) bb[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Moves every hit into its slot's region (regions in slot order; order inside a region is
-// arbitrary, which changes nothing downstream: the result is sorted).  cursor[64] starts at 0.
 __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__ hits,
                                                          const unsigned long long* __restrict__ nh_dev,
                                                          uint32_t big,
-                                                         const uint32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ cursor,
+                                                         const uint32_t* __restrict__ bb_off,
                                                          Hit* __restrict__ out)
 {
-    __shared__ uint32_t base[128];
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int k = 0; k < 128; ++k) {
-            base[k] = run;
-            run += counts[k];
-        }
-    }
-    __syncthreads();
-    __shared__ uint32_t cnt[128], res[128];
+    __shared__ uint32_t run[128], cnt[128];
+    if (threadIdx.x < 128) run[threadIdx.x] = bb_off[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x];
     const uint64_t nh = *nh_dev;
     for (uint64_t k0 = (uint64_t)blockIdx.x * kBlock; k0 < nh; k0 += (uint64_t)gridDim.x * kBlock) {
-        // one global reservation per (block, slot) per round; local ranks from LDS atomics
         if (threadIdx.x < 128) cnt[threadIdx.x] = 0;
         __syncthreads();
         const uint64_t k = k0 + threadIdx.x;
@@ -739,11 +732,9 @@ __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__
             rank = atomicAdd(&cnt[sl], 1u);
         }
         __syncthreads();
-        if (threadIdx.x < 128 && cnt[threadIdx.x])
-            res[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        if (k < nh) out[run[sl] + rank] = v;
         __syncthreads();
-        if (k < nh) out[base[sl] + res[sl] + rank] = v;
-        __syncthreads();
+        if (threadIdx.x < 128) run[threadIdx.x] += cnt[threadIdx.x];
     }
 }
 
@@ -1407,15 +1398,22 @@ static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint6
 
 uint64_t batched_chunks(uint64_t ncand) { return (ncand + kWaveChunk - 1) / kWaveChunk; }
 
+unsigned slot_bucket_grid(uint64_t nh_cap)
+{
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nh_cap + kBlock - 1) / kBlock, 2048));
+}
+
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
-                              uint32_t big, uint32_t* counts, uint32_t* cursor, Hit* out,
-                              hipStream_t s)
+                              uint32_t big, uint32_t* bb, uint32_t* bb_off, void* scan_tmp,
+                              size_t scan_bytes, Hit* out, hipStream_t s)
 {
     if (nh_cap == 0) return hipSuccess;
-    unsigned grid = (unsigned)std::min<uint64_t>((nh_cap + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, counts);
-    hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, counts,
-                       cursor, out);
+    const unsigned grid = slot_bucket_grid(nh_cap);
+    hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, bb);
+    hipError_t e = scan_u32_to_u32(bb, bb_off, (uint64_t)grid * 128, scan_tmp, scan_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, bb_off,
+                       out);
     return hipGetLastError();
 }
 

@@ -472,17 +472,21 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     uint64_t bucket_min = kBucketMinCandidates;
     if (const char* e = getenv("PJ_BUCKET_MIN_CANDIDATES")) bucket_min = strtoull(e, nullptr, 10);
     if (batched && J.nhits > 0 && J.ncand >= bucket_min) {
-        uint32_t* sc = (uint32_t*)W.get("join.slotcnt", 256 * sizeof(uint32_t));
-        hip_check(hipMemsetAsync(sc, 0, 256 * sizeof(uint32_t), st), "memset");
+        const unsigned g = slot_bucket_grid(J.nhits);
+        const size_t nbb = (size_t)g * 128;
+        uint32_t* bb = (uint32_t*)W.get("join.bb", sizeof(uint32_t) * nbb);
+        uint32_t* bb_off = (uint32_t*)W.get("join.bb_off", sizeof(uint32_t) * (nbb + 1));
+        const size_t sb = scan_tmp_bytes(nbb);
+        void* stmp = W.get("scan.tmp3", sb);
         Hit* sorted = (Hit*)W.get("join.hits2", sizeof(Hit) * (size_t)J.nhits);
-        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, (uint32_t)J.tp.big_list, sc,
-                                     sc + 128, sorted, st), "slot_bucket");
+        hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, (uint32_t)J.tp.big_list, bb,
+                                     bb_off, stmp, sb, sorted, st), "slot_bucket");
         J.hits = sorted;
-        uint32_t hc[128];
-        hip_check(hipMemcpyAsync(hc, sc, sizeof hc, hipMemcpyDeviceToHost, st), "bucket counts");
+        uint32_t ns = 0;
+        hip_check(hipMemcpyAsync(&ns, bb_off + (size_t)g * 64, sizeof ns, hipMemcpyDeviceToHost,
+                                 st), "small-list hits");
         hip_check(hipStreamSynchronize(st), "sync");
-        nsmall = 0;
-        for (int k = 0; k < 64; ++k) nsmall += hc[k];
+        nsmall = ns;
         nbig = J.nhits - nsmall;
     }
 

@@ -133,11 +133,14 @@ hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, ui
 hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
-// batched path: bucket hits by slot (counts and cursor: 64 zeroed u32 each), then verify with
-// per-wave chunks (first: batched_chunks(ncand) u32 of scratch)
+// batched path: bucket the hits by (list size class, slot) into out, bucket regions in order;
+// bb: 128 * slot_bucket_grid(nh_cap) u32, bb_off: one more (bb_off[64 * grid] = hits in the
+// small-list buckets), scan_tmp: scan_tmp_bytes(128 * grid).  Then verify with per-wave chunks
+// (first: batched_chunks(ncand) u32 of scratch)
+unsigned slot_bucket_grid(uint64_t nh_cap);
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
-                              uint32_t big, uint32_t* counts, uint32_t* cursor, Hit* out,
-                              hipStream_t s);
+                              uint32_t big, uint32_t* bb, uint32_t* bb_off, void* scan_tmp,
+                              size_t scan_bytes, Hit* out, hipStream_t s);
 // list-segment verification of the lists with >= big candidates (hits big[0 .. nbig), segp =
 // exclusive scan of ceil(count / seg_members), nseg segments, `chunk` segments per wave chunk; first:
 // seg_chunks(nseg, chunk) u32 of scratch)
