@@ -392,16 +392,43 @@ __global__ __launch_bounds__(kBlock) void k_pack_arena(const uint8_t* __restrict
 
 // One thread per (indexed string, slot): emits (key, g) at a position grouped by (l, i) and
 // ordered by g inside the group, so a stable sort by key keeps lists in ascending g.
+// bitmap of the bytes present in the strings of a set (one thread per string)
+__global__ __launch_bounds__(kBlock) void k_byte_presence(const uint8_t* __restrict__ sarena,
+                                                          const uint16_t* __restrict__ slen,
+                                                          const int32_t* __restrict__ lenstart,
+                                                          const int64_t* __restrict__ gbase,
+                                                          int64_t n, uint32_t* __restrict__ bitmap)
+{
+    __shared__ uint32_t bm[8];
+    if (threadIdx.x < 8) bm[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n;
+         g += (int64_t)gridDim.x * kBlock) {
+        const int l = slen[g];
+        const uint8_t* s = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
+        for (int k = 0; k < l; ++k) {
+            const uint32_t b = s[k];
+            const uint32_t bit = 1u << (b & 31u);
+            if (!(bm[b >> 5] & bit)) atomicOr(&bm[b >> 5], bit);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && bm[threadIdx.x]) atomicOr(&bitmap[threadIdx.x], bm[threadIdx.x]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit_segments(const uint8_t* __restrict__ sarena,
                                                           const uint16_t* __restrict__ slen,
                                                           const int32_t* __restrict__ lenstart,
                                                           const int64_t* __restrict__ gbase,
                                                           const int64_t* __restrict__ ebase,
                                                           int tau, int64_t g_first,
-                                                          int64_t g_count, Div div,
+                                                          int64_t g_count, Div div, SymMap sym,
                                                           uint64_t* __restrict__ keys,
                                                           uint32_t* __restrict__ vals)
 {
+    __shared__ uint16_t s_sym[256];
+    s_sym[threadIdx.x] = sym.code[threadIdx.x];
+    __syncthreads();
     const int T1 = tau + 1;
     int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= g_count * T1) return;
@@ -410,10 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_segments(const uint8_t* __restr
     int l = slen[g];
     Seg sg = partition_seg(l, i, tau, div);
     const uint8_t* s = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
-    uint64_t h = seg_code(s + sg.p - 1, sg.len);
+    uint64_t h = seg_code(s + sg.p - 1, sg.len, s_sym, sym.bits, sym.exact_len);
     int64_t nl = lenstart[l + 1] - lenstart[l];
     int64_t e = ebase[l] + (int64_t)(i - 1) * nl + (g - lenstart[l]);
-    keys[e] = make_key(l, i, tau, sg.len, h);
+    keys[e] = make_key(l, i, tau, sg.len, h, sym.exact_len);
     vals[e] = (uint32_t)g;
 }
 
@@ -475,6 +502,10 @@ __global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restri
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
 {
     __shared__ Hit s_hits[kWaves][kAppendCap];
+    __shared__ uint16_t s_sym[256];
+    s_sym[threadIdx.x] = P.sym.code[threadIdx.x];
+    __syncthreads();
+    const int sym_bits = P.sym.bits, exact_len = P.sym.exact_len;
     const int lane = threadIdx.x & 63;
     WaveAppender<Hit, kAppendCap> app{s_hits[threadIdx.x >> 6], 0};
     const int T1 = P.tau + 1;
@@ -536,9 +567,9 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
             uint32_t start = 0, count = 0;
             if (active) {
                 const uint8_t* w = x + p - 1;
-                if (s == 0) h = seg_code(w, sg.len);
-                else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top);
-                const uint64_t key = make_key(l, i, tau, sg.len, h);
+                if (s == 0) h = seg_code(w, sg.len, s_sym, sym_bits, exact_len);
+                else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top, s_sym, sym_bits, exact_len);
+                const uint64_t key = make_key(l, i, tau, sg.len, h, exact_len);
                 if (table_lookup(table, mask, key, &start, &count)) {
                     if (P.self && l == n) {
                         // keep members with g < gx (lists are ascending in g)
@@ -633,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
                                    (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
                 const Seg sg = partition_seg(l, i, tau, dv);
                 bool same = true;
-                if (sg.len > kExactLen)
+                if (sg.len > V.exact_len)
                     for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
                 if (!same) {
                     my_miss += 1;
@@ -841,7 +872,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
                                    (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
                 const Seg sg = partition_seg(l, i, tau, dv);
                 bool same = true;
-                if (sg.len > kExactLen)
+                if (sg.len > V.exact_len)
                     for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
                 if (!same) {
                     my_miss += 1;
@@ -1076,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         if (right) gy[c] = sq[slot];
                         else gy[c] = vals[start + member];
                         y[c] = load_y(gy[c], yr[c]);
-                        if (!right && sgm.len > kExactLen) {
+                        if (!right && sgm.len > V.exact_len) {
                             // hashed key: compare the segment bytes before extension
                             // verification, which skips the segment
                             const LdsChars xs{xl8 + (p - 1)};
@@ -1317,15 +1348,26 @@ hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const in
     return hipGetLastError();
 }
 
+hipError_t launch_byte_presence(const DevSet& S, uint32_t* bitmap, hipStream_t s)
+{
+    if (S.n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<uint64_t>(blocks_for((uint64_t)S.n), 1024);
+    hipLaunchKernelGGL(k_byte_presence, dim3(grid), dim3(kBlock), 0, s, S.sarena, S.slen,
+                       S.lenstart, S.gbase, S.n, bitmap);
+    return hipGetLastError();
+}
+
 hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
-                                int64_t g_first, int64_t g_count, uint64_t* keys, uint32_t* vals,
-                                hipStream_t s)
+                                int64_t g_first, int64_t g_count, const SymMap& sym,
+                                uint64_t* keys, uint32_t* vals, hipStream_t s)
 {
     if (g_count <= 0) return hipSuccess;
+    if (!sym.code || sym.bits < 1 || sym.bits > 9 || sym.exact_len * sym.bits > kHashBits)
+        return hipErrorInvalidValue;
     uint64_t threads = (uint64_t)g_count * (tau + 1);
     hipLaunchKernelGGL(k_emit_segments, dim3(blocks_for(threads)), dim3(kBlock), 0, s, S.sarena,
                        S.slen, S.lenstart, S.gbase, ebase_dev, tau, g_first, g_count,
-                       make_div(tau + 1), keys, vals);
+                       make_div(tau + 1), sym, keys, vals);
     return hipGetLastError();
 }
 
@@ -1377,6 +1419,7 @@ hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hip
 hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s)
 {
     if (P.threads == 0) return hipSuccess;
+    if (!P.sym.code) return hipErrorInvalidValue;
     const uint64_t blocks = std::min<uint64_t>(blocks_for(P.threads), (uint64_t)max_blocks);
     hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(kBlock), 0, s, P, make_div(P.tau + 1));
     return hipGetLastError();

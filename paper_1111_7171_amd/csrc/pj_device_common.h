@@ -101,32 +101,35 @@ __host__ __device__ inline uint64_t mix64(uint64_t x)
     return x;
 }
 
-// Segment code: the raw bytes (big-endian) when len <= kExactLen, else the polynomial hash.
-// Both roll across consecutive start positions.
-__device__ inline uint64_t seg_code(const uint8_t* w, int len)
+// Segment code: the packed symbol codes when len <= exact_len (sym: the indexed set's symbol
+// map, `bits` per symbol), else the polynomial hash of the bytes.  Both roll across consecutive
+// start positions.
+__device__ inline uint64_t seg_code(const uint8_t* w, int len, const uint16_t* sym, int bits,
+                                    int exact_len)
 {
     uint64_t h = 0;
-    if (len <= kExactLen) {
-        for (int k = 0; k < len; ++k) h = (h << 8) | (uint64_t)w[k];
+    if (len <= exact_len) {
+        for (int k = 0; k < len; ++k) h = (h << bits) | (uint64_t)sym[w[k]];
     } else {
         for (int k = 0; k < len; ++k) h = h * kHashBase + (uint64_t)w[k] + 1ull;
     }
     return h;
 }
 
-__device__ inline uint64_t roll_code(uint64_t h, int len, uint8_t out, uint8_t in, uint64_t top)
+__device__ inline uint64_t roll_code(uint64_t h, int len, uint8_t out, uint8_t in, uint64_t top,
+                                     const uint16_t* sym, int bits, int exact_len)
 {
-    if (len <= kExactLen) {
-        const uint64_t mask = (len >= 8) ? ~0ull : ((1ull << (8 * len)) - 1ull);
-        return ((h << 8) | (uint64_t)in) & mask;
+    if (len <= exact_len) {
+        const int nb = len * bits;                      // <= kHashBits
+        return ((h << bits) | (uint64_t)sym[in]) & ((1ull << nb) - 1ull);
     }
     return roll_hash(h, out, in, top);
 }
 
-__device__ inline uint64_t make_key(int l, int i, int tau, int len, uint64_t code)
+__device__ inline uint64_t make_key(int l, int i, int tau, int len, uint64_t code, int exact_len)
 {
     const uint64_t grp = (uint64_t)(l - (tau + 1)) * (uint64_t)(tau + 1) + (uint64_t)(i - 1);
-    const uint64_t c = (len <= kExactLen) ? code : (mix64(code) >> (64 - kHashBits));
+    const uint64_t c = (len <= exact_len) ? code : (mix64(code) >> (64 - kHashBits));
     return (grp << kHashBits) | c;
 }
 

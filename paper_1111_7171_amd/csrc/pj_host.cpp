@@ -314,6 +314,25 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     int64_t E = g_count * T1;
     if (E >= (int64_t)UINT32_MAX) throw Error(PJ_ERANGE, "index too large (%lld entries)", (long long)E);
     X.entries = E;
+    {
+        // symbol map of the bytes the set contains: codes 1..sigma, 0 for absent bytes
+        Workspace& WS = thread_workspace();
+        uint32_t* bm = (uint32_t*)WS.get("index.bytemap", 8 * sizeof(uint32_t));
+        hip_check(hipMemsetAsync(bm, 0, 8 * sizeof(uint32_t), st), "memset");
+        hip_check(launch_byte_presence(D, bm, st), "byte_presence");
+        uint32_t hb[8];
+        hip_check(hipMemcpyAsync(hb, bm, sizeof hb, hipMemcpyDeviceToHost, st), "bytemap");
+        hip_check(hipStreamSynchronize(st), "sync");
+        uint16_t code[256];
+        int sigma = 0;
+        for (int b = 0; b < 256; ++b)
+            code[b] = (hb[b >> 5] >> (b & 31)) & 1u ? (uint16_t)(++sigma) : (uint16_t)0;
+        const int sbits = std::max(1, bitlen((uint64_t)sigma));
+        uint16_t* dcode = (uint16_t*)A.get(nm("sym").c_str(), sizeof code);
+        hip_check(hipMemcpyAsync(dcode, code, sizeof code, hipMemcpyHostToDevice, st), "upload sym");
+        hip_check(hipStreamSynchronize(st), "sync");
+        X.sym = SymMap{dcode, sbits, kHashBits / sbits};
+    }
     if (E == 0) {
         X.keys = (uint64_t*)A.get(nm("keys").c_str(), 16);
         X.vals = (uint32_t*)A.get(nm("vals").c_str(), 16);
@@ -337,7 +356,8 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     uint32_t* vals = (uint32_t*)A.get(nm("vals").c_str(), sizeof(uint32_t) * (size_t)E);
     uint64_t* keys2 = (uint64_t*)W.get("index.keys2", sizeof(uint64_t) * (size_t)E);
     uint32_t* vals2 = (uint32_t*)W.get("index.vals2", sizeof(uint32_t) * (size_t)E);
-    hip_check(launch_emit_segments(D, tau, d_ebase, g_first, g_count, keys, vals, st), "emit");
+    hip_check(launch_emit_segments(D, tau, d_ebase, g_first, g_count, X.sym, keys, vals, st),
+              "emit");
     uint64_t grp_max = (uint64_t)(D.lmax - T1) * T1 + tau;
     int bits = kHashBits + std::max(1, bitlen(grp_max));
     size_t tb = radix_tmp_bytes((uint64_t)E);
@@ -440,6 +460,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         }
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
+        pp.sym = spec.sym;
         pp.hits = J.hits; pp.hit_cap = hit_cap;
         pp.counters = J.counters;
         int k0 = tm.mark();
@@ -540,6 +561,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.nhits = nsmall; vp.ncand = ncand_small;
             vp.tau = tau;
             vp.y_maxlen = Y.lmax;
+            vp.exact_len = spec.sym.exact_len;
             vp.out = J.out; vp.out_cap = cap;
             vp.counters = J.counters;
             int k0 = tm.mark();
@@ -772,6 +794,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     spec.self = self;
     spec.tau = tau;
     spec.X = &X;
+    spec.sym = X.sym;
     run_candidates(P, YY, spec, J, t_stats, tm, st);
     int e3 = tm.mark();
     int32_t *da = nullptr, *db = nullptr;

@@ -104,6 +104,7 @@ struct ProbeSpec {
     const int32_t* q_tau = nullptr;    // device, per sorted position (mixed batch)
     const IndexRef* refs = nullptr;    // device, [kTauMax + 1] (mixed batch)
     uint64_t bound = 0;                // selection bound for a mixed batch (computed by the caller)
+    SymMap sym;                        // the indexed set's symbol map (index keys)
     bool has_entries = true;           // some index has entries
 };
 
@@ -122,6 +123,7 @@ int64_t query_footprint(const pj_index* idx, int n, int tau);
 void index_taus(const pj_index* idx, int* lo, int* hi);
 const DevSet& index_set(const pj_index* idx);
 const IndexRef* index_refs(const pj_index* idx);
+SymMap index_sym(const pj_index* idx);
 bool index_has_entries(const pj_index* idx);
 int64_t query_selections(const pj_index* idx, int n, int tau);
 

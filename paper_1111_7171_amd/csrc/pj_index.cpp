@@ -33,6 +33,7 @@ void validate_host_strings(const pj_strings* S, const char* what);
 
 const DevSet& index_set(const pj_index* idx) { return idx->S; }
 const IndexRef* index_refs(const pj_index* idx) { return idx->refs; }
+SymMap index_sym(const pj_index* idx) { return idx->X.front().sym; }
 bool index_has_entries(const pj_index* idx) { return idx->has_entries; }
 const DevIndex& index_for(const pj_index* idx, int tau) { return idx->X[tau - idx->tau_min]; }
 void index_taus(const pj_index* idx, int* lo, int* hi)
@@ -101,6 +102,7 @@ void run_query_batch(const pj_index* idx, const pj_strings* Q, const int32_t* ta
     spec.refs = idx->refs;
     spec.bound = bound;
     spec.has_entries = idx->has_entries;
+    spec.sym = index_sym(idx);
     JoinScratch J;
     J.mode = PJ_MODE_BATCHED;
     J.tp = tune_lookup(tune_cache, tmax, Q->n ? (double)(Q->offsets[Q->n] - Q->offsets[0]) / (double)Q->n

@@ -26,8 +26,16 @@ constexpr uint64_t kEmptyKey = ~0ull;  // keys use at most 57 bits, so this neve
 
 __host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 15) & ~15); }
 
-// Segments of at most kExactLen bytes are keyed by their raw bytes (exact, no byte guard).
-constexpr int kExactLen = 5;
+// Symbol map of an indexed set: code[b] = 1 + rank of byte b among the bytes the set contains
+// (0: absent), bits = bit length of the largest code.  A segment of at most exact_len =
+// floor(kHashBits / bits) bytes is keyed by its packed codes (exact: no byte guard); a longer
+// one by a hash of its bytes.  A probe segment with an absent byte packs a 0 code, which no
+// indexed key has.
+struct SymMap {
+    const uint16_t* code = nullptr;   // device [256]
+    int bits = 9;
+    int exact_len = kHashBits / 9;
+};
 
 // Length-sorted device arena of one string set.
 struct DevSet {
@@ -47,6 +55,7 @@ struct DevSet {
 // Segment index of one set for one tau.
 struct DevIndex {
     int tau = 0;
+    SymMap sym;
     int64_t entries = 0;                // (string, slot) entries
     int64_t lists = 0;                  // distinct keys (inverted lists)
     uint64_t* keys = nullptr;           // [entries] sorted
@@ -93,6 +102,7 @@ struct ProbeParams {
     unsigned long long* counters;   // [0] hits, [1] candidates, [2] selected
     // device-resident probe count (captured batches): threads = *nx_dev * nl * (tau + 1)
     const uint32_t* nx_dev;
+    SymMap sym;                 // the indexed set's symbol map (keys)
 };
 
 struct VerifyParams {
@@ -111,6 +121,7 @@ struct VerifyParams {
     // device-resident sizes (captured batches): [0] hits, [1] candidates, [2] wave chunks;
     // when set they replace nhits, ncand and the launch's chunk count
     const unsigned long long* dev_counts;
+    int exact_len;              // segments up to this length have exact keys (no byte guard)
 };
 
 // ---- launchers (pj_device.hip) ----
@@ -121,9 +132,11 @@ hipError_t launch_iota_len_keys(const int32_t* offs, int64_t n, uint32_t* keys, 
 hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const int32_t* perm,
                              int64_t n, const int32_t* lenstart, const int64_t* gbase,
                              uint8_t* sarena, uint16_t* slen, hipStream_t s);
+// bytes present in a set's strings: bitmap (8 u32, zeroed by the caller)
+hipError_t launch_byte_presence(const DevSet& S, uint32_t* bitmap, hipStream_t s);
 hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
-                                int64_t g_first, int64_t g_count, uint64_t* keys, uint32_t* vals,
-                                hipStream_t s);
+                                int64_t g_first, int64_t g_count, const SymMap& sym,
+                                uint64_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_mark_heads(const uint64_t* keys, int64_t E, uint32_t* flags, hipStream_t s);
 hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid, int64_t E,
                                    uint32_t* runstart, hipStream_t s);

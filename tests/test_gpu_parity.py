@@ -210,3 +210,55 @@ def test_query_mixed_tau_with_short_strings(seed):
                 exp.append((int(ids[a]), b))
     exp = np.array(sorted(exp), dtype=np.int32).reshape(-1, 2)
     _same(got, exp, f"mixed tau seed={seed}")
+
+
+def test_symbol_map_keys_small_alphabet_long_strings():
+    """Two symbols pack into 2 bits, so segments of up to 20 characters have exact keys and
+    longer ones are hashed; both kinds must give the oracle's candidates and pairs."""
+    rng = np.random.default_rng(61)
+    col = W.random_small(rng, 600, alphabet=b"ab", lmin=30, lmax=70, dup_frac=0.5, kmax=3)
+    for tau in (1, 2, 3):
+        _say("two-symbol alphabet tau", tau)
+        pj = O.self_join_pj(col, tau)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"ab tau={tau}")
+        assert st["candidates"] == pj.candidates and st["cells"] == pj.cells
+
+
+def test_symbol_map_bytes_absent_from_indexed_side():
+    """Probe strings with bytes the indexed set lacks (their code is 0): no false matches."""
+    rng = np.random.default_rng(62)
+    S = W.random_small(rng, 400, alphabet=b"abc", lmin=4, lmax=14, dup_frac=0.3)
+    R0 = W.random_small(rng, 300, alphabet=b"abcxyz", lmin=4, lmax=14, dup_frac=0.3)
+    R = W.from_list(R0.as_list() + S.as_list()[:100])
+    for tau in (0, 1, 2, 3):
+        _say("absent bytes tau", tau)
+        pj = O.join_pj(R, S, tau)
+        got = P.pj_join(R, S, tau)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"absent tau={tau}")
+        assert st["candidates"] == pj.candidates
+
+
+def test_symbol_map_all_byte_values():
+    """All 256 byte values present: 9-bit codes, exact keys up to 4 bytes."""
+    rng = np.random.default_rng(63)
+    base = [bytes(rng.integers(0, 256, size=int(rng.integers(6, 24))).astype(np.uint8))
+            for _ in range(300)]
+    base.append(bytes(range(256))[:40])
+    strs = []
+    for b in base:
+        strs.append(b)
+        e = bytearray(b)
+        if e:
+            e[int(rng.integers(len(e)))] = int(rng.integers(0, 256))
+        strs.append(bytes(e))
+    col = W.from_list(strs)
+    for tau in (1, 2, 3):
+        _say("all bytes tau", tau)
+        pj = O.self_join_pj(col, tau)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"bytes tau={tau}")
+        assert st["candidates"] == pj.candidates
