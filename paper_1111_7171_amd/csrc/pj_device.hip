@@ -1078,12 +1078,20 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             // right-part rows are not spent on lanes whose left part already failed.  Each
             // iteration runs one band DP: a left step (next segment) or a right batch (SEG queued
             // survivors, or the rest once the segments are done).
+            // A part whose two strings are both empty passes with no cells (ED 0 <= t): the
+            // left parts of slot 1 (p = p_1 = 1) and the right parts of slot tau+1 (x and y both
+            // end with the segment).  Then the other part runs directly on the segment members,
+            // without the queue.
+            const bool left_trivial = (p == 1) && (sgm.p == 1);
+            const bool right_trivial = (rx == n) && (ry == l);
             uint32_t qn = 0;    // queued survivors (wave-uniform)
             for (;;) {
-                const bool right = qn >= SEG || (sidx >= s_stop && qn > 0);
+                const bool right = left_trivial ? sidx < s_stop
+                                                : (qn >= SEG || (sidx >= s_stop && qn > 0));
                 if (!right && sidx >= s_stop) break;
-                const uint32_t k = right ? (qn < SEG ? qn : SEG) : 0;
-                if (right) {
+                const bool from_queue = right && !left_trivial;
+                const uint32_t k = from_queue ? (qn < SEG ? qn : SEG) : 0;
+                if (from_queue) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1100,14 +1108,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                 for (int c = 0; c < NC; ++c) {
                     const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
                     const uint32_t member = sidx * SEG + slot;
-                    ok[c] = right ? slot < k : member < count;
+                    ok[c] = from_queue ? slot < k : member < count;
                     gy[c] = 0;
                     y[c] = V.y_arena;
                     if (ok[c]) {
-                        if (right) gy[c] = sq[slot];
+                        if (from_queue) gy[c] = sq[slot];
                         else gy[c] = vals[start + member];
                         y[c] = load_y(gy[c], yr[c]);
-                        if (!right && sgm.len > V.exact_len) {
+                        if (!from_queue && sgm.len > V.exact_len) {
                             // hashed key: compare the segment bytes before extension
                             // verification, which skips the segment
                             const LdsChars xs{xl8 + (p - 1)};
@@ -1149,11 +1157,17 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         ok[c] = ok[c] && d[c] <= tt;
                     }
                 }
-                if (right) {
+                if (right || right_trivial) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c)
                         acc.push(ok[c], ((uint64_t)gx << 32) | gy[c], V.out, V.out_cap,
                                  &V.counters[3]);
+                }
+                if (!from_queue) {
+                    ++sidx;
+                    ++sg_i;
+                }
+                if (from_queue) {
                     // move the rest of the queue to its front (all reads before the writes)
                     const uint32_t rest = qn - k;
                     uint32_t mv[NC];
@@ -1168,7 +1182,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         if (slot < rest) sq[slot] = mv[c];
                     }
                     qn = rest;
-                } else {
+                } else if (!right && !right_trivial) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         const uint64_t surv = __builtin_amdgcn_ballot_w64(ok[c]);
@@ -1178,8 +1192,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] = gy[c];
                         qn += (uint32_t)__builtin_popcountll(surv);
                     }
-                    ++sidx;
-                    ++sg_i;
                 }
             }
             ++h;
