@@ -1109,11 +1109,17 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
                     const uint32_t member = sidx * SEG + slot;
                     ok[c] = from_queue ? slot < k : member < count;
+                    // the two sources in separate uniform branches (one merged load would be a
+                    // flat load of LDS or global memory)
                     gy[c] = 0;
+                    if (from_queue) {
+                        const uint32_t q = sq[slot];          // slot < 2 * SEG: in bounds
+                        gy[c] = ok[c] ? q : 0u;
+                    } else if (ok[c]) {
+                        gy[c] = vals[start + member];
+                    }
                     y[c] = V.y_arena;
                     if (ok[c]) {
-                        if (from_queue) gy[c] = sq[slot];
-                        else gy[c] = vals[start + member];
                         y[c] = load_y(gy[c], yr[c]);
                         if (!from_queue && sgm.len > V.exact_len) {
                             // hashed key: compare the segment bytes before extension
