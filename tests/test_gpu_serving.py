@@ -156,3 +156,51 @@ def test_captured_batch_falls_back_on_overflow():
         assert np.array_equal(got_big, exp_big)
     finally:
         idx.free()
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_captured_batches_with_short_strings(seed):
+    """Indexed and query strings shorter than tau + 1 (the side path inside the captured graph),
+    per-query thresholds from 0 to 6: the server's pairs equal pj_query's and the oracle's."""
+    rng = np.random.default_rng(5000 + seed)
+    S = W.random_small(rng, 400, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.4)
+    idx = P.pj_build_index(S, 0, 6)
+    try:
+        reqs = []
+        for _ in range(6):
+            Q = W.random_small(rng, 40, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.2)
+            reqs.append((Q, rng.integers(0, 7, size=Q.n).astype(np.int32)))
+        with P.Server(idx, slots=2, max_batch_queries=128) as srv:
+            ids = [srv.submit(q, t) for q, t in reqs]
+            got = [srv.wait(i)[0] for i in ids]
+        for (Q, T), g in zip(reqs, got):
+            exp = []
+            for t in range(0, 7):
+                ids_t = np.nonzero(T == t)[0]
+                if len(ids_t):
+                    for a, b in O.join_bf(Q.subset(ids_t), S, t, 4).tolist():
+                        exp.append((int(ids_t[a]), b))
+            exp = np.array(sorted(exp), dtype=np.int32).reshape(-1, 2)
+            assert np.array_equal(g, exp)
+            assert np.array_equal(g, P.pj_query(idx, Q, T))
+    finally:
+        idx.free()
+
+
+def test_captured_batches_index_tau_range_above_zero():
+    """An index over tau 2..5 served with thresholds in that range (captured path)."""
+    S = W.cfg5_index(5_000)
+    rng = np.random.default_rng(88)
+    idx = P.pj_build_index(S, 2, 5)
+    try:
+        Q, _ = W.cfg5_batch(rng, S, mean=48)
+        T = rng.integers(2, 6, size=Q.n).astype(np.int32)
+        exp = P.pj_query(idx, Q, T)
+        with P.Server(idx, slots=1) as srv:
+            got, _ = srv.wait(srv.submit(Q, T))
+        assert np.array_equal(got, exp)
+        with pytest.raises(P.PassJoinError):
+            with P.Server(idx, slots=1) as srv:
+                srv.submit(Q, np.ones(Q.n, np.int32))       # tau 1 is outside the index
+    finally:
+        idx.free()
