@@ -43,8 +43,8 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     cache = str(tmp_path / "tune.txt")
     _say("pj_tune cfg2 n=20000 tau=3")
     r = P.pj_tune(col, 3, tune_cache=cache)
-    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128, 256)
-    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128)
+    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128, 256, 512)
+    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
     assert r["big_list"] in (16, 32, 64, 128)
     assert r["probe_blocks_per_cu"] in (4, 8, 16)
     assert r["lane_cands"] in (1, 2)
@@ -68,7 +68,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert sorted(t for _, t, _, _, _ in _read_cache(cache)) == [2, 3]
 
 
-@pytest.mark.parametrize("params", [(8, 1, 16, 4, 1), (256, 128, 128, 16, 2), (16, 2, 64, 8, 2),
+@pytest.mark.parametrize("params", [(8, 1, 16, 4, 1), (512, 512, 128, 16, 2), (16, 2, 64, 8, 2),
                                     (32, 4, 32, 8, 1)])
 def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     # the list-segment kernel at these sizes needs the slot bucketing forced on
