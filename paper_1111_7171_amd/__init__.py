@@ -95,6 +95,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise PassJoinError(PJ_EDEVICE, f"{LIB_PATH} is not built; run "
                                 "`python -m paper_1111_7171_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own copy of the runtime under the same
+        # soname.  Loaded first, it is the one libpassjoin.so binds to; loaded after the
+        # system's, PyTorch would bring in a second runtime that finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         sp, pp, op = C.POINTER(PjStrings), C.POINTER(PjPairs), C.POINTER(PjOptions)
         lib.pj_self_join.argtypes = [sp, C.c_int32, op, pp]
@@ -232,10 +239,11 @@ def _hip_d2h(host: np.ndarray, dev_ptr: int):
     """Copies device memory into a host array with the HIP runtime's hipMemcpy."""
     global _hip
     if _hip is None:
-        _hip = C.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
-        _hip.hipMemcpy.restype = C.c_int
-    rc = _hip.hipMemcpy(host.ctypes.data, dev_ptr, host.nbytes, 2)   # hipMemcpyDeviceToHost
+        # the runtime libpassjoin.so is bound to (resolved through the library's own handle)
+        _hip = load().hipMemcpy
+        _hip.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.restype = C.c_int
+    rc = _hip(host.ctypes.data, dev_ptr, host.nbytes, 2)   # hipMemcpyDeviceToHost
     if rc != 0:
         raise PassJoinError(PJ_EDEVICE, f"hipMemcpy failed ({rc})")
 

@@ -45,17 +45,35 @@ def cfg2():
     return W.cfg2()
 
 
-@pytest.mark.parametrize("tau", [1, 2, 3, 4])
-def test_cfg2_full(cfg2, tau):
-    _say("cfg2 full tau", tau)
-    dp = P.pj_self_join(_device(cfg2), tau, outputs_on_device=True)
+@pytest.fixture(scope="module")
+def cfg2_tuned(cfg2, tmp_path_factory):
+    """The launch parameters bench.py times: tuned on this workload, per tau."""
+    cache = str(tmp_path_factory.mktemp("tune") / "tune.txt")
+    for tau in (1, 2, 3, 4):
+        _say("tuning cfg2 tau", tau)
+        P.pj_tune(cfg2, tau, tune_cache=cache)
+    return cache
+
+
+def _join_dev(col, tau, **kw):
+    dp = P.pj_self_join(_device(col), tau, outputs_on_device=True, **kw)
     try:
-        pairs = dp.to_numpy()
+        return dp.to_numpy(), P.pj_last_stats()
     finally:
         dp.free()
-    st = P.pj_last_stats()
+
+
+@pytest.mark.parametrize("tau", [1, 2, 3, 4])
+def test_cfg2_full(cfg2, cfg2_tuned, tau):
+    _say("cfg2 full tau", tau, "(tuned launch parameters)")
+    pairs, st = _join_dev(cfg2, tau, tune_cache=cfg2_tuned)
     _say("  pairs", len(pairs), "candidates", st["candidates"])
     _check(cfg2, pairs, tau, 64, 100 + tau)
+    # the built-in defaults give the same result and the same counts
+    pairs0, st0 = _join_dev(cfg2, tau)
+    assert np.array_equal(pairs0, pairs)
+    for k in ("candidates", "cells", "accepted", "hits", "selected"):
+        assert st0[k] == st[k], k
 
 
 @pytest.mark.parametrize("tau", [2, 4, 6, 8])
