@@ -403,6 +403,22 @@ __device__ inline BandLanes band_lanes(LdsChars U, int lu, int lv, int t, int la
     return B;
 }
 
+// Cells of rows 1..s of the band of Lemma 4 (a cells left of the diagonal, b right of it),
+// clipped to columns 1..nc: the sum over rows i of |[max(1, i - a), min(nc, i + b)]|, in closed
+// form.  Rows i <= nc - b reach the right end i + b; rows i <= a + 1 start at column 1.
+__device__ inline int band_cells(int s, int nc, int a, int b)
+{
+    // every operand is in [0, 2047] (|delta| <= t keeps a, b >= 0), so the full-rate 24-bit
+    // multiplier is exact; the halved terms are even and non-negative
+    const unsigned us = s, unc = nc, ua = a, ub = b;
+    const unsigned c1 = min(max(nc - b, 0), s);  // rows whose right end is i + b
+    const unsigned hi = (__umul24(c1, c1 + 1) >> 1) + __umul24(ub, c1) + __umul24(us - c1, unc);
+    const unsigned c2 = min(a + 1, s);           // rows whose left end is column 1
+    const unsigned lo =
+        c2 + ((__umul24(us, us + 1) - __umul24(c2, c2 + 1)) >> 1) - __umul24(ua, us - c2);
+    return (int)(hi - lo + us);
+}
+
 // NC candidates per lane (members of the same list, so the same probe-string part and band):
 // the scalar work of a row (band bounds, shared characters, cell count, loop control) is shared
 // by all of them.  A candidate with act[c] false is dead from the start (cells 0, result t+1).
@@ -445,15 +461,15 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
     }
     int idx_in = MAXW - a;                       // column character entering after row 1
     int ai_pre = (!YROWS && nr > 0) ? U[0] : 256;
-    int cum = 0;                                 // recurrence cells of rows 1..i (uniform)
-    int stop_cells[NC];
+    int stop_row[NC];                            // rows evaluated before the candidate died
     bool live[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        stop_cells[c] = 0;
+        stop_row[c] = 0;
         live[c] = act[c];
     }
-    for (int i = 1; i <= nr; ++i) {
+    int i = 1;
+    for (; i <= nr; ++i) {
         // row characters: the lanes' own (registers) or the shared one, read a row ahead
         int ai[NC], ai_next = 256;
         if (YROWS) {
@@ -467,7 +483,7 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
         int cin[NW];                             // column characters entering after the row
         const bool cin_ok = (unsigned)idx_in < (unsigned)nc;
         if (YROWS) {
-            cin[0] = cin_ok ? __builtin_amdgcn_readfirstlane(U[idx_in]) : 256;
+            cin[0] = cin_ok ? U[idx_in] : 256;     // vector registers: the shift is VALU work
         } else {
 #pragma unroll
             for (int c = 0; c < NW; ++c) cin[c] = cin_ok ? V[c][idx_in] : 256;
@@ -495,13 +511,11 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
             if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
             anyc[c] = emin <= t;
         }
-        const int j0 = i - a;
-        cum += max(0, min(nc, j0 + W - 1) - max(1, j0) + 1);
         bool anylive = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const bool now = live[c] && anyc[c];
-            if (live[c] && !now) stop_cells[c] = cum;
+            if (live[c] && !now) stop_row[c] = i;
             live[c] = now;
             anylive = anylive || now;
         }
@@ -518,7 +532,7 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (!act[c]) continue;
-        cells[c] = live[c] ? cum : stop_cells[c];
+        cells[c] = band_cells(live[c] ? nr : stop_row[c], nc, a, b);
         if (live[c]) {
             int out = BIG;
 #pragma unroll
