@@ -940,27 +940,29 @@ __global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __r
     first[ch] = (uint32_t)a;
 }
 
-template <int MAXW, bool EXACT, int NC, typename LaneChars>
+template <int MAXW, int NC, typename LaneChars>
 __device__ inline void vsp_seg_any(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
                                    int lv, int t, BandLanes BL, const bool (&act)[NC],
                                    int (&cells)[NC], int (&res)[NC])
 {
-    if (yrows) vsp_seg<MAXW, EXACT, true, NC>(U, lu, V, lv, t, BL, act, cells, res);
-    else vsp_seg<MAXW, EXACT, false, NC>(U, lu, V, lv, t, BL, act, cells, res);
+    if (yrows) vsp_seg<MAXW, true, NC>(U, lu, V, lv, t, BL, act, cells, res);
+    else vsp_seg<MAXW, false, NC>(U, lu, V, lv, t, BL, act, cells, res);
 }
 
-// exact band width for uniform t < min(9, GMAXW), else the width class GMAXW
+// band width t + 1 for a uniform t <= 8 below the width class, else the class width GMAXW
 template <int GMAXW, int NC, typename LaneChars>
 __device__ inline void vsp_seg_dispatch(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
                                         int lv, int t, BandLanes BL, const bool (&act)[NC],
                                         int (&cells)[NC], int (&res)[NC])
 {
+    if (t + 1 >= GMAXW || t > 8) {
+        vsp_seg_any<GMAXW, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);
+        return;
+    }
 #define PJ_SEG_CASE(T)                                                                      \
     case T:                                                                                 \
-        if constexpr (T + 1 <= GMAXW)                                                       \
-            vsp_seg_any<T + 1, true, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);      \
-        else                                                                                \
-            vsp_seg_any<GMAXW, false, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);     \
+        if constexpr (T + 1 < GMAXW)                                                        \
+            vsp_seg_any<T + 1, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);            \
         break;
     switch (t) {
     PJ_SEG_CASE(0)
@@ -972,7 +974,7 @@ __device__ inline void vsp_seg_dispatch(bool yrows, LdsChars U, int lu, const La
     PJ_SEG_CASE(6)
     PJ_SEG_CASE(7)
     PJ_SEG_CASE(8)
-    default: vsp_seg_any<GMAXW, false, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res); break;
+    default: break;
     }
 #undef PJ_SEG_CASE
 }
@@ -993,7 +995,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         uint64_t nchunks, uint32_t seg_chunk)
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
-    __shared__ uint32_t s_x[kWaves][(kLenMax + 4) / 4];   // the current probe string
+    // the current probe string; the band DP may read up to MAXW + t <= 127 bytes past its end
+    __shared__ uint32_t s_x[kWaves][(kLenMax + 1 + 128 + 3) / 4];
     __shared__ uint32_t s_q[kWaves][256];                 // left-part survivors (gy)
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;

@@ -368,13 +368,22 @@ struct LdsChars {
 //  * cells right of column nc are never an input of a cell inside the matrix, and their
 //    expected distance exceeds that of cell (i, nc), which is in the band whenever they are,
 //    so they change neither a row's stop test nor the result;
-//  * the band's outer neighbours (left of index 0, above index W-1) read as BIG.
+//  * band indices W..MAXW-1 (right of the band, when MAXW > W) are computed like the others,
+//    without a mask: the values are then those of a DP restricted to a wider band, at most the
+//    banded ones.  Reaching a cell at diagonal offset j - i > b costs at least j - i, so its
+//    expected distance is at least (j - i) + |delta - (j - i)| >= t + 1, and any value that
+//    improves on the banded one through such a cell inherits that bound: every row's test,
+//    and the result once saturated at t+1, are those of the band of Lemma 4;
+//  * the outer neighbours (left of index 0, above index MAXW-1) read as BIG.
+// So the characters of columns outside 1..nc are never needed: a window slot there may hold any
+// byte (the probe string's LDS buffer is padded so that such reads stay inside it).
 // Values are not saturated at t+1: min(v, t+1) commutes with the recurrence, so stop rows
 // and verdicts are those of the saturated form.  The expected distance M + |delta + a - k|
 // never decreases along a step of the recurrence, so once a row has no cell with expected
 // distance <= t no later row has one: a lane is live exactly while its current row passes,
-// and it stops at its first failing row.
-// EXACT: MAXW == t + 1, so only the last band index can lie outside the band (W >= MAXW - 1).
+// and it stops at its first failing row.  A lane therefore only counts the rows it passed
+// (rows evaluated = passes + 1 if it stopped, nr if it passed them all), and a candidate
+// that is not active starts with every band cell at BIG, so it never passes a row.
 // Row 0, the expected-distance offsets |kfin - k| and (rows from y) the first column window of
 // one part's band, one band index k per lane.  Computed while the whole wave is active: the
 // verification reads entry k back from lane k with readlane, which also reads lanes that are
@@ -422,7 +431,7 @@ __device__ inline int band_cells(int s, int nc, int a, int b)
 // NC candidates per lane (members of the same list, so the same probe-string part and band):
 // the scalar work of a row (band bounds, shared characters, cell count, loop control) is shared
 // by all of them.  A candidate with act[c] false is dead from the start (cells 0, result t+1).
-template <int MAXW, bool EXACT, bool YROWS, int NC, typename LaneChars>
+template <int MAXW, bool YROWS, int NC, typename LaneChars>
 __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int lv, int t,
                                BandLanes BL, const bool (&act)[NC], int (&cells)[NC],
                                int (&res)[NC])
@@ -439,7 +448,6 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
     if (delta > t) return;
     const int a = (t - delta) >> 1;
     const int b = (t + delta) >> 1;
-    const int W = a + b + 1;
     const int kfin = delta + a;                  // band index of the last cell (nr, nc)
     constexpr int BIG = 1 << 20;
     constexpr int NW = YROWS ? 1 : NC;           // column windows: shared (YROWS) or per candidate
@@ -448,7 +456,7 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
     for (int k = 0; k < MAXW; ++k) {
         const int r0 = __builtin_amdgcn_readlane(BL.r0, k);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) R[c][k] = r0;
+        for (int c = 0; c < NC; ++c) R[c][k] = act[c] ? r0 : BIG;
         ek[k] = __builtin_amdgcn_readlane(BL.ek, k);
         if (YROWS) {
             w[0][k] = __builtin_amdgcn_readlane(BL.w0, k);
@@ -461,79 +469,89 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
     }
     int idx_in = MAXW - a;                       // column character entering after row 1
     int ai_pre = (!YROWS && nr > 0) ? U[0] : 256;
-    int stop_row[NC];                            // rows evaluated before the candidate died
-    bool live[NC];
+    int passes[NC];                              // rows passed (a prefix of the rows)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        stop_row[c] = 0;
-        live[c] = act[c];
-    }
-    int i = 1;
-    for (; i <= nr; ++i) {
-        // row characters: the lanes' own (registers) or the shared one, read a row ahead
-        int ai[NC], ai_next = 256;
-        if (YROWS) {
+    for (int c = 0; c < NC; ++c) passes[c] = 0;
+    // Narrow bands unroll the row loop MAXW times and rotate the column window by renaming:
+    // at unrolled step u band index k reads slot (u + k) % MAXW, and the entering column
+    // character replaces slot u, so no register moves per row.  Wider bands shift the window.
+    constexpr bool ROT = MAXW <= 9;
+    constexpr int UNROLL = ROT ? MAXW : 1;
+    int row = 1;
+    bool go = nr > 0;
+    while (go) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ai[c] = V[c][i - 1];
-        } else {
+        for (int u = 0; u < UNROLL; ++u) {
+            // the row index is uniform (the loop exits on a wave vote), but the compiler does
+            // not see it; as a scalar, register-array reads at it stay single moves
+            const int i = __builtin_amdgcn_readfirstlane(row);
+            // row characters: the lanes' own (registers) or the shared one, read a row ahead
+            // (U[nr] lies inside the padded buffer)
+            int ai[NC];
+            if (YROWS) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ai[c] = ai_pre;
-            if (i < nr) ai_next = U[i];
-        }
-        int cin[NW];                             // column characters entering after the row
-        const bool cin_ok = (unsigned)idx_in < (unsigned)nc;
-        if (YROWS) {
-            cin[0] = cin_ok ? U[idx_in] : 256;     // vector registers: the shift is VALU work
-        } else {
+                for (int c = 0; c < NC; ++c) ai[c] = V[c][i - 1];
+            } else {
 #pragma unroll
-            for (int c = 0; c < NW; ++c) cin[c] = cin_ok ? V[c][idx_in] : 256;
-        }
-        bool anyc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int* wc = w[YROWS ? 0 : c];
-            int left = BIG;
-            int e[MAXW];
-#pragma unroll
-            for (int k = 0; k < MAXW; ++k) {
-                const int up = (k + 1 < MAXW) ? R[c][(k + 1) < MAXW ? k + 1 : k] : BIG;
-                // min(up + 1, left + 1, diag + d) as min(up, left, diag - [match]) + 1
-                const int dg = R[c][k] - ((ai[c] == wc[k]) ? 1 : 0);
-                int v = min(min(up, left), dg) + 1;
-                if (!EXACT || k == MAXW - 1) v = (k < W) ? v : BIG;
-                e[k] = v + ek[k];
-                R[c][k] = v;
-                left = v;
+                for (int c = 0; c < NC; ++c) ai[c] = ai_pre;
+                ai_pre = U[i];
             }
-            int emin = e[0];
+            int cin[NW];                         // column characters entering after the row
+            if (YROWS) {
+                cin[0] = U[idx_in];              // past nc: any byte of the padded buffer
+            } else {
+                const bool cin_ok = (unsigned)idx_in < (unsigned)nc;
 #pragma unroll
-            for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(e[k], e[k + 1]));
-            if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
-            anyc[c] = emin <= t;
+                for (int c = 0; c < NW; ++c) cin[c] = cin_ok ? V[c][idx_in] : 256;
+            }
+            bool anyc = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int* wc = w[YROWS ? 0 : c];
+                int left = BIG;
+                int e[MAXW];
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) {
+                    const int up = (k + 1 < MAXW) ? R[c][(k + 1) < MAXW ? k + 1 : k] : BIG;
+                    // min(up + 1, left + 1, diag + d) as min(up, left, diag - [match]) + 1
+                    const int dg = R[c][k] - ((ai[c] == wc[(u + k) % MAXW]) ? 1 : 0);
+                    const int v = min(min(up, left), dg) + 1;
+                    e[k] = v + ek[k];
+                    R[c][k] = v;
+                    left = v;
+                }
+                int emin = e[0];
+#pragma unroll
+                for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(e[k], e[k + 1]));
+                if ((MAXW & 1) == 0) emin = min(emin, e[MAXW - 1]);
+                const bool pass = emin <= t;
+                passes[c] += pass ? 1 : 0;
+                anyc = anyc || pass;
+            }
+            if (__builtin_amdgcn_ballot_w64(anyc) == 0 || i == nr) {
+                go = false;
+                break;
+            }
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                if (ROT) {
+                    w[c][u] = cin[c];
+                } else {
+#pragma unroll
+                    for (int k = 0; k + 1 < MAXW; ++k) w[c][k] = w[c][k + 1];
+                    w[c][MAXW - 1] = cin[c];
+                }
+            }
+            ++idx_in;
+            ++row;
         }
-        bool anylive = false;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const bool now = live[c] && anyc[c];
-            if (live[c] && !now) stop_row[c] = i;
-            live[c] = now;
-            anylive = anylive || now;
-        }
-        if (__builtin_amdgcn_ballot_w64(anylive) == 0) break;
-#pragma unroll
-        for (int c = 0; c < NW; ++c) {
-#pragma unroll
-            for (int k = 0; k + 1 < MAXW; ++k) w[c][k] = w[c][k + 1];
-            w[c][MAXW - 1] = cin[c];
-        }
-        ++idx_in;
-        ai_pre = ai_next;
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (!act[c]) continue;
-        cells[c] = band_cells(live[c] ? nr : stop_row[c], nc, a, b);
-        if (live[c]) {
+        const bool all = passes[c] == nr;
+        cells[c] = band_cells(all ? nr : passes[c] + 1, nc, a, b);
+        if (all) {
             int out = BIG;
 #pragma unroll
             for (int k = 0; k < MAXW; ++k)
