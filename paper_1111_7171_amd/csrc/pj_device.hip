@@ -940,29 +940,31 @@ __global__ __launch_bounds__(kBlock) void k_seg_chunk_starts(const uint32_t* __r
     first[ch] = (uint32_t)a;
 }
 
-template <int MAXW, int NC, typename LaneChars>
+using LdsInts = const __attribute__((address_space(3))) int*;
+
+template <int MAXW, int NC, int TS, typename LaneChars>
 __device__ inline void vsp_seg_any(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
-                                   int lv, int t, BandLanes BL, const bool (&act)[NC],
+                                   int lv, int t, LdsInts tab, const bool (&act)[NC],
                                    int (&cells)[NC], int (&res)[NC])
 {
-    if (yrows) vsp_seg<MAXW, true, NC>(U, lu, V, lv, t, BL, act, cells, res);
-    else vsp_seg<MAXW, false, NC>(U, lu, V, lv, t, BL, act, cells, res);
+    if (yrows) vsp_seg<MAXW, true, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
+    else vsp_seg<MAXW, false, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
 }
 
 // band width t + 1 for a uniform t <= 8 below the width class, else the class width GMAXW
-template <int GMAXW, int NC, typename LaneChars>
+template <int GMAXW, int NC, int TS, typename LaneChars>
 __device__ inline void vsp_seg_dispatch(bool yrows, LdsChars U, int lu, const LaneChars (&V)[NC],
-                                        int lv, int t, BandLanes BL, const bool (&act)[NC],
+                                        int lv, int t, LdsInts tab, const bool (&act)[NC],
                                         int (&cells)[NC], int (&res)[NC])
 {
     if (t + 1 >= GMAXW || t > 8) {
-        vsp_seg_any<GMAXW, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);
+        vsp_seg_any<GMAXW, NC, TS>(yrows, U, lu, V, lv, t, tab, act, cells, res);
         return;
     }
 #define PJ_SEG_CASE(T)                                                                      \
     case T:                                                                                 \
         if constexpr (T + 1 < GMAXW)                                                        \
-            vsp_seg_any<T + 1, NC>(yrows, U, lu, V, lv, t, BL, act, cells, res);            \
+            vsp_seg_any<T + 1, NC, TS>(yrows, U, lu, V, lv, t, tab, act, cells, res);       \
         break;
     switch (t) {
     PJ_SEG_CASE(0)
@@ -998,6 +1000,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
     // the current probe string; the band DP may read up to MAXW + t <= 127 bytes past its end
     __shared__ uint32_t s_x[kWaves][(kLenMax + 1 + 128 + 3) / 4];
     __shared__ uint32_t s_q[kWaves][256];                 // left-part survivors (gy)
+    // band tables of the current hit's two parts (row 0, distance offsets, first window)
+    constexpr int BTS = (GMAXW + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) int s_band[kWaves][2][3 * BTS];
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     uint32_t* sx = s_x[threadIdx.x >> 6];
@@ -1052,8 +1057,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             // with t = tau+1-i (Algorithm 3)
             const int tl = i - 1, tr = tau + 1 - i;
             const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
-            const BandLanes bl = band_lanes(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane);
-            const BandLanes br = band_lanes(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane);
+            // the previous hit's table reads were issued before these writes
+            __attribute__((address_space(3))) int* tab_l =
+                (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][0];
+            __attribute__((address_space(3))) int* tab_r =
+                (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][1];
+            band_table(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane, BTS, tab_l);
+            band_table(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane, BTS, tab_r);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // NC candidates per lane: a list segment has 64 * NC members
             constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
             constexpr uint32_t SEG = 64u * NC;
@@ -1099,9 +1112,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                // the part's band set-up, selected with the whole wave active
-                BandLanes bd = right ? br : bl;
-                asm volatile("" : "+v"(bd.r0), "+v"(bd.ek), "+v"(bd.w0));
                 uint32_t gy[NC];
                 uint32_t yr[NC][REGY > 0 ? REGY / 4 : 1];
                 const uint8_t* y[NC];
@@ -1151,14 +1161,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         RegChars vc[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) vc[c] = RegChars{yr[c], yo};
-                        vsp_seg_dispatch<GMAXW, NC>(yl <= xl, LdsChars{xl8 + xo}, xl, vc, yl, tt,
-                                                    bd, ok, cl, d);
+                        vsp_seg_dispatch<GMAXW, NC, BTS>(yl <= xl, LdsChars{xl8 + xo}, xl, vc,
+                                                         yl, tt, right ? tab_r : tab_l, ok, cl,
+                                                         d);
                     } else {
                         GlobalChars vc[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) vc[c] = GlobalChars{y[c] + yo};
-                        vsp_seg_dispatch<GMAXW, NC>(yl <= xl, LdsChars{xl8 + xo}, xl, vc, yl, tt,
-                                                    bd, ok, cl, d);
+                        vsp_seg_dispatch<GMAXW, NC, BTS>(yl <= xl, LdsChars{xl8 + xo}, xl, vc,
+                                                         yl, tt, right ? tab_r : tab_l, ok, cl,
+                                                         d);
                     }
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {

@@ -385,14 +385,11 @@ struct LdsChars {
 // (rows evaluated = passes + 1 if it stopped, nr if it passed them all), and a candidate
 // that is not active starts with every band cell at BIG, so it never passes a row.
 // Row 0, the expected-distance offsets |kfin - k| and (rows from y) the first column window of
-// one part's band, one band index k per lane.  Computed while the whole wave is active: the
-// verification reads entry k back from lane k with readlane, which also reads lanes that are
-// inactive at that point.
-struct BandLanes {
-    int r0, ek, w0;
-};
-
-__device__ inline BandLanes band_lanes(LdsChars U, int lu, int lv, int t, int lane)
+// one part's band, as a table in the wave's LDS: entry k of each of the three rows of TS
+// ints.  Written once per hit by lanes k < TS (every lane computes its entry), then read by
+// every candidate's DP with broadcast loads.
+__device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, int ts,
+                                  __attribute__((address_space(3))) int* tab)
 {
     const bool yrows = lv <= lu;
     const int nr = yrows ? lv : lu;
@@ -402,14 +399,14 @@ __device__ inline BandLanes band_lanes(LdsChars U, int lu, int lv, int t, int la
     const int b = (t + delta) >> 1;
     const int kfin = delta + a;
     const int jl = lane - a;
-    BandLanes B;
-    B.r0 = ((unsigned)jl <= (unsigned)min(nc, b)) ? jl : (1 << 20);
-    B.ek = kfin - lane < 0 ? lane - kfin : kfin - lane;
-    B.w0 = (yrows && (unsigned)jl < (unsigned)nc) ? U[jl] : 256;
-    // define the three values here, with every lane active, so that they are not recomputed
-    // later inside a branch that only some lanes take
-    asm volatile("" : "+v"(B.r0), "+v"(B.ek), "+v"(B.w0));
-    return B;
+    const int r0 = ((unsigned)jl <= (unsigned)min(nc, b)) ? jl : (1 << 20);
+    const int ek = kfin - lane < 0 ? lane - kfin : kfin - lane;
+    const int w0 = (yrows && (unsigned)jl < (unsigned)nc) ? U[jl] : 256;
+    if (lane < ts) {
+        tab[lane] = r0;
+        tab[ts + lane] = ek;
+        tab[2 * ts + lane] = w0;
+    }
 }
 
 // Cells of rows 1..s of the band of Lemma 4 (a cells left of the diagonal, b right of it),
@@ -431,10 +428,10 @@ __device__ inline int band_cells(int s, int nc, int a, int b)
 // NC candidates per lane (members of the same list, so the same probe-string part and band):
 // the scalar work of a row (band bounds, shared characters, cell count, loop control) is shared
 // by all of them.  A candidate with act[c] false is dead from the start (cells 0, result t+1).
-template <int MAXW, bool YROWS, int NC, typename LaneChars>
+template <int MAXW, bool YROWS, int NC, int TS, typename LaneChars>
 __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int lv, int t,
-                               BandLanes BL, const bool (&act)[NC], int (&cells)[NC],
-                               int (&res)[NC])
+                               const __attribute__((address_space(3))) int* tab,
+                               const bool (&act)[NC], int (&cells)[NC], int (&res)[NC])
 {
     static_assert(MAXW <= 64, "one band index per lane");
     const int nr = YROWS ? lv : lu;
@@ -454,12 +451,12 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
     int R[NC][MAXW], w[NW][MAXW], ek[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) {
-        const int r0 = __builtin_amdgcn_readlane(BL.r0, k);
+        const int r0 = tab[k];
 #pragma unroll
         for (int c = 0; c < NC; ++c) R[c][k] = act[c] ? r0 : BIG;
-        ek[k] = __builtin_amdgcn_readlane(BL.ek, k);
+        ek[k] = tab[TS + k];
         if (YROWS) {
-            w[0][k] = __builtin_amdgcn_readlane(BL.w0, k);
+            w[0][k] = tab[2 * TS + k];
         } else {
             const int idx = k - a;
 #pragma unroll
@@ -546,18 +543,15 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
             ++row;
         }
     }
+    const int kf = __builtin_amdgcn_readfirstlane(kfin);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (!act[c]) continue;
+        // branch-free: every lane takes the same path
         const bool all = passes[c] == nr;
-        cells[c] = band_cells(all ? nr : passes[c] + 1, nc, a, b);
-        if (all) {
-            int out = BIG;
-#pragma unroll
-            for (int k = 0; k < MAXW; ++k)
-                if (k == kfin) out = R[c][k];
-            res[c] = min(out, t + 1);
-        }
+        const int nrows = all ? nr : passes[c] + 1;
+        const int out = min(R[c][kf], t + 1);
+        cells[c] = act[c] ? band_cells(nrows, nc, a, b) : 0;
+        res[c] = (act[c] && all) ? out : t + 1;
     }
 }
 
