@@ -947,8 +947,14 @@ __device__ inline void vsp_seg_any(bool yrows, LdsChars U, int lu, const LaneCha
                                    int lv, int t, LdsInts tab, const bool (&act)[NC],
                                    int (&cells)[NC], int (&res)[NC])
 {
-    if (yrows) vsp_seg<MAXW, true, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
-    else vsp_seg<MAXW, false, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
+    if constexpr (NC == 2) {
+        // two candidates per lane: the packed 16-bit DP (register strings only)
+        if (yrows) vsp_seg2<MAXW, true, TS>(U, lu, V, lv, t, tab, act, cells, res);
+        else vsp_seg2<MAXW, false, TS>(U, lu, V, lv, t, tab, act, cells, res);
+    } else {
+        if (yrows) vsp_seg<MAXW, true, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
+        else vsp_seg<MAXW, false, NC, TS>(U, lu, V, lv, t, tab, act, cells, res);
+    }
 }
 
 // band width t + 1 for a uniform t <= 8 below the width class, else the class width GMAXW
@@ -1057,18 +1063,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             // with t = tau+1-i (Algorithm 3)
             const int tl = i - 1, tr = tau + 1 - i;
             const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
+            // NC candidates per lane: a list segment has 64 * NC members
+            constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
             // the previous hit's table reads were issued before these writes
             __attribute__((address_space(3))) int* tab_l =
                 (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][0];
             __attribute__((address_space(3))) int* tab_r =
                 (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][1];
-            band_table(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane, BTS, tab_l);
-            band_table(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane, BTS, tab_r);
+            band_table(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane, BTS, NC == 2, tab_l);
+            band_table(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane, BTS, NC == 2, tab_r);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // NC candidates per lane: a list segment has 64 * NC members
-            constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
             constexpr uint32_t SEG = 64u * NC;
             const uint32_t hsegs = (count + SEG - 1) / SEG;
             const uint64_t left_in_chunk = sg_end - sg_i;
@@ -1157,7 +1163,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     const int yo = right ? ry : 0, yl = right ? l - ry : sgm.p - 1;
                     const int tt = right ? tr : tl;
                     int cl[NC], d[NC];
-                    if (REGY > 0) {
+                    if constexpr (REGY > 0) {
                         RegChars vc[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) vc[c] = RegChars{yr[c], yo};

@@ -354,6 +354,16 @@ struct RegChars {
     }
 };
 
+// Character k of two register strings (same part offset) as the low and high 16-bit halves
+// of one word: one byte permute picks byte q & 3 of each string's word q >> 2.
+__device__ inline uint32_t reg_pair(const RegChars (&V)[2], int k)
+{
+    const int q = V[0].off + k;
+    const uint32_t d0 = V[0].r[q >> 2], d1 = V[1].r[q >> 2];
+    // selector bytes: 0..3 take bytes of d0, 4..7 bytes of d1, 12 gives zero
+    return __builtin_amdgcn_perm(d1, d0, 0x0c040c00u + (uint32_t)(q & 3) * 0x10001u);
+}
+
 // Bytes of the probe string staged in the wave's LDS buffer, read at wave-uniform positions
 // (a broadcast read; no bank conflicts).
 struct LdsChars {
@@ -384,12 +394,17 @@ struct LdsChars {
 // and it stops at its first failing row.  A lane therefore only counts the rows it passed
 // (rows evaluated = passes + 1 if it stopped, nr if it passed them all), and a candidate
 // that is not active starts with every band cell at BIG, so it never passes a row.
+// Large value of the two-candidate DP's 16-bit cells: it and every value that grows from it
+// (at most one per row, rows <= 2047, plus a distance offset <= 63) stay below 2^16, and it
+// exceeds every value reached from row 0 of the band.
+constexpr uint32_t kBig16 = 0x4000u;
+
 // Row 0, the expected-distance offsets |kfin - k| and (rows from y) the first column window of
 // one part's band, as a table in the wave's LDS: entry k of each of the three rows of TS
 // ints.  Written once per hit by lanes k < TS (every lane computes its entry), then read by
 // every candidate's DP with broadcast loads.
 __device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, int ts,
-                                  __attribute__((address_space(3))) int* tab)
+                                  bool packed, __attribute__((address_space(3))) int* tab)
 {
     const bool yrows = lv <= lu;
     const int nr = yrows ? lv : lu;
@@ -403,9 +418,17 @@ __device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, i
     const int ek = kfin - lane < 0 ? lane - kfin : kfin - lane;
     const int w0 = (yrows && (unsigned)jl < (unsigned)nc) ? U[jl] : 256;
     if (lane < ts) {
-        tab[lane] = r0;
-        tab[ts + lane] = ek;
-        tab[2 * ts + lane] = w0;
+        if (packed) {
+            // both 16-bit halves (two candidates per lane), BIG lowered to kBig16
+            const uint32_t r16 = r0 == (1 << 20) ? kBig16 : (uint32_t)r0;
+            tab[lane] = (int)(r16 * 0x10001u);
+            tab[ts + lane] = (int)((uint32_t)ek * 0x10001u);
+            tab[2 * ts + lane] = (int)((uint32_t)w0 * 0x10001u);
+        } else {
+            tab[lane] = r0;
+            tab[ts + lane] = ek;
+            tab[2 * ts + lane] = w0;
+        }
     }
 }
 
@@ -454,7 +477,8 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
         const int r0 = tab[k];
 #pragma unroll
         for (int c = 0; c < NC; ++c) R[c][k] = act[c] ? r0 : BIG;
-        ek[k] = tab[TS + k];
+        // wide bands keep the offsets in scalar registers (vector registers are scarce there)
+        ek[k] = MAXW <= 9 ? tab[TS + k] : __builtin_amdgcn_readfirstlane(tab[TS + k]);
         if (YROWS) {
             w[0][k] = tab[2 * TS + k];
         } else {
@@ -553,6 +577,121 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
         cells[c] = act[c] ? band_cells(nrows, nc, a, b) : 0;
         res[c] = (act[c] && all) ? out : t + 1;
     }
+}
+
+// Two candidates per lane (members of one list, so one band geometry), packed as the low and
+// high 16-bit halves of every cell: the same recurrence as vsp_seg, in packed 16-bit integer
+// operations (the cost form min(up + 1, left + 1, diag + [mismatch]) keeps every value
+// non-negative).  Cells start at kBig16 where vsp_seg starts at BIG; everything said there about
+// the band, the wave vote and the pass counts holds per half.
+typedef unsigned short pj_u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline pj_u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(pj_u16x2, x); }
+__device__ inline uint32_t as_u32(pj_u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+template <int MAXW, bool YROWS, int TS>
+__device__ inline void vsp_seg2(LdsChars U, int lu, const RegChars (&V)[2], int lv, int t,
+                                const __attribute__((address_space(3))) int* tab,
+                                const bool (&act)[2], int (&cells)[2], int (&res)[2])
+{
+    static_assert(MAXW <= 64, "one band index per table entry");
+    const int nr = YROWS ? lv : lu;
+    const int nc = YROWS ? lu : lv;
+    const int delta = nc - nr;
+    cells[0] = cells[1] = 0;
+    res[0] = res[1] = t + 1;
+    if (delta > t) return;
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    const int kfin = delta + a;
+    // 1 in both halves, opaque to the compiler: min(x, 1) stays one packed min instead of two
+    // compares and selects
+    uint32_t one_bits = 0x10001u;
+    asm volatile("" : "+v"(one_bits));
+    const pj_u16x2 ONE = as_u16x2(one_bits);
+    const pj_u16x2 BIG = as_u16x2(kBig16 * 0x10001u);
+    constexpr uint32_t NOCHAR = 256u * 0x10001u;  // matches no byte
+    // halves of inactive candidates start at kBig16: they never pass a row
+    const uint32_t keep = (act[0] ? 0x0000ffffu : 0u) | (act[1] ? 0xffff0000u : 0u);
+    pj_u16x2 R[MAXW], ek[MAXW];
+    uint32_t w[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const uint32_t r0 = (uint32_t)tab[k];
+        R[k] = as_u16x2((r0 & keep) | (kBig16 * 0x10001u & ~keep));
+        ek[k] = as_u16x2((uint32_t)tab[TS + k]);
+        if (YROWS) {
+            w[k] = (uint32_t)tab[2 * TS + k];
+        } else {
+            const int idx = k - a;
+            w[k] = ((unsigned)idx < (unsigned)nc) ? reg_pair(V, idx) : NOCHAR;
+        }
+    }
+    int idx_in = MAXW - a;
+    uint32_t ai_pre = (!YROWS && nr > 0) ? (uint32_t)U[0] * 0x10001u : NOCHAR;
+    int passes0 = 0, passes1 = 0;
+    constexpr bool ROT = MAXW <= 9;
+    constexpr int UNROLL = ROT ? MAXW : 1;
+    int row = 1;
+    bool go = nr > 0;
+    while (go) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int i = __builtin_amdgcn_readfirstlane(row);
+            uint32_t ai;
+            if (YROWS) {
+                ai = reg_pair(V, i - 1);
+            } else {
+                ai = ai_pre;
+                ai_pre = (uint32_t)U[i] * 0x10001u;   // U[nr]: inside the padded buffer
+            }
+            uint32_t cin;
+            if (YROWS) {
+                cin = (uint32_t)U[idx_in] * 0x10001u;
+            } else {
+                cin = ((unsigned)idx_in < (unsigned)nc) ? reg_pair(V, idx_in) : NOCHAR;
+            }
+            pj_u16x2 left = BIG, emin = BIG;
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                const pj_u16x2 up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : BIG;
+                // [mismatch] per half: min(a ^ b, 1)
+                const pj_u16x2 d =
+                    __builtin_elementwise_min(as_u16x2(ai ^ w[(u + k) % MAXW]), ONE);
+                const pj_u16x2 v =
+                    __builtin_elementwise_min(__builtin_elementwise_min(up, left) + ONE,
+                                              R[k] + d);
+                const pj_u16x2 e = v + ek[k];
+                emin = k == 0 ? e : __builtin_elementwise_min(emin, e);
+                R[k] = v;
+                left = v;
+            }
+            const bool p0 = (int)emin.x <= t, p1 = (int)emin.y <= t;
+            passes0 += p0 ? 1 : 0;
+            passes1 += p1 ? 1 : 0;
+            if (__builtin_amdgcn_ballot_w64(p0 || p1) == 0 || i == nr) {
+                go = false;
+                break;
+            }
+            if (ROT) {
+                w[u] = cin;
+            } else {
+#pragma unroll
+                for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
+                w[MAXW - 1] = cin;
+            }
+            ++idx_in;
+            ++row;
+        }
+    }
+    const int kf = __builtin_amdgcn_readfirstlane(kfin);
+    const uint32_t fin = as_u32(R[kf]);
+    const int out0 = min((int)(fin & 0xffffu), t + 1), out1 = min((int)(fin >> 16), t + 1);
+    const bool all0 = passes0 == nr, all1 = passes1 == nr;
+    cells[0] = act[0] ? band_cells(all0 ? nr : passes0 + 1, nc, a, b) : 0;
+    cells[1] = act[1] ? band_cells(all1 ? nr : passes1 + 1, nc, a, b) : 0;
+    res[0] = (act[0] && all0) ? out0 : t + 1;
+    res[1] = (act[1] && all1) ? out1 : t + 1;
 }
 
 }  // namespace pj
