@@ -451,6 +451,28 @@ __global__ __launch_bounds__(kBlock) void k_mark_heads(const uint64_t* __restric
     if (e < E) flags[e] = (e == 0 || keys[e] != keys[e - 1]) ? 1u : 0u;
 }
 
+// Inline copies of the list members' strings: entry j of the sorted index (length l, read from
+// its key's group) gets the bytes of string vals[j], in a slot of stride_of(l) bytes at
+// inl + inl_base[l] + j * stride_of(l).  Entries of one length are contiguous in the sorted
+// index (the group is the key's top field), so the copies of one list are contiguous too.
+__global__ __launch_bounds__(kBlock) void k_gather_inline(
+    const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t E, int tau,
+    const uint8_t* __restrict__ sarena, const int32_t* __restrict__ lenstart,
+    const int64_t* __restrict__ gbase, const int64_t* __restrict__ inl_base,
+    uint8_t* __restrict__ inl)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= E) return;
+    const int T1 = tau + 1;
+    const int l = (int)((keys[j] >> kHashBits) / (uint64_t)T1) + T1;
+    const uint32_t g = vals[j];
+    const int64_t st = stride_of(l);
+    const uint4* src = reinterpret_cast<const uint4*>(sarena + gbase[l] +
+                                                      (int64_t)(g - (uint32_t)lenstart[l]) * st);
+    uint4* dst = reinterpret_cast<uint4*>(inl + inl_base[l] + j * st);
+    for (int q = 0; q < (int)(st >> 4); ++q) dst[q] = src[q];
+}
+
 __global__ __launch_bounds__(kBlock) void k_clear_table(uint4* __restrict__ table, uint64_t slots)
 {
     uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1082,8 +1104,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                         ? hsegs : sidx + (uint32_t)left_in_chunk;
             // REGY > 0: the whole indexed string (at most REGY bytes, 16-byte aligned slot) goes
             // to registers with wide loads and is read at wave-uniform offsets
-            auto load_y = [&](uint32_t g, uint32_t* yr) -> const uint8_t* {
-                const uint8_t* y = V.y_arena + ybase + (int64_t)g * stride_of(l);
+            // With the index's inline copies a list's strings are contiguous (entry e at
+            // yinl + e * stride), so a segment's loads are coalesced and need no list entry first
+            const uint8_t* yinl = nullptr;
+            if (REGY > 0 && V.y_inl) yinl = V.y_inl + uniform_load(V.y_inl_base + l);
+            auto load_y = [&](uint32_t g, uint32_t e, uint32_t* yr) -> const uint8_t* {
+                const uint8_t* y = yinl ? yinl + (int64_t)e * stride_of(l)
+                                        : V.y_arena + ybase + (int64_t)g * stride_of(l);
                 if (REGY > 0) {
                     const uint4* yq = reinterpret_cast<const uint4*>(y);
 #pragma unroll
@@ -1118,7 +1145,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                uint32_t gy[NC];
+                uint32_t gy[NC], ent[NC];
                 uint32_t yr[NC][REGY > 0 ? REGY / 4 : 1];
                 const uint8_t* y[NC];
                 bool ok[NC];
@@ -1130,16 +1157,24 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     ok[c] = from_queue ? slot < k : member < count;
                     // the two sources in separate uniform branches (one merged load would be a
                     // flat load of LDS or global memory)
+                    // the queue holds index entries (inline copies) or string positions
                     gy[c] = 0;
+                    ent[c] = 0;
                     if (from_queue) {
                         const uint32_t q = sq[slot];          // slot < 2 * SEG: in bounds
-                        gy[c] = ok[c] ? q : 0u;
+                        if (yinl) {
+                            ent[c] = ok[c] ? q : 0u;
+                            if (ok[c]) gy[c] = vals[q];
+                        } else {
+                            gy[c] = ok[c] ? q : 0u;
+                        }
                     } else if (ok[c]) {
+                        ent[c] = start + member;
                         gy[c] = vals[start + member];
                     }
                     y[c] = V.y_arena;
                     if (ok[c]) {
-                        y[c] = load_y(gy[c], yr[c]);
+                        y[c] = load_y(gy[c], ent[c], yr[c]);
                         if (!from_queue && sgm.len > V.exact_len) {
                             // hashed key: compare the segment bytes before extension
                             // verification, which skips the segment
@@ -1216,7 +1251,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         if (ok[c])
                             sq[qn + __builtin_amdgcn_mbcnt_hi(
                                         (uint32_t)(surv >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] = gy[c];
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] =
+                                yinl ? ent[c] : gy[c];
                         qn += (uint32_t)__builtin_popcountll(surv);
                     }
                 }
@@ -1414,6 +1450,16 @@ hipError_t launch_mark_heads(const uint64_t* keys, int64_t E, uint32_t* flags, h
 {
     if (E <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mark_heads, dim3(blocks_for(E)), dim3(kBlock), 0, s, keys, E, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_inline(const DevSet& S, const uint64_t* keys, const uint32_t* vals,
+                                int64_t E, int tau, const int64_t* inl_base, uint8_t* inl,
+                                hipStream_t s)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_inline, dim3(blocks_for(E)), dim3(kBlock), 0, s, keys, vals, E,
+                       tau, S.sarena, S.lenstart, S.gbase, inl_base, inl);
     return hipGetLastError();
 }
 

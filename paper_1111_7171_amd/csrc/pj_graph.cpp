@@ -127,6 +127,8 @@ GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t s
     vp.x_arena = pp.x_arena; vp.x_slen = pp.x_slen; vp.x_lenstart = pp.x_lenstart;
     vp.x_gbase = pp.x_gbase;
     vp.y_arena = Y.sarena; vp.y_lenstart = Y.lenstart; vp.y_gbase = Y.gbase;
+    vp.y_inl = nullptr;                               // serving indices keep no inline copies
+    vp.y_inl_base = nullptr;
     vp.hits = hits;
     vp.prefix = prefix;
     vp.tau = g->tau_max;

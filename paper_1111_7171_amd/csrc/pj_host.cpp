@@ -304,7 +304,7 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
 // ------------------------------------------------------------------------------------------
 
 void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
-                 hipStream_t st)
+                 hipStream_t st, bool with_inline)
 {
     const int T1 = tau + 1;
     X.tau = tau;
@@ -373,6 +373,25 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     }
     X.keys = keys;
     X.vals = vals;
+    // inline copies of the members' strings (short strings only, and only within the budget):
+    // the list-segment kernel then reads a list's strings contiguously
+    std::vector<int64_t> inl_base(kLenTab, 0);
+    if (with_inline && D.lmax <= kInlineMaxLen) {
+        int64_t bytes = 0;
+        for (int l = T1; l < kLenTab; ++l) {
+            inl_base[l] = bytes - ebase[l] * stride_of(l);
+            bytes += (int64_t)(D.h_lenstart[l + 1] - D.h_lenstart[l]) * T1 * stride_of(l);
+        }
+        const size_t need = (size_t)bytes + sizeof(int64_t) * kLenTab;
+        if (A.budget == 0 || (long long)(A.used + need) <= A.budget) {
+            X.inl = (uint8_t*)A.get(nm("inl").c_str(), (size_t)std::max<int64_t>(bytes, 16));
+            X.inl_base = (int64_t*)A.get(nm("inl_base").c_str(), sizeof(int64_t) * kLenTab);
+            hip_check(hipMemcpyAsync(X.inl_base, inl_base.data(), sizeof(int64_t) * kLenTab,
+                                     hipMemcpyHostToDevice, st), "upload inl_base");
+            hip_check(launch_gather_inline(D, keys, vals, E, tau, X.inl_base, X.inl, st),
+                      "gather_inline");
+        }
+    }
     // lists = runs of equal keys
     uint32_t* flags = (uint32_t*)W.get("index.flags", sizeof(uint32_t) * (size_t)E);
     uint32_t* runid = (uint32_t*)W.get("index.runid", sizeof(uint32_t) * (size_t)(E + 1));
@@ -555,6 +574,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.x_gbase = P.gbase;
             vp.y_arena = Y.sarena; vp.y_lenstart = Y.lenstart; vp.y_gbase = Y.gbase;
             vp.vals = spec.X ? spec.X->vals : nullptr;
+            vp.y_inl = spec.X ? spec.X->inl : nullptr;
+            vp.y_inl_base = spec.X ? spec.X->inl_base : nullptr;
             vp.q_tau = spec.q_tau;
             vp.refs = spec.refs;
             vp.hits = J.hits; vp.prefix = J.prefix;
@@ -783,7 +804,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     const DevSet& YY = self ? P : Y;
     int e1 = tm.mark();
     DevIndex X;
-    build_index(YY, tau, W, "X", X, st);
+    build_index(YY, tau, W, "X", X, st, !(opt && opt->mode == PJ_MODE_PLAIN));
     int e2 = tm.mark();
     t_stats.strings = P.n + (self ? 0 : Y.n);
     t_stats.index_entries = X.entries;

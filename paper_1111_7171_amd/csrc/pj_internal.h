@@ -25,6 +25,7 @@ constexpr int kHashBits = 40;          // hash bits kept in an index key
 constexpr uint64_t kEmptyKey = ~0ull;  // keys use at most 57 bits, so this never collides
 
 __host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 15) & ~15); }
+constexpr int kInlineMaxLen = 64;       // longest string the list-segment kernel keeps in registers
 
 // Symbol map of an indexed set: code[b] = 1 + rank of byte b among the bytes the set contains
 // (0: absent), bits = bit length of the largest code.  A segment of at most exact_len =
@@ -62,6 +63,10 @@ struct DevIndex {
     uint32_t* vals = nullptr;           // [entries] sorted position g of the string
     uint4* table = nullptr;             // [mask + 1] {key lo, key hi, start, count}
     uint64_t mask = 0;
+    // inline copies of the members' strings in index order (strings of at most kInlineMaxLen
+    // bytes; nullptr otherwise): entry j of length l at inl + inl_base[l] + j * stride_of(l)
+    uint8_t* inl = nullptr;
+    int64_t* inl_base = nullptr;        // [kLenTab] device
 };
 
 // Per-threshold view of a multi-tau index (serving): the bucket table and list entries of the
@@ -110,6 +115,8 @@ struct VerifyParams {
     const int64_t* x_gbase;
     const uint8_t* y_arena; const int32_t* y_lenstart; const int64_t* y_gbase;
     const uint32_t* vals;
+    // inline member strings of the index (DevIndex::inl / inl_base), or nullptr
+    const uint8_t* y_inl; const int64_t* y_inl_base;
     const Hit* hits; const unsigned long long* prefix;   // [nhits + 1] exclusive prefix of counts
     uint64_t nhits; uint64_t ncand;
     int tau;                                              // uniform tau or the batch's largest
@@ -137,6 +144,9 @@ hipError_t launch_byte_presence(const DevSet& S, uint32_t* bitmap, hipStream_t s
 hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
                                 int64_t g_first, int64_t g_count, const SymMap& sym,
                                 uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_gather_inline(const DevSet& S, const uint64_t* keys, const uint32_t* vals,
+                                int64_t E, int tau, const int64_t* inl_base, uint8_t* inl,
+                                hipStream_t s);
 hipError_t launch_mark_heads(const uint64_t* keys, int64_t E, uint32_t* flags, hipStream_t s);
 hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid, int64_t E,
                                    uint32_t* runstart, hipStream_t s);
