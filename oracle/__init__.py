@@ -16,7 +16,8 @@ Functions (paper sections in brackets):
   self_join_bf       all pairs with ED <= tau (brute force)                [Definition 1]
   join_bf            all (r, s) with ED <= tau (brute force)               [Definition 1]
   partners_bf        partners of listed strings (brute force)              [Definition 1]
-  self_join_pj       Pass-Join self-join with candidate/cell counts        [Alg. 1-3]
+  self_join_pj       Pass-Join self-join with candidate/cell counts, any   [Alg. 1-3, Sec. 4]
+                     of the four substring-selection methods
   join_pj            Pass-Join join of two sets                            [Sec. 3.2]
 """
 from __future__ import annotations
@@ -89,9 +90,9 @@ def _load():
         lib.orc_join_bf.restype = rp
         lib.orc_partners_bf.argtypes = [u8p, i32p, i64, i32p, i64, i32, i32]
         lib.orc_partners_bf.restype = rp
-        lib.orc_self_join_pj.argtypes = [u8p, i32p, i64, i32, i32, i32, i32]
+        lib.orc_self_join_pj.argtypes = [u8p, i32p, i64, i32, i32, i32, i32, i32]
         lib.orc_self_join_pj.restype = rp
-        lib.orc_join_pj.argtypes = [u8p, i32p, i64, u8p, i32p, i64, i32, i32]
+        lib.orc_join_pj.argtypes = [u8p, i32p, i64, u8p, i32p, i64, i32, i32, i32]
         lib.orc_join_pj.restype = rp
         lib.orc_result_free.argtypes = [rp]
         lib.orc_result_free.restype = None
@@ -221,18 +222,20 @@ def partners_bf(col, xs, tau: int, nthreads: int = 0) -> np.ndarray:
 
 
 def self_join_pj(col, tau: int, tiebreak: int = 0, probe_stride: int = 1,
-                 keep_cands: bool = False) -> JoinResult:
+                 keep_cands: bool = False, method: int = SEL_MULTIMATCH) -> JoinResult:
     """Pass-Join self-join; tiebreak 0 visits equal lengths by id, 1 by bytes (the paper's
-    alphabetical order).  probe_stride > 1 lets only every k-th visited string probe."""
+    alphabetical order).  probe_stride > 1 lets only every k-th visited string probe.  method
+    is the substring selection (SEL_*; multi-match, Sec. 4.2, by default)."""
     ch, of = _arena(col)
     rp = _load().orc_self_join_pj(ch.ctypes.data, of.ctypes.data, col.n, tau, tiebreak,
-                                  probe_stride, int(keep_cands))
+                                  probe_stride, int(keep_cands), int(method))
     return _take(rp, keep_cands)
 
 
-def join_pj(R, S, tau: int, keep_cands: bool = False) -> JoinResult:
+def join_pj(R, S, tau: int, keep_cands: bool = False,
+            method: int = SEL_MULTIMATCH) -> JoinResult:
     rc, ro = _arena(R)
     sc, so = _arena(S)
     rp = _load().orc_join_pj(rc.ctypes.data, ro.ctypes.data, R.n, sc.ctypes.data,
-                             so.ctypes.data, S.n, tau, int(keep_cands))
+                             so.ctypes.data, S.n, tau, int(keep_cands), int(method))
     return _take(rp, keep_cands)

@@ -528,21 +528,25 @@ static void index_string(orc_index* X, const uint8_t* s, int32_t len, int32_t ta
 }
 
 /* Probes the index with string x (Algorithm 1 inner loops): for every length l in [lmin, lmax]
- * (l >= tau+1) and slot i, the multi-match window of Sec. 4.2 selects start positions p
- * (SubstringSelection, Algorithm 2); each selected substring x[p, l_i] found in L_l^i yields the
- * candidates (y, x, i, p) for y in L_l^i(x[p, l_i]), which are verified by extension
+ * (l >= tau+1) and slot i, the window of the selection method (multi-match, Sec. 4.2, by
+ * default; the length, shift and position methods of Sec. 4 and 4.1 select supersets of it)
+ * selects start positions p (SubstringSelection, Algorithm 2), restricted to the positions
+ * where x has a substring of length l_i; each selected substring x[p, l_i] found in L_l^i yields
+ * the candidates (y, x, i, p) for y in L_l^i(x[p, l_i]), which are verified by extension
  * (Verification, Algorithm 3).  Accepted y are appended to R as (pair_a, pair_b) by the caller's
  * convention. */
 static void probe_string(const orc_index* X, const uint8_t* chars, const int32_t* offs, int32_t x,
                          const uint8_t* xs, int32_t n, int32_t lmin, int32_t lmax, int32_t tau,
-                         int32_t self, int32_t keep_cands, orc_result* R)
+                         int32_t self, int32_t keep_cands, int32_t method, orc_result* R)
 {
     for (int32_t l = imax(lmin, tau + 1); l <= lmax; ++l) {
         int32_t start[128], sl[128];
         orc_partition(l, tau, start, sl);
         for (int32_t i = 1; i <= tau + 1; ++i) {
             int32_t lo, hi;
-            orc_window(ORC_SEL_MULTIMATCH, n, l, tau, i, &lo, &hi);
+            orc_window(method, n, l, tau, i, &lo, &hi);
+            lo = imax(lo, 1);
+            hi = imin(hi, n - sl[i - 1] + 1);
             for (int32_t p = lo; p <= hi; ++p) {
                 R->selected++;
                 const orc_node* e = index_find(X, l, i, xs + p - 1, sl[i - 1]);
@@ -595,7 +599,8 @@ static int cmp_visit(const void* u, const void* v, void* arg)
  * (and take part in the direct path); every string is still indexed.
  * keep_cands = 1 records every candidate (y, x, i, p) with its verdict and cells. */
 orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t n, int32_t tau,
-                             int32_t tiebreak, int32_t probe_stride, int32_t keep_cands)
+                             int32_t tiebreak, int32_t probe_stride, int32_t keep_cands,
+                             int32_t method)
 {
     orc_result* R = res_new();
     if (probe_stride < 1) probe_stride = 1;
@@ -616,7 +621,8 @@ orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t 
         int32_t xl = offs[x + 1] - offs[x];
         if (rank % probe_stride == 0) {
             if (xl >= tau + 1)
-                probe_string(&X, chars, offs, x, xs, xl, xl - tau, xl, tau, 1, keep_cands, R);
+                probe_string(&X, chars, offs, x, xs, xl, xl - tau, xl, tau, 1, keep_cands, method,
+                             R);
             for (int64_t k = 0; k < nshort; ++k) {
                 int32_t y = shorts[k];
                 int32_t yl = offs[y + 1] - offs[y];
@@ -641,7 +647,8 @@ orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t 
  * Delta = |r| - l.  Strings of S shorter than tau+1 are compared with every r directly.
  * Pairs are (r, s). */
 orc_result* orc_join_pj(const uint8_t* rc, const int32_t* ro, int64_t rn, const uint8_t* sc,
-                        const int32_t* so, int64_t sn, int32_t tau, int32_t keep_cands)
+                        const int32_t* so, int64_t sn, int32_t tau, int32_t keep_cands,
+                        int32_t method)
 {
     orc_result* R = res_new();
     orc_index X;
@@ -657,7 +664,8 @@ orc_result* orc_join_pj(const uint8_t* rc, const int32_t* ro, int64_t rn, const 
     for (int64_t x = 0; x < rn; ++x) {
         const uint8_t* xs = rc + ro[x];
         int32_t xl = ro[x + 1] - ro[x];
-        probe_string(&X, sc, so, (int32_t)x, xs, xl, xl - tau, xl + tau, tau, 0, keep_cands, R);
+        probe_string(&X, sc, so, (int32_t)x, xs, xl, xl - tau, xl + tau, tau, 0, keep_cands,
+                     method, R);
         for (int64_t k = 0; k < nshort; ++k) {
             int32_t y = shorts[k];
             int32_t yl = so[y + 1] - so[y];

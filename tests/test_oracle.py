@@ -424,6 +424,63 @@ def test_theorem6_join_two_sets(seed):
         assert np.array_equal(O.join_pj(R, S, tau).pairs, O.join_bf(R, S, tau, 4)), tau
 
 
+SEL_METHODS = (O.SEL_MULTIMATCH, O.SEL_POSITION, O.SEL_SHIFT, O.SEL_LENGTH)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_every_selection_method_is_complete(seed):
+    # Sec. 4: the length, shift, position and multi-match selections all find every similar
+    # pair (completeness), so each Pass-Join equals the brute-force join
+    rng = np.random.default_rng(300 + seed)
+    alph = [b"ab", b"abc", b"abcd"][seed % 3]
+    col = W.random_small(rng, 250, alphabet=alph, lmin=0, lmax=14, dup_frac=0.4, kmax=3)
+    S = W.random_small(rng, 150, alphabet=alph, lmin=0, lmax=14, dup_frac=0.3, kmax=3)
+    for tau in range(0, 5):
+        bf = O.self_join_bf(col, tau, 4)
+        jbf = O.join_bf(col, S, tau, 4)
+        for m in SEL_METHODS:
+            assert np.array_equal(O.self_join_pj(col, tau, method=m).pairs, bf), (tau, m)
+            assert np.array_equal(O.join_pj(col, S, tau, method=m).pairs, jbf), (tau, m)
+
+
+def test_selection_methods_nest():
+    # Lemma 3 and Sec. 4: multi-match selects a subset of position-aware, which selects a subset
+    # of shift-based, which selects a subset of all substrings; so the candidate sets nest too
+    col = W.cfg1(1500)
+    for tau in (1, 2, 3):
+        res = [O.self_join_pj(col, tau, method=m, keep_cands=True) for m in SEL_METHODS]
+        sets = [set(zip(r.cands["y"].tolist(), r.cands["x"].tolist(), r.cands["i"].tolist(),
+                        r.cands["p"].tolist())) for r in res]
+        for a, b_ in zip(sets, sets[1:]):
+            assert a <= b_
+        sel = [r.selected for r in res]
+        assert sel == sorted(sel) and sel[0] < sel[-1]
+        # every pair a method finds comes from candidates it verified
+        for r in res:
+            assert np.array_equal(r.pairs, res[0].pairs)
+
+
+def test_length_selection_count():
+    # the length method selects every substring of length l_i: a probe string of length n has
+    # n - l_i + 1 of them for each probed length l and slot i (closed form over the lengths)
+    rng = np.random.default_rng(7)
+    col = W.random_small(rng, 60, alphabet=b"abc", lmin=3, lmax=12, dup_frac=0.0, kmax=1)
+    tau = 2
+    lens = (col.offsets[1:] - col.offsets[:-1]).tolist()
+    expect = 0
+    order = sorted(range(col.n), key=lambda k: (lens[k], k))
+    for x in order:
+        n = lens[x]
+        if n < tau + 1:
+            continue
+        for l in range(max(n - tau, tau + 1), n + 1):
+            q, k = divmod(l, tau + 1)
+            for i in range(1, tau + 2):
+                li = q + (1 if i > tau + 1 - k else 0)
+                expect += n - li + 1
+    assert O.self_join_pj(col, tau, method=O.SEL_LENGTH).selected == expect
+
+
 def test_tiebreak_order_gives_same_set():
     col = W.cfg1(2000)
     for tau in (1, 2, 3):
