@@ -70,13 +70,28 @@ typedef struct {
     int32_t on_device;
 } pj_pairs;
 
+/* Substring selection (pj_options.selection): which substrings of a probe string are looked up
+ * in the segment index.  All four find every similar pair (Sec. 4); they differ in how many
+ * substrings and candidates they generate, multi-match the fewest (Lemma 3, Sec. 4.2).  Windows
+ * of start positions, restricted to where the probe string has a substring of length l_i:
+ *   multi-match  the intersection of [p_i - (i-1), p_i + (i-1)] and
+ *                [p_i + Delta - (tau+1-i), p_i + Delta + (tau+1-i)]            (Sec. 4.2)
+ *   position     [p_i - floor((tau-Delta)/2), p_i + floor((tau+Delta)/2)]    (Sec. 4.1)
+ *   shift        [p_i - tau, p_i + tau]                                       (Sec. 4)
+ *   length       every start position                                        (Sec. 4)
+ * Delta = |probe string| - l.  Serving queries always use multi-match. */
+#define PJ_SELECT_MULTIMATCH 0
+#define PJ_SELECT_POSITION   1
+#define PJ_SELECT_SHIFT      2
+#define PJ_SELECT_LENGTH     3
+
 /* Per-call options; a NULL pointer means all defaults (zero-initialised struct). */
 typedef struct {
     void* hip_stream;          /* hipStream_t the work is ordered on; NULL = the null stream */
     int32_t inputs_on_device;  /* 1: pj_strings pointers are device pointers */
     int32_t outputs_on_device; /* 1: pj_pairs stay in device memory */
     int32_t mode;              /* PJ_MODE_* */
-    int32_t reserved;
+    int32_t selection;         /* PJ_SELECT_* (pj_self_join, pj_join, pj_tune); 0 = multi-match */
     int64_t mem_budget_bytes;  /* 0 = no limit; otherwise the device bytes a call may hold */
     const char* tune_cache;    /* autotune cache file (read, and written when tuning); NULL = none */
 } pj_options;

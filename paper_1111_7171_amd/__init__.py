@@ -31,6 +31,7 @@ LIB_PATH = os.path.join(_HERE, "libpassjoin.so")
 PJ_OK, PJ_EINVAL, PJ_ERANGE, PJ_ENOMEM, PJ_EDEVICE = 0, -1, -2, -3, -4
 PJ_TAU_MAX, PJ_LEN_MAX = 63, 2047
 MODE_AUTO, MODE_PLAIN, MODE_BATCHED = 0, 1, 2
+SELECT_MULTIMATCH, SELECT_POSITION, SELECT_SHIFT, SELECT_LENGTH = 0, 1, 2, 3
 _CODES = {PJ_EINVAL: "EINVAL", PJ_ERANGE: "ERANGE", PJ_ENOMEM: "ENOMEM", PJ_EDEVICE: "EDEVICE"}
 
 
@@ -51,7 +52,7 @@ class PjPairs(C.Structure):
 
 class PjOptions(C.Structure):
     _fields_ = [("hip_stream", C.c_void_p), ("inputs_on_device", C.c_int32),
-                ("outputs_on_device", C.c_int32), ("mode", C.c_int32), ("reserved", C.c_int32),
+                ("outputs_on_device", C.c_int32), ("mode", C.c_int32), ("selection", C.c_int32),
                 ("mem_budget_bytes", C.c_int64), ("tune_cache", C.c_char_p)]
 
 
@@ -194,11 +195,12 @@ class _Marshalled:
 
 
 def _options(on_device: bool, outputs_on_device: bool, mode: int, mem_budget: int,
-             stream, tune_cache: str | None) -> PjOptions:
+             stream, tune_cache: str | None, selection: int = 0) -> PjOptions:
     o = PjOptions()
     o.inputs_on_device = 1 if on_device else 0
     o.outputs_on_device = 1 if outputs_on_device else 0
     o.mode = mode
+    o.selection = int(selection)
     o.mem_budget_bytes = int(mem_budget)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     if stream is None and on_device:
@@ -261,26 +263,30 @@ def _take_pairs(raw: PjPairs, outputs_on_device: bool):
 
 
 def pj_self_join(strings, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = False,
-                 mem_budget: int = 0, stream=None, tune_cache: str | None = None):
+                 mem_budget: int = 0, stream=None, tune_cache: str | None = None,
+                 selection: int = 0):
     """All pairs (a, b), a < b, of one string set with ED <= tau, as an int32 [m, 2] array
-    sorted by (a, b)."""
+    sorted by (a, b).  selection: SELECT_* substring selection (multi-match by default)."""
     lib = load()
     s = _Marshalled(strings)
-    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache)
+    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache,
+                 selection)
     raw = PjPairs()
     _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
 
 
 def pj_join(R, S, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = False,
-            mem_budget: int = 0, stream=None, tune_cache: str | None = None):
+            mem_budget: int = 0, stream=None, tune_cache: str | None = None,
+            selection: int = 0):
     """All (r, s) with ED(R[r], S[s]) <= tau, int32 [m, 2] sorted by (r, s)."""
     lib = load()
     r = _Marshalled(R)
     s = _Marshalled(S)
     if r.on_device != s.on_device:
         raise PassJoinError(PJ_EINVAL, "R and S must both be on the host or both on the device")
-    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache)
+    o = _options(s.on_device, outputs_on_device, mode, mem_budget, stream, tune_cache,
+                 selection)
     raw = PjPairs()
     _check(lib.pj_join(C.byref(r.s), C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)

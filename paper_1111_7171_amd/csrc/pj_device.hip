@@ -566,23 +566,28 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
             }
             l = P.self ? n - dl : n - tau + dl;
             const bool in_window = i <= tau + 1 && dl <= (P.self ? tau : 2 * tau) && l >= tau + 1;
-            // substrings selected for L_l^1 .. L_l^{tau+1}: the Lemma 2 count, whether or not
-            // strings of length l exist (Algorithm 1 selects for every l in the length window)
-            if (in_window && i == 1) {
+            // substrings selected for L_l^1 .. L_l^{tau+1}, whether or not strings of length l
+            // exist (Algorithm 1 selects for every l in the length window): for multi-match
+            // the Lemma 2 count, otherwise each slot's window size
+            if (in_window && P.selection == 0 && i == 1) {
                 const int d = n - l;
                 my_sel += (uint64_t)((tau * tau - d * d) / 2 + tau + 1);
             }
+            if (in_window) {
+                sg = partition_seg(l, i, tau, dv);
+                select_window(P.selection, n, l, tau, i, sg, &lo, &hi);
+                if (P.selection != 0 && hi >= lo) my_sel += (uint64_t)(hi - lo + 1);
+            }
             valid = in_window && (l >= P.ymin) && (l <= P.ymax) &&
                     (P.y_lenstart[l + 1] > P.y_lenstart[l]);
-            if (valid) {
-                sg = partition_seg(l, i, tau, dv);
-                multimatch_window(n, l, tau, i, sg, &lo, &hi);
+            if (valid)
                 x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
-            }
         }
         uint64_t h = 0, top = 0;
         if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
-        for (int s = 0; s < T1; ++s) {
+        // the window has at most tau+1 positions for multi-match, more for the other methods;
+        // the loop ends when no lane of the wave has a position left
+        for (int s = 0;; ++s) {
             const int p = lo + s;
             const bool active = valid && p <= hi;
             if (__ballot(active) == 0) break;

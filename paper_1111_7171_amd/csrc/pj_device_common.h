@@ -61,6 +61,32 @@ __device__ inline void multimatch_window(int n, int l, int tau, int i, Seg sg, i
     *hi = b;
 }
 
+// Start-position window of a selection method other than multi-match (PJ_SELECT_POSITION,
+// _SHIFT, _LENGTH; Sec. 4 and 4.1), restricted to [1, n - l_i + 1]: position-aware
+// [p_i - floor((tau-Delta)/2), p_i + floor((tau+Delta)/2)], shift-based [p_i - tau, p_i + tau],
+// length-based every start position.  |Delta| <= tau here, so the halvings are of
+// non-negative values.
+__device__ inline void select_window(int method, int n, int l, int tau, int i, Seg sg, int* lo,
+                                     int* hi)
+{
+    if (method == 0) {
+        multimatch_window(n, l, tau, i, sg, lo, hi);
+        return;
+    }
+    const int delta = n - l;
+    const int last = n - sg.len + 1;
+    int a = 1, b = last;
+    if (method == 1) {
+        a = sg.p - ((tau - delta) >> 1);
+        b = sg.p + ((tau + delta) >> 1);
+    } else if (method == 2) {
+        a = sg.p - tau;
+        b = sg.p + tau;
+    }
+    *lo = a < 1 ? 1 : a;
+    *hi = b > last ? last : b;
+}
+
 // Polynomial segment hash h = sum (c_k + 1) * B^(L-1-k) mod 2^64 (Horner form), rolled across
 // consecutive start positions.  Equal segments always hash equal; unequal ones that collide are
 // rejected by the byte comparison done before verification.

@@ -117,6 +117,7 @@ GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t s
     pp.counters = counters;
     pp.nx_dev = (const uint32_t*)g->d_tables;
     pp.sym = index_sym(idx);
+    pp.selection = PJ_SELECT_MULTIMATCH;
     // grids sized for the plan's capacity (a serving batch is small; idle blocks of a
     // chip-wide grid would still cost every batch their launch)
     const uint64_t probe_threads = (uint64_t)Q * (uint64_t)pp.nl * (uint64_t)(g->tau_max + 1);

@@ -452,6 +452,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
     int64_t probe_first = 0;
     uint64_t bound = spec.q_tau ? spec.bound : selection_bound(P, Y, tau, self, &probe_first);
+    // the other selection methods select supersets of the multi-match windows: start the hit
+    // buffer larger (an overflow re-runs the probe with the exact size anyway)
+    if (spec.selection != PJ_SELECT_MULTIMATCH) bound *= (uint64_t)(2 * tau + 1);
     int64_t nprobe = P.n - probe_first;
     // hit records: the Lemma 2 bound can be far above the real count (long segments rarely
     // match), so start from a capped buffer and re-run the probe with the exact size if needed
@@ -480,6 +483,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
         pp.sym = spec.sym;
+        pp.selection = spec.selection;
         pp.hits = J.hits; pp.hit_cap = hit_cap;
         pp.counters = J.counters;
         int k0 = tm.mark();
@@ -786,6 +790,8 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     check_tau(tau);
     if (opt && (opt->mode < PJ_MODE_AUTO || opt->mode > PJ_MODE_BATCHED))
         throw Error(PJ_EINVAL, "unknown mode %d", opt->mode);
+    if (opt && (opt->selection < PJ_SELECT_MULTIMATCH || opt->selection > PJ_SELECT_LENGTH))
+        throw Error(PJ_EINVAL, "unknown selection method %d", opt->selection);
     hipStream_t st = stream_of(opt);
     bool on_dev = opt && opt->inputs_on_device;
     if (!on_dev) {
@@ -816,6 +822,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     spec.tau = tau;
     spec.X = &X;
     spec.sym = X.sym;
+    spec.selection = opt ? opt->selection : PJ_SELECT_MULTIMATCH;
     run_candidates(P, YY, spec, J, t_stats, tm, st);
     int e3 = tm.mark();
     int32_t *da = nullptr, *db = nullptr;

@@ -106,6 +106,7 @@ struct ProbeSpec {
     uint64_t bound = 0;                // selection bound for a mixed batch (computed by the caller)
     SymMap sym;                        // the indexed set's symbol map (index keys)
     bool has_entries = true;           // some index has entries
+    int selection = 0;                 // PJ_SELECT_*
 };
 
 void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, JoinScratch& J,

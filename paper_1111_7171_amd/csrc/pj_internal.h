@@ -108,6 +108,7 @@ struct ProbeParams {
     // device-resident probe count (captured batches): threads = *nx_dev * nl * (tau + 1)
     const uint32_t* nx_dev;
     SymMap sym;                 // the indexed set's symbol map (keys)
+    int selection;              // PJ_SELECT_* window of start positions
 };
 
 struct VerifyParams {
