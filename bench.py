@@ -218,6 +218,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning the launch parameters (built-in defaults)")
+    ap.add_argument("--selection", type=int, default=0,
+                    help="substring selection: 0 multi-match (default), 1 position, 2 shift, "
+                         "3 every substring (Sec. 4)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotune cache file (written when tuning; with --no-tune it is only "
                          "read).  Default: a fresh file in the temp directory")
@@ -270,7 +273,7 @@ def main():
         outs = []
         for t in taus:
             r = P.pj_self_join((chars, offs), t, mode=args.mode, outputs_on_device=True,
-                               stream=stream, tune_cache=cache)
+                               stream=stream, tune_cache=cache, selection=args.selection)
             st = P.pj_last_stats()
             outs.append(r)
             if collect is not None:
@@ -334,7 +337,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": args.n, "taus": taus, "mode": args.mode},
+        "config": {"workload": WORKLOAD, "n": args.n, "taus": taus, "mode": args.mode,
+                   **({"selection": args.selection} if args.selection else {})},
         "gcups": cells / max(verify_ms, 1e-9) / 1e6,
         "self_join_ms": {k: v["ms"] for k, v in per_tau.items()},
         "per_tau": per_tau,
