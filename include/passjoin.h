@@ -121,6 +121,18 @@ typedef struct {
  * (length, id) order, which yields the same set as the paper's (length, bytes) order. */
 int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out);
 
+/* Self-join of a set that need not fit in device memory, in windows of lengths (the sliding
+ * window of live inverted lists of Sec. 3.2 taken in blocks): a window [a, b] moves the strings
+ * with lengths in [a - tau, b] to the device, lets the strings of length >= a probe, and keeps
+ * the pairs whose longer string is at least a long, so every similar pair is reported by exactly
+ * one window.  Windows are cut greedily so that their strings hold at most window_bytes bytes
+ * (at least one length per window).  S and the result are in host memory
+ * (opt->inputs_on_device and opt->outputs_on_device must be 0); the result equals
+ * pj_self_join's.  pj_last_stats sums the windows' counters.  Errors as pj_self_join, and
+ * PJ_EINVAL for window_bytes <= 0. */
+int pj_self_join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes,
+                          const pj_options* opt, pj_pairs* out);
+
 /* Join of two sets (Definition 1, Sec. 3.2): every (r, s) with ED(R[r], S[s]) <= tau, sorted by
  * (r, s).  S is indexed and each r probes the lengths |r|-tau .. |r|+tau. */
 int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,

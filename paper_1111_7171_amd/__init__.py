@@ -108,6 +108,8 @@ def load():
         lib.pj_self_join.argtypes = [sp, C.c_int32, op, pp]
         lib.pj_self_join.restype = C.c_int
         lib.pj_join.argtypes = [sp, sp, C.c_int32, op, pp]
+        lib.pj_self_join_streamed.argtypes = [sp, C.c_int32, C.c_int64, op, pp]
+        lib.pj_self_join_streamed.restype = C.c_int
         lib.pj_join.restype = C.c_int
         lib.pj_build_index.argtypes = [sp, C.c_int32, C.c_int32, op, C.POINTER(C.c_void_p)]
         lib.pj_build_index.restype = C.c_int
@@ -274,6 +276,22 @@ def pj_self_join(strings, tau: int, *, mode: int = MODE_AUTO, outputs_on_device:
     raw = PjPairs()
     _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
+
+
+def pj_self_join_streamed(strings, tau: int, window_bytes: int, *, mode: int = MODE_AUTO,
+                          mem_budget: int = 0, stream=None, tune_cache: str | None = None,
+                          selection: int = 0):
+    """pj_self_join of a host string set in length windows whose strings hold at most
+    window_bytes bytes each (for sets larger than device memory); same result."""
+    lib = load()
+    s = _Marshalled(strings)
+    if s.on_device:
+        raise PassJoinError(PJ_EINVAL, "pj_self_join_streamed takes host strings")
+    o = _options(False, False, mode, mem_budget, stream, tune_cache, selection)
+    raw = PjPairs()
+    _check(lib.pj_self_join_streamed(C.byref(s.s), int(tau), C.c_int64(int(window_bytes)),
+                                     C.byref(o), C.byref(raw)))
+    return _take_pairs(raw, False)
 
 
 def pj_join(R, S, tau: int, *, mode: int = MODE_AUTO, outputs_on_device: bool = False,

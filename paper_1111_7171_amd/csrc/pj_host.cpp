@@ -421,11 +421,11 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
 
 // Upper bound on the selected substrings (Lemma 2 count per probed length), which bounds hits.
 static uint64_t selection_bound(const DevSet& P, const DevSet& Y, int tau, bool self,
-                                int64_t* probe_first)
+                                int64_t* probe_first, int min_len)
 {
     const int T1 = tau + 1;
     uint64_t total = 0;
-    for (int n = 0; n < kLenTab; ++n) {
+    for (int n = self ? std::max(min_len, 0) : 0; n < kLenTab; ++n) {
         int64_t cnt = P.h_lenstart[n + 1] - P.h_lenstart[n];
         if (cnt == 0) continue;
         int lo = self ? n - tau : n - tau, hi = self ? n : n + tau;
@@ -437,7 +437,8 @@ static uint64_t selection_bound(const DevSet& P, const DevSet& Y, int tau, bool 
         }
         total += per * (uint64_t)cnt;
     }
-    *probe_first = self ? (T1 <= kLenMax ? P.h_lenstart[T1] : P.n) : 0;
+    const int first_len = std::max(T1, min_len);
+    *probe_first = self ? (first_len <= kLenMax ? P.h_lenstart[first_len] : P.n) : 0;
     return total;
 }
 
@@ -451,7 +452,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     J.counters = (unsigned long long*)W.get("join.counters", 8 * sizeof(unsigned long long));
     hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
     int64_t probe_first = 0;
-    uint64_t bound = spec.q_tau ? spec.bound : selection_bound(P, Y, tau, self, &probe_first);
+    uint64_t bound = spec.q_tau ? spec.bound
+                                : selection_bound(P, Y, tau, self, &probe_first,
+                                                  spec.probe_min_len);
     // the other selection methods select supersets of the multi-match windows: start the hit
     // buffer larger (an overflow re-runs the probe with the exact size anyway)
     if (spec.selection != PJ_SELECT_MULTIMATCH) bound *= (uint64_t)(2 * tau + 1);
@@ -783,7 +786,8 @@ static double mean_length(const DevSet& D)
 }
 
 static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
-                      pj_pairs* out, bool self, const TuneParams* force = nullptr)
+                      pj_pairs* out, bool self, const TuneParams* force = nullptr,
+                      int probe_min_len = 0)
 {
     if (!out) throw Error(PJ_EINVAL, "null output");
     zero_pairs(out);
@@ -823,6 +827,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     spec.X = &X;
     spec.sym = X.sym;
     spec.selection = opt ? opt->selection : PJ_SELECT_MULTIMATCH;
+    spec.probe_min_len = probe_min_len;
     run_candidates(P, YY, spec, J, t_stats, tm, st);
     int e3 = tm.mark();
     int32_t *da = nullptr, *db = nullptr;
@@ -835,6 +840,118 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     t_stats.ms_output = tm.ms(e3, e4);
     t_stats.ms_total = std::chrono::duration<double, std::milli>(
                            std::chrono::steady_clock::now() - t0).count();
+}
+
+// Self-join in length windows (for sets larger than device memory; the sliding window of live
+// lists of Sec. 3.2 taken in blocks).  A similar pair is reported by the window holding the
+// length of its longer string: window [a, b] joins the strings with lengths in [a - tau, b],
+// where only strings of length >= a probe, and keeps the pairs whose longer string is at least
+// a long.  Windows are chosen greedily so that the strings of [a - tau, b] hold at most
+// window_bytes bytes (at least one length per window).  Host strings in, host pairs out.
+static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes,
+                          const pj_options* opt, pj_pairs* out)
+{
+    if (!out) throw Error(PJ_EINVAL, "null output");
+    zero_pairs(out);
+    check_tau(tau);
+    if (window_bytes <= 0) throw Error(PJ_EINVAL, "window_bytes must be positive");
+    if (opt && (opt->inputs_on_device || opt->outputs_on_device))
+        throw Error(PJ_EINVAL, "streamed self-joins take host strings and return host pairs");
+    validate_host_strings(S, "S");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S->n;
+    std::vector<int64_t> cnt(kLenTab + 1, 0), bytes(kLenTab + 1, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        const int l = S->offsets[k + 1] - S->offsets[k];
+        ++cnt[l];
+        bytes[l] += l;
+    }
+    // ids grouped by length, ascending within a length
+    std::vector<int64_t> lstart(kLenTab + 2, 0);
+    for (int l = 0; l <= kLenTab; ++l) lstart[l + 1] = lstart[l] + cnt[l];
+    std::vector<int32_t> by_len((size_t)std::max<int64_t>(n, 1));
+    {
+        std::vector<int64_t> fill(lstart.begin(), lstart.end() - 1);
+        for (int64_t k = 0; k < n; ++k)
+            by_len[(size_t)fill[S->offsets[k + 1] - S->offsets[k]]++] = (int32_t)k;
+    }
+    pj_options o{};
+    if (opt) o = *opt;
+    o.outputs_on_device = 0;
+    pj_stats acc{};
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    int lmax = -1;
+    for (int l = 0; l <= kLenMax; ++l)
+        if (cnt[l]) lmax = l;
+    int a = 0;
+    while (a <= lmax) {
+        while (a <= lmax && cnt[a] == 0) ++a;
+        if (a > lmax) break;
+        auto span_bytes = [&](int lo, int hi) {
+            int64_t t = 0;
+            for (int l = std::max(lo, 0); l <= hi; ++l) t += bytes[l];
+            return t;
+        };
+        int b = a;
+        while (b + 1 <= lmax && span_bytes(a - tau, b + 1) <= window_bytes) ++b;
+        // the window's strings, ascending ids, as a host set
+        const int lo = std::max(a - tau, 0);
+        std::vector<int32_t> ids(by_len.begin() + lstart[lo], by_len.begin() + lstart[b + 1]);
+        std::sort(ids.begin(), ids.end());
+        std::vector<int32_t> offs(ids.size() + 1, 0);
+        std::vector<uint8_t> buf((size_t)std::max<int64_t>(span_bytes(lo, b), 1));
+        for (size_t k = 0; k < ids.size(); ++k) {
+            const int32_t x0 = S->offsets[ids[k]], x1 = S->offsets[ids[k] + 1];
+            if (x1 > x0) memcpy(buf.data() + offs[k], S->bytes + x0, (size_t)(x1 - x0));
+            offs[k + 1] = offs[k] + (x1 - x0);
+        }
+        pj_strings sub{(int64_t)ids.size(), buf.data(), offs.data()};
+        pj_pairs part{};
+        t_stats = pj_stats{};
+        join_impl(nullptr, &sub, tau, &o, &part, true, nullptr, a);
+        for (int64_t k = 0; k < part.count; ++k) {
+            const int32_t u = ids[(size_t)part.a[k]], v = ids[(size_t)part.b[k]];
+            const int lu = S->offsets[u + 1] - S->offsets[u];
+            const int lv = S->offsets[v + 1] - S->offsets[v];
+            if (std::max(lu, lv) >= a) pairs.emplace_back(std::min(u, v), std::max(u, v));
+        }
+        pj_pairs_free(&part);
+        acc.strings += t_stats.strings;
+        acc.index_entries += t_stats.index_entries;
+        acc.selected += t_stats.selected;
+        acc.hits += t_stats.hits;
+        acc.candidates += t_stats.candidates;
+        acc.cells += t_stats.cells;
+        acc.accepted += t_stats.accepted;
+        acc.side_pairs += t_stats.side_pairs;
+        acc.ms_upload += t_stats.ms_upload;
+        acc.ms_index += t_stats.ms_index;
+        acc.ms_probe += t_stats.ms_probe;
+        acc.ms_verify += t_stats.ms_verify;
+        acc.ms_output += t_stats.ms_output;
+        acc.ms_probe_kernel += t_stats.ms_probe_kernel;
+        acc.ms_verify_kernel += t_stats.ms_verify_kernel;
+        acc.verify_launches += t_stats.verify_launches;
+        acc.ms_list_kernel += t_stats.ms_list_kernel;
+        acc.list_cells += t_stats.list_cells;
+        acc.list_launches += t_stats.list_launches;
+        a = b + 1;
+    }
+    std::sort(pairs.begin(), pairs.end());
+    const size_t m = pairs.size();
+    out->on_device = 0;
+    out->a = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
+    out->b = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
+    if (!out->a || !out->b) throw std::bad_alloc();
+    for (size_t k = 0; k < m; ++k) {
+        out->a[k] = pairs[k].first;
+        out->b[k] = pairs[k].second;
+    }
+    out->count = (int64_t)m;
+    acc.pairs = (int64_t)m;
+    acc.ms_total = std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t0).count();
+    t_stats = acc;
 }
 
 int self_join_with(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out,
@@ -852,6 +969,15 @@ extern "C" {
 int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pairs* out)
 {
     return guarded(out, [&] { join_impl(nullptr, S, tau, opt, out, true); });
+}
+
+int pj_self_join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes,
+                          const pj_options* opt, pj_pairs* out)
+{
+    return guarded(out, [&] {
+        if (!S) throw Error(PJ_EINVAL, "null pj_strings");
+        join_streamed(S, tau, window_bytes, opt, out);
+    });
 }
 
 int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,

@@ -107,6 +107,7 @@ struct ProbeSpec {
     SymMap sym;                        // the indexed set's symbol map (index keys)
     bool has_entries = true;           // some index has entries
     int selection = 0;                 // PJ_SELECT_*
+    int probe_min_len = 0;             // self-join: only strings at least this long probe
 };
 
 void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, JoinScratch& J,

@@ -52,6 +52,11 @@ def test_invalid_inputs_rejected_on_host():
     assert _err(P.pj_self_join, (long, np.array([0, 2048], np.int32)), 1) == P.PJ_ERANGE
     assert _err(P.pj_join, ok, (ok[0], np.array([0, 5, 3], np.int32)), 1) == P.PJ_EINVAL
     assert "offsets" in P.pj_last_error()
+    # streamed self-join: positive window, host strings
+    assert _err(P.pj_self_join_streamed, ok, 1, 0) == P.PJ_EINVAL
+    assert _err(P.pj_self_join_streamed, ok, 64, 100) == P.PJ_EINVAL
+    assert _err(P.pj_self_join_streamed, (ok[0], np.array([0, 4, 3], np.int32)), 1, 100) \
+        == P.PJ_EINVAL
     # substring-selection method outside PJ_SELECT_*
     assert _err(P.pj_self_join, ok, 1, selection=4) == P.PJ_EINVAL
     assert _err(P.pj_join, ok, ok, 1, selection=-1) == P.PJ_EINVAL
