@@ -221,6 +221,9 @@ def main():
     ap.add_argument("--selection", type=int, default=0,
                     help="substring selection: 0 multi-match (default), 1 position, 2 shift, "
                          "3 every substring (Sec. 4)")
+    ap.add_argument("--window-bytes", type=int, default=0,
+                    help="time pj_self_join_streamed with length windows of at most this many "
+                         "string bytes instead (host inputs and outputs: includes the copies)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotune cache file (written when tuning; with --no-tune it is only "
                          "read).  Default: a fresh file in the temp directory")
@@ -269,11 +272,20 @@ def main():
             tuning[str(t)] = r
             log(f"tuned tau={t}: {r}")
 
+    class _HostPairs:
+        def free(self):
+            pass
+
     def step(collect):
         outs = []
         for t in taus:
-            r = P.pj_self_join((chars, offs), t, mode=args.mode, outputs_on_device=True,
-                               stream=stream, tune_cache=cache, selection=args.selection)
+            if args.window_bytes:
+                P.pj_self_join_streamed(col, t, args.window_bytes, mode=args.mode,
+                                        tune_cache=cache, selection=args.selection)
+                r = _HostPairs()
+            else:
+                r = P.pj_self_join((chars, offs), t, mode=args.mode, outputs_on_device=True,
+                                   stream=stream, tune_cache=cache, selection=args.selection)
             st = P.pj_last_stats()
             outs.append(r)
             if collect is not None:
@@ -338,7 +350,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": args.n, "taus": taus, "mode": args.mode,
-                   **({"selection": args.selection} if args.selection else {})},
+                   **({"selection": args.selection} if args.selection else {}),
+                   **({"window_bytes": args.window_bytes, "inputs": "host"}
+                      if args.window_bytes else {})},
         "gcups": cells / max(verify_ms, 1e-9) / 1e6,
         "self_join_ms": {k: v["ms"] for k, v in per_tau.items()},
         "per_tau": per_tau,

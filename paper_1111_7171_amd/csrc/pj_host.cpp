@@ -866,54 +866,59 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         ++cnt[l];
         bytes[l] += l;
     }
-    // ids grouped by length, ascending within a length
-    std::vector<int64_t> lstart(kLenTab + 2, 0);
-    for (int l = 0; l <= kLenTab; ++l) lstart[l + 1] = lstart[l] + cnt[l];
-    std::vector<int32_t> by_len((size_t)std::max<int64_t>(n, 1));
-    {
-        std::vector<int64_t> fill(lstart.begin(), lstart.end() - 1);
-        for (int64_t k = 0; k < n; ++k)
-            by_len[(size_t)fill[S->offsets[k + 1] - S->offsets[k]]++] = (int32_t)k;
-    }
+    auto span_bytes = [&](int lo, int hi) {
+        int64_t t = 0;
+        for (int l = std::max(lo, 0); l <= hi; ++l) t += bytes[l];
+        return t;
+    };
+    // string lengths, scanned once per window (the windows' strings in ascending id order)
+    std::vector<uint16_t> len((size_t)std::max<int64_t>(n, 1));
+    for (int64_t k = 0; k < n; ++k) len[(size_t)k] = (uint16_t)(S->offsets[k + 1] - S->offsets[k]);
     pj_options o{};
     if (opt) o = *opt;
     o.outputs_on_device = 0;
     pj_stats acc{};
-    std::vector<std::pair<int32_t, int32_t>> pairs;
+    // each window's pairs as keys (a << 32 | b), ascending within the window
+    std::vector<std::vector<uint64_t>> runs;
     int lmax = -1;
     for (int l = 0; l <= kLenMax; ++l)
         if (cnt[l]) lmax = l;
+    std::vector<int32_t> ids;
+    std::vector<int32_t> offs;
+    std::vector<uint8_t> buf;
     int a = 0;
     while (a <= lmax) {
         while (a <= lmax && cnt[a] == 0) ++a;
         if (a > lmax) break;
-        auto span_bytes = [&](int lo, int hi) {
-            int64_t t = 0;
-            for (int l = std::max(lo, 0); l <= hi; ++l) t += bytes[l];
-            return t;
-        };
         int b = a;
         while (b + 1 <= lmax && span_bytes(a - tau, b + 1) <= window_bytes) ++b;
-        // the window's strings, ascending ids, as a host set
+        // the window's strings in ascending id order (so local order is global order)
         const int lo = std::max(a - tau, 0);
-        std::vector<int32_t> ids(by_len.begin() + lstart[lo], by_len.begin() + lstart[b + 1]);
-        std::sort(ids.begin(), ids.end());
-        std::vector<int32_t> offs(ids.size() + 1, 0);
-        std::vector<uint8_t> buf((size_t)std::max<int64_t>(span_bytes(lo, b), 1));
-        for (size_t k = 0; k < ids.size(); ++k) {
-            const int32_t x0 = S->offsets[ids[k]], x1 = S->offsets[ids[k] + 1];
-            if (x1 > x0) memcpy(buf.data() + offs[k], S->bytes + x0, (size_t)(x1 - x0));
-            offs[k + 1] = offs[k] + (x1 - x0);
+        ids.clear();
+        offs.assign(1, 0);
+        buf.resize((size_t)std::max<int64_t>(span_bytes(lo, b), 1));
+        for (int64_t k = 0; k < n; ++k) {
+            const int l = len[(size_t)k];
+            if (l < lo || l > b) continue;
+            if (l) memcpy(buf.data() + offs.back(), S->bytes + S->offsets[k], (size_t)l);
+            ids.push_back((int32_t)k);
+            offs.push_back(offs.back() + l);
         }
         pj_strings sub{(int64_t)ids.size(), buf.data(), offs.data()};
         pj_pairs part{};
         t_stats = pj_stats{};
         join_impl(nullptr, &sub, tau, &o, &part, true, nullptr, a);
+        // pairs with both strings in the halo [a - tau, a) come only from the short-string
+        // path, so the length filter is needed only when the window holds strings <= tau long
+        const bool filter = lo <= tau;
+        runs.emplace_back();
+        std::vector<uint64_t>& run = runs.back();
+        run.reserve((size_t)part.count);
         for (int64_t k = 0; k < part.count; ++k) {
-            const int32_t u = ids[(size_t)part.a[k]], v = ids[(size_t)part.b[k]];
-            const int lu = S->offsets[u + 1] - S->offsets[u];
-            const int lv = S->offsets[v + 1] - S->offsets[v];
-            if (std::max(lu, lv) >= a) pairs.emplace_back(std::min(u, v), std::max(u, v));
+            const int32_t la = part.a[k], lb = part.b[k];
+            if (filter && std::max(offs[la + 1] - offs[la], offs[lb + 1] - offs[lb]) < a)
+                continue;
+            run.push_back((uint64_t)(uint32_t)ids[(size_t)la] << 32 | (uint32_t)ids[(size_t)lb]);
         }
         pj_pairs_free(&part);
         acc.strings += t_stats.strings;
@@ -937,15 +942,31 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.list_launches += t_stats.list_launches;
         a = b + 1;
     }
-    std::sort(pairs.begin(), pairs.end());
-    const size_t m = pairs.size();
+    // k-way merge of the windows' sorted runs straight into the output arrays
+    size_t m = 0;
+    for (const auto& r : runs) m += r.size();
     out->on_device = 0;
     out->a = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     out->b = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     if (!out->a || !out->b) throw std::bad_alloc();
+    using Head = std::pair<uint64_t, size_t>;          // (key, run)
+    std::vector<Head> heap;
+    std::vector<size_t> pos(runs.size(), 0);
+    for (size_t r = 0; r < runs.size(); ++r)
+        if (!runs[r].empty()) heap.emplace_back(runs[r][0], r);
+    auto greater = [](const Head& x, const Head& y) { return x.first > y.first; };
+    std::make_heap(heap.begin(), heap.end(), greater);
     for (size_t k = 0; k < m; ++k) {
-        out->a[k] = pairs[k].first;
-        out->b[k] = pairs[k].second;
+        std::pop_heap(heap.begin(), heap.end(), greater);
+        const Head h = heap.back();
+        heap.pop_back();
+        out->a[k] = (int32_t)(h.first >> 32);
+        out->b[k] = (int32_t)(uint32_t)h.first;
+        const size_t r = h.second;
+        if (++pos[r] < runs[r].size()) {
+            heap.emplace_back(runs[r][pos[r]], r);
+            std::push_heap(heap.begin(), heap.end(), greater);
+        }
     }
     out->count = (int64_t)m;
     acc.pairs = (int64_t)m;
