@@ -57,6 +57,10 @@ def test_invalid_inputs_rejected_on_host():
     assert _err(P.pj_self_join_streamed, ok, 64, 100) == P.PJ_EINVAL
     assert _err(P.pj_self_join_streamed, (ok[0], np.array([0, 4, 3], np.int32)), 1, 100) \
         == P.PJ_EINVAL
+    # an empty set has no length window: no device work, no pairs
+    got = P.pj_self_join_streamed((np.zeros(0, np.uint8), np.zeros(1, np.int32)), 2, 100)
+    assert got.shape == (0, 2)
+    assert P.pj_last_stats()["pairs"] == 0
     # substring-selection method outside PJ_SELECT_*
     assert _err(P.pj_self_join, ok, 1, selection=4) == P.PJ_EINVAL
     assert _err(P.pj_join, ok, ok, 1, selection=-1) == P.PJ_EINVAL
