@@ -1025,7 +1025,8 @@ template <int GMAXW, int REGY, int NCT>
 __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         const Hit* __restrict__ big,
                                                         const uint32_t* __restrict__ segp,
-                                                        uint64_t nbig, uint64_t nseg,
+                                                        uint64_t /* hits (unused) */,
+                                                        uint64_t nseg,
                                                         const uint32_t* __restrict__ first,
                                                         uint64_t nchunks, uint32_t seg_chunk)
 {
