@@ -32,6 +32,16 @@ OPS_PER_CELL = 7   # recurrence: compare, add, min, add, min; expected distance:
 WORKLOAD = ("cfg2 short-string self-join: 1,000,000 strings, lengths round(N(15,4)) in [5,40], "
             "27 symbols (a-z, space) with English letter frequencies, 30% near-duplicates with "
             "1-4 edits, tau in {1,2,3,4}")
+# other workloads (--workload): generator, default size, default taus, description
+OTHER_WORKLOADS = {
+    "cfg3": ("cfg3", 500_000, "2,4,6,8",
+             "cfg3 medium-string self-join: 500,000 strings, lengths round(N(45,15)) in [10,120], "
+             "40 symbols with Zipf(1.1) frequencies, 20% near-duplicates with 1-8 edits"),
+    "cfg4": ("cfg4", 100_000, "8,16,32",
+             "cfg4 long-string self-join: 100,000 strings of words from a 20,000-word Zipf(1.0) "
+             "vocabulary, lengths round(LogNormal(ln 700, 0.5)) in [200,2000], 10% "
+             "near-duplicates with 1-40 edits"),
+}
 
 
 def log(*a):
@@ -206,8 +216,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--taus", default="1,2,3,4")
-    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--taus", default=None, help="default: 1,2,3,4 (cfg2)")
+    ap.add_argument("--n", type=int, default=None, help="default: 1,000,000 (cfg2)")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2"] + sorted(OTHER_WORKLOADS),
+                    help="cfg2 (the default benchmark) or another synthetic workload")
     ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 plain, 2 batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -241,9 +253,22 @@ def main():
     import paper_1111_7171_amd as P
     import workloads as W
 
+    workload = WORKLOAD
+    if args.workload == "cfg2":
+        args.n = args.n or 1_000_000
+        args.taus = args.taus or "1,2,3,4"
+        gen = W.cfg2
+    else:
+        name, n0, taus0, workload = OTHER_WORKLOADS[args.workload]
+        args.n = args.n or n0
+        args.taus = args.taus or taus0
+        gen = getattr(W, name)
+        # the CPU baseline's sampling and the serving run are sized for cfg2
+        args.no_cpu = True
+        args.no_serve = True
     taus = [int(t) for t in args.taus.split(",")]
-    log(f"generating workload n={args.n}")
-    col = W.cfg2(args.n)
+    log(f"generating workload {args.workload} n={args.n}")
+    col = gen(args.n)
     dev = torch.device("cuda:0")
     chars = torch.from_numpy(col.chars.copy()).to(dev)
     offs = torch.from_numpy(col.offsets.copy()).to(dev)
@@ -349,7 +374,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": args.n, "taus": taus, "mode": args.mode,
+        "config": {"workload": workload, "n": args.n, "taus": taus, "mode": args.mode,
                    **({"selection": args.selection} if args.selection else {}),
                    **({"window_bytes": args.window_bytes, "inputs": "host"}
                       if args.window_bytes else {})},

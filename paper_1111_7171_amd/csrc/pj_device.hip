@@ -738,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(VerifyParams V, Div div)
 // from the hits' end offsets with one OR-reduced boundary mask per 64 candidates.
 // ------------------------------------------------------------------------------------------
 
-constexpr int kWaveRounds = 16;
+constexpr int kWaveRounds = kBatchedRoundsMax;   // captured batches use the full chunk
 constexpr uint64_t kWaveChunk = 64ull * kWaveRounds;
 
 // Bucket of a hit: lists with at least `big` candidates after all smaller ones, each part in
@@ -796,14 +796,15 @@ __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__
     }
 }
 
-// first[ch] = the hit containing candidate ch * kWaveChunk (largest h with prefix[h] <= it)
+// first[ch] = the hit containing candidate ch * chunk (largest h with prefix[h] <= it)
 __global__ __launch_bounds__(kBlock) void k_chunk_starts(const unsigned long long* __restrict__ prefix,
                                                          uint64_t nhits, uint64_t nchunks,
+                                                         uint64_t chunk,
                                                          uint32_t* __restrict__ first)
 {
     const uint64_t ch = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (ch >= nchunks) return;
-    const unsigned long long c0 = ch * kWaveChunk;
+    const unsigned long long c0 = ch * chunk;
     uint64_t a = 0, b = nhits - 1;
     while (a < b) {
         const uint64_t m = (a + b + 1) >> 1;
@@ -857,9 +858,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
     const uint64_t nhits = V.dev_counts ? V.dev_counts[0] : V.nhits;
     const uint64_t ncand = V.dev_counts ? V.dev_counts[1] : V.ncand;
     const uint64_t nch = V.dev_counts ? V.dev_counts[2] : nchunks;
+    const uint64_t chunk = 64ull * (uint64_t)V.wave_rounds;
     for (uint64_t ch = wave; ch < nch; ch += nwaves) {
-        const uint64_t c0 = ch * kWaveChunk;
-        const uint64_t cend = (c0 + kWaveChunk < ncand) ? c0 + kWaveChunk : ncand;
+        const uint64_t c0 = ch * chunk;
+        const uint64_t cend = (c0 + chunk < ncand) ? c0 + chunk : ncand;
         uint64_t h = first[ch];
         unsigned long long hstart = V.prefix[h];
         for (uint64_t g0 = c0; g0 < cend; g0 += 64) {
@@ -1530,7 +1532,11 @@ static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint6
                        make_div(V.tau + 1), first, nchunks);
 }
 
-uint64_t batched_chunks(uint64_t ncand) { return (ncand + kWaveChunk - 1) / kWaveChunk; }
+uint64_t batched_chunks(uint64_t ncand, int rounds)
+{
+    const uint64_t chunk = 64ull * (uint64_t)rounds;
+    return (ncand + chunk - 1) / chunk;
+}
 
 unsigned slot_bucket_grid(uint64_t nh_cap)
 {
@@ -1622,9 +1628,10 @@ hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint3
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s)
 {
     if (V.ncand == 0) return hipSuccess;
-    const uint64_t nchunks = batched_chunks(V.ncand);
+    if (V.wave_rounds < 1 || V.wave_rounds > kWaveRounds) return hipErrorInvalidValue;
+    const uint64_t nchunks = batched_chunks(V.ncand, V.wave_rounds);
     hipLaunchKernelGGL(k_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, V.prefix,
-                       V.nhits, nchunks, first);
+                       V.nhits, nchunks, 64ull * (uint64_t)V.wave_rounds, first);
     const int w = V.tau + 1;
     if (w <= 9) verify_batched_w<9>(V, first, nchunks, grid, s);
     else if (w <= 17) verify_batched_w<17>(V, first, nchunks, grid, s);

@@ -128,6 +128,7 @@ GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t s
     vp.x_arena = pp.x_arena; vp.x_slen = pp.x_slen; vp.x_lenstart = pp.x_lenstart;
     vp.x_gbase = pp.x_gbase;
     vp.y_arena = Y.sarena; vp.y_lenstart = Y.lenstart; vp.y_gbase = Y.gbase;
+    vp.wave_rounds = kBatchedRoundsMax;               // fixed chunk: the sizes are on device
     vp.y_inl = nullptr;                               // serving indices keep no inline copies
     vp.y_inl_base = nullptr;
     vp.hits = hits;

@@ -595,7 +595,13 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             int k0 = tm.mark();
             if (batched) {
                 if (ncand_small > 0) {
-                    const uint64_t nchunks = batched_chunks(ncand_small);
+                    // at least ~32 wave chunks per CU before a wave takes more than one round
+                    // of 64 candidates: a few long candidates (long strings, high tau) then
+                    // still spread over the whole device
+                    const uint64_t per = (uint64_t)device_cus() * 32ull * 64ull;
+                    vp.wave_rounds = (int)std::max<uint64_t>(
+                        1, std::min<uint64_t>((uint64_t)kBatchedRoundsMax, ncand_small / per));
+                    const uint64_t nchunks = batched_chunks(ncand_small, vp.wave_rounds);
                     uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
                     // persistent: enough waves to fill the chip, each walking its chunks
                     const uint64_t waves = std::min<uint64_t>(

@@ -25,6 +25,7 @@ constexpr int kHashBits = 40;          // hash bits kept in an index key
 constexpr uint64_t kEmptyKey = ~0ull;  // keys use at most 57 bits, so this never collides
 
 __host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 15) & ~15); }
+constexpr int kBatchedRoundsMax = 16;   // rounds of 64 candidates per batched-verify wave chunk
 constexpr int kInlineMaxLen = 64;       // longest string the list-segment kernel keeps in registers
 
 // Symbol map of an indexed set: code[b] = 1 + rank of byte b among the bytes the set contains
@@ -130,6 +131,7 @@ struct VerifyParams {
     // when set they replace nhits, ncand and the launch's chunk count
     const unsigned long long* dev_counts;
     int exact_len;              // segments up to this length have exact keys (no byte guard)
+    int wave_rounds;            // batched verification: rounds of 64 candidates per wave chunk
 };
 
 // ---- launchers (pj_device.hip) ----
@@ -177,7 +179,8 @@ hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint3
                               int lane_cands, int grid, hipStream_t s);
 uint64_t seg_chunks(uint64_t nseg, int chunk);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
-uint64_t batched_chunks(uint64_t ncand);
+// wave chunks of 64 * rounds candidates (rounds in [1, kBatchedRoundsMax])
+uint64_t batched_chunks(uint64_t ncand, int rounds);
 // A captured query batch: every size is read from device memory, so one instantiated graph
 // serves every batch.  counters: [0] hits [1] candidates [2] selected [3] accepted [4] cells
 // [5] guard misses [6] side pairs [7] unused; bcounts: [0] hits [1] candidates [2] wave chunks
