@@ -601,6 +601,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     const uint64_t per = (uint64_t)device_cus() * 32ull * 64ull;
                     vp.wave_rounds = (int)std::max<uint64_t>(
                         1, std::min<uint64_t>((uint64_t)kBatchedRoundsMax, ncand_small / per));
+                    // tests force the chunk size (it changes no result)
+                    if (const char* e = getenv("PJ_BATCHED_ROUNDS"))
+                        vp.wave_rounds = std::max(1, std::min(kBatchedRoundsMax, atoi(e)));
                     const uint64_t nchunks = batched_chunks(ncand_small, vp.wave_rounds);
                     uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
                     // persistent: enough waves to fill the chip, each walking its chunks

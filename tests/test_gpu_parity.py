@@ -262,3 +262,18 @@ def test_symbol_map_all_byte_values():
         st = P.pj_last_stats()
         _same(got, pj.pairs, f"bytes tau={tau}")
         assert st["candidates"] == pj.candidates
+
+
+@pytest.mark.parametrize("rounds", ["1", "3", "16"])
+def test_batched_chunk_sizes(rounds, monkeypatch):
+    # the small-list kernel's wave chunks (64 x rounds candidates) change no result
+    monkeypatch.setenv("PJ_BATCHED_ROUNDS", rounds)
+    col = W.cfg3(6_000, seed=71)
+    for tau in (2, 4, 6):
+        _say("batched rounds", rounds, "tau", tau)
+        got = P.pj_self_join(col, tau, mode=P.MODE_BATCHED)
+        st = P.pj_last_stats()
+        pj = O.self_join_pj(col, tau)
+        _same(got, pj.pairs, f"rounds={rounds} tau={tau}")
+        assert st["candidates"] == pj.candidates
+        assert st["cells"] == pj.cells
