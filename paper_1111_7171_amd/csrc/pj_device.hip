@@ -1016,6 +1016,48 @@ __device__ inline void vsp_seg_dispatch(bool yrows, LdsChars U, int lu, const La
 #undef PJ_SEG_CASE
 }
 
+template <int MAXW, int KF, int TS>
+__device__ inline void vsp_lane_or(bool yrows, LdsChars U, int lu, LdsLaneChars V, int lv, int t,
+                                   LdsInts tab, bool act, int& cells, int& res)
+{
+    if (yrows) vsp_lane<MAXW, KF, true, TS>(U, lu, V, lv, t, tab, act, cells, res);
+    else vsp_lane<MAXW, KF, false, TS>(U, lu, V, lv, t, tab, act, cells, res);
+}
+
+// vsp_lane at width t + 1 (the width class GMAXW when t + 1 reaches it); for t <= 4 the band
+// index of the final cell, (t + |lu - lv|) / 2, is a compile-time constant too
+template <int GMAXW, int TS>
+__device__ inline void vsp_lane_dispatch(bool yrows, LdsChars U, int lu, LdsLaneChars V, int lv,
+                                         int t, LdsInts tab, bool act, int& cells, int& res)
+{
+    static_assert(GMAXW >= 5 && GMAXW <= 9, "narrow width classes only");
+    const int delta = lu > lv ? lu - lv : lv - lu;
+    if (delta > t) {
+        cells = 0;
+        res = t + 1;
+        return;
+    }
+    const int kf = (t + delta) >> 1;
+    cells = 0;                                   // t < GMAXW always; kept defined regardless
+    res = t + 1;
+#define PJ_LANE(W, K) vsp_lane_or<W, K, TS>(yrows, U, lu, V, lv, t, tab, act, cells, res)
+    switch (t) {
+    case 0: PJ_LANE(1, 0); return;
+    case 1: if (kf == 0) PJ_LANE(2, 0); else PJ_LANE(2, 1); return;
+    case 2: if (kf == 1) PJ_LANE(3, 1); else PJ_LANE(3, 2); return;
+    case 3: if (kf == 1) PJ_LANE(4, 1); else if (kf == 2) PJ_LANE(4, 2); else PJ_LANE(4, 3); return;
+    case 4: if (kf == 2) PJ_LANE(5, 2); else if (kf == 3) PJ_LANE(5, 3); else PJ_LANE(5, 4); return;
+    default: break;
+    }
+    if constexpr (GMAXW > 5) {
+        if (t == 5 && GMAXW > 6) { PJ_LANE(6 < GMAXW ? 6 : GMAXW, -1); return; }
+        if (t == 6 && GMAXW > 7) { PJ_LANE(7 < GMAXW ? 7 : GMAXW, -1); return; }
+        if (t == 7 && GMAXW > 8) { PJ_LANE(8 < GMAXW ? 8 : GMAXW, -1); return; }
+        PJ_LANE(GMAXW, -1);
+    }
+#undef PJ_LANE
+}
+
 // a wave-uniform load through the scalar cache (read-only data)
 template <typename T>
 __device__ inline T uniform_load(const T* p)
@@ -1032,19 +1074,44 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                                                         const uint32_t* __restrict__ first,
                                                         uint64_t nchunks, uint32_t seg_chunk)
 {
-    __shared__ uint64_t s_acc[kWaves][kAppendCap];
-    // the current probe string; the band DP may read up to MAXW + t <= 127 bytes past its end
-    __shared__ uint32_t s_x[kWaves][(kLenMax + 1 + 128 + 3) / 4];
-    __shared__ uint32_t s_q[kWaves][256];                 // left-part survivors (gy)
-    // band tables of the current hit's two parts (row 0, distance offsets, first window)
+    // NC candidates per lane: a list segment has 64 * NC members
+    constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
+    constexpr uint32_t SEG = 64u * NC;
+    // one candidate per lane with the indexed strings in registers: each lane also copies its
+    // string into an LDS slot, from which the band DP reads it (vsp_lane)
+    constexpr bool LANE = REGY > 0 && NC == 1 && GMAXW <= 9;
+    // slot stride REGY + 4 bytes, an odd number of words, so a wave's reads at one offset hit
+    // distinct banks; 16 bytes before the first slot and after the last absorb the reads of
+    // columns outside the string (at most 4 before a string and 2 * 9 - 2 - 4 after it)
+    constexpr int SL = REGY + 4, YPAD = 16, YTAIL = 16;
+    constexpr int kCap = 96;                               // pairs buffered per wave
+    __shared__ uint64_t s_acc[kWaves][kCap];
+    // the current probe string; the band DP reads at most 2 * MAXW bytes past a part's end
+    // (vsp_seg and vsp_lane up to width 9; the wider classes keep 128).  An indexed string of
+    // at most REGY bytes has probes of at most REGY + tau bytes.
+    constexpr int XMAX = REGY > 0 ? REGY + kTauMax : kLenMax;
+    constexpr int XPAD = GMAXW <= 9 ? 32 : 128;
+    __shared__ uint32_t s_x[kWaves][(XMAX + 1 + XPAD + 3) / 4];
+    __shared__ uint32_t s_q[kWaves][2 * SEG];             // left-part survivors
+    // band tables of the current hit's two parts (row 0, distance offsets, first window, and
+    // the rows of vsp_lane)
     constexpr int BTS = (GMAXW + 3) & ~3;
-    __shared__ __attribute__((aligned(16))) int s_band[kWaves][2][3 * BTS];
-    WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
+    constexpr int CT = LANE ? REGY + 4 : 0;               // cells table: rows 0 .. nr <= REGY
+    __shared__ __attribute__((aligned(16))) int s_band[kWaves][2][6 * BTS + CT];
+    constexpr int YW = LANE ? (YPAD + 64 * SL + YTAIL) / 4 : 1;
+    __shared__ __attribute__((aligned(16))) uint32_t s_y[kWaves][YW];   // lane slots (LANE)
+    WaveAppender<uint64_t, kCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     uint32_t* sx = s_x[threadIdx.x >> 6];
     uint32_t* sq = s_q[threadIdx.x >> 6];
     const __attribute__((address_space(3))) uint8_t* xl8 =
         (const __attribute__((address_space(3))) uint8_t*)(sx);
+    // this lane's slot (LANE)
+    __attribute__((address_space(3))) uint32_t* ysw =
+        (__attribute__((address_space(3))) uint32_t*)(s_y[threadIdx.x >> 6]) +
+        (YPAD + lane * SL) / 4;
+    const __attribute__((address_space(3))) uint8_t* ys8 =
+        (const __attribute__((address_space(3))) uint8_t*)(ysw);
     // wave id as a scalar, so that everything derived from it is known to be wave-uniform
     const uint64_t wave = (uint64_t)blockIdx.x * kWaves +
                           (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1093,19 +1160,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             // with t = tau+1-i (Algorithm 3)
             const int tl = i - 1, tr = tau + 1 - i;
             const int ry = sgm.p - 1 + sgm.len, rx = p - 1 + sgm.len;
-            // NC candidates per lane: a list segment has 64 * NC members
-            constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
             // the previous hit's table reads were issued before these writes
             __attribute__((address_space(3))) int* tab_l =
                 (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][0];
             __attribute__((address_space(3))) int* tab_r =
                 (__attribute__((address_space(3))) int*)s_band[threadIdx.x >> 6][1];
-            band_table(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane, BTS, NC == 2, tab_l);
-            band_table(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane, BTS, NC == 2, tab_r);
+            band_table(LdsChars{xl8}, p - 1, sgm.p - 1, tl, lane, BTS, NC == 2, tab_l, CT);
+            band_table(LdsChars{xl8 + rx}, n - rx, l - ry, tr, lane, BTS, NC == 2, tab_r, CT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            constexpr uint32_t SEG = 64u * NC;
             const uint32_t hsegs = (count + SEG - 1) / SEG;
             const uint64_t left_in_chunk = sg_end - sg_i;
             const uint32_t s_stop = (uint64_t)(hsegs - sidx) < left_in_chunk
@@ -1116,10 +1180,28 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
             // yinl + e * stride), so a segment's loads are coalesced and need no list entry first
             const uint8_t* yinl = nullptr;
             if (REGY > 0 && V.y_inl) yinl = V.y_inl + uniform_load(V.y_inl_base + l);
+            // REGY > 0: the indexed string's words (at most REGY bytes) go to registers, or,
+            // with LANE, straight into the lane's LDS slot (a wave's LDS requests complete in
+            // order: the DP's reads see these words, the previous DP's reads did not); words
+            // past the string are not loaded
             auto load_y = [&](uint32_t g, uint32_t e, uint32_t* yr) -> const uint8_t* {
                 const uint8_t* y = yinl ? yinl + (int64_t)e * stride_of(l)
                                         : V.y_arena + ybase + (int64_t)g * stride_of(l);
-                if (REGY > 0) {
+                if constexpr (LANE) {
+                    // every load first, then the writes: one wait for all of them
+                    const uint4* yq = reinterpret_cast<const uint4*>(y);
+                    uint4 v[REGY / 16];
+#pragma unroll
+                    for (int q = 0; q < REGY / 16; ++q)
+                        if (q * 16 < l) v[q] = yq[q];
+#pragma unroll
+                    for (int q = 0; q < REGY / 16; ++q) {
+                        if (q * 16 < l) {
+                            ysw[4 * q] = v[q].x; ysw[4 * q + 1] = v[q].y;
+                            ysw[4 * q + 2] = v[q].z; ysw[4 * q + 3] = v[q].w;
+                        }
+                    }
+                } else if (REGY > 0) {
                     const uint4* yq = reinterpret_cast<const uint4*>(y);
 #pragma unroll
                     for (int q = 0; q < (REGY > 0 ? REGY / 16 : 0); ++q) {
@@ -1154,7 +1236,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
                 uint32_t gy[NC], ent[NC];
-                uint32_t yr[NC][REGY > 0 ? REGY / 4 : 1];
+                uint32_t yr[NC][(REGY > 0 && !LANE) ? REGY / 4 : 1];
                 const uint8_t* y[NC];
                 bool ok[NC];
                 bool anyok = false;
@@ -1178,7 +1260,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                         }
                     } else if (ok[c]) {
                         ent[c] = start + member;
-                        gy[c] = vals[start + member];
+                        // string positions are needed to load the string (no inline copies)
+                        // or to emit the pair; a queued survivor is kept as its entry
+                        if (!yinl || right || right_trivial) gy[c] = vals[start + member];
                     }
                     y[c] = V.y_arena;
                     if (ok[c]) {
@@ -1188,7 +1272,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                             // verification, which skips the segment
                             const LdsChars xs{xl8 + (p - 1)};
                             bool same = true;
-                            if (REGY > 0) {
+                            if constexpr (LANE) {
+                                const LdsLaneChars yc{ys8 + (sgm.p - 1)};
+                                for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
+                            } else if constexpr (REGY > 0) {
                                 const RegChars yc{yr[c], sgm.p - 1};
                                 for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
                             } else {
@@ -1206,7 +1293,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     const int yo = right ? ry : 0, yl = right ? l - ry : sgm.p - 1;
                     const int tt = right ? tr : tl;
                     int cl[NC], d[NC];
-                    if constexpr (REGY > 0) {
+                    if constexpr (LANE) {
+                        vsp_lane_dispatch<GMAXW, BTS>(yl <= xl, LdsChars{xl8 + xo}, xl,
+                                                      LdsLaneChars{ys8 + yo}, yl, tt,
+                                                      right ? tab_r : tab_l, ok[0], cl[0], d[0]);
+                    } else if constexpr (REGY > 0) {
                         RegChars vc[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) vc[c] = RegChars{yr[c], yo};

@@ -426,11 +426,16 @@ struct LdsChars {
 constexpr uint32_t kBig16 = 0x4000u;
 
 // Row 0, the expected-distance offsets |kfin - k| and (rows from y) the first column window of
-// one part's band, as a table in the wave's LDS: entry k of each of the three rows of TS
-// ints.  Written once per hit by lanes k < TS (every lane computes its entry), then read by
-// every candidate's DP with broadcast loads.
+// one part's band, as a table in the wave's LDS: entry k of each row of TS ints.  Written once
+// per hit by lanes k < TS (every lane computes its entry), then read by every candidate's DP
+// with broadcast loads.  Unpacked tables have three more rows for vsp_lane: row 0 plus the
+// offsets (BIG outside the band), and the neighbour adjustments 1 + ek(k) - ek(k + 1) and
+// 1 + ek(k) - ek(k - 1) (each 0 or 2); with ct > 0 they are followed by ct entries holding the
+// band's cells in rows 1..s for s = 0 .. ct-1 (s <= nr), from which a DP reads its count.
+__device__ inline int band_cells(int s, int nc, int a, int b);
 __device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, int ts,
-                                  bool packed, __attribute__((address_space(3))) int* tab)
+                                  bool packed, __attribute__((address_space(3))) int* tab,
+                                  int ct = 0)
 {
     const bool yrows = lv <= lu;
     const int nr = yrows ? lv : lu;
@@ -454,7 +459,13 @@ __device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, i
             tab[lane] = r0;
             tab[ts + lane] = ek;
             tab[2 * ts + lane] = w0;
+            tab[3 * ts + lane] = r0 == (1 << 20) ? r0 : r0 + ek;
+            tab[4 * ts + lane] = kfin > lane ? 2 : 0;
+            tab[5 * ts + lane] = kfin < lane ? 2 : 0;
         }
+    }
+    if (ct > 0 && delta <= t) {
+        for (int s = lane; s < ct && s <= nr; s += 64) tab[6 * ts + s] = band_cells(s, nc, a, b);
     }
 }
 
@@ -603,6 +614,121 @@ __device__ inline void vsp_seg(LdsChars U, int lu, const LaneChars (&V)[NC], int
         cells[c] = act[c] ? band_cells(nrows, nc, a, b) : 0;
         res[c] = (act[c] && all) ? out : t + 1;
     }
+}
+
+// A lane's own copy of its indexed string in the wave's LDS (one slot per lane), read at
+// wave-uniform offsets: no register-array indexing.  Bytes before and after the string are
+// other lanes' bytes or padding, which the band DP may read wherever any byte will do.
+struct LdsLaneChars {
+    const __attribute__((address_space(3))) uint8_t* p;
+    __device__ inline int operator[](int k) const { return (int)p[k]; }
+};
+
+// The band DP of vsp_seg in the form that keeps each cell's expected distance
+// D(i, k) = M(i, k) + |kfin - k| instead of M: the recurrence keeps its shape,
+//   D(i, k) = min(D(i-1, k) + [mismatch], D(i-1, k+1) + cu(k), D(i, k-1) + cl(k)),
+// with cu(k) = 1 + ek(k) - ek(k+1) = 2 left of band index kfin (else 0) and
+// cl(k) = 1 + ek(k) - ek(k-1) = 2 right of it (else 0), since adjacent diagonals' offsets
+// differ by exactly one; a row passes when its smallest D is at most t (Lemma 4), and the
+// distance is D at band index kfin, whose offset is 0.  Every cell is the M of vsp_seg plus a
+// constant of its band index, so the rows evaluated and the verdicts are those of vsp_seg
+// (which argues the unmasked band, the BIG borders and the pass counting).  KF >= 0 is kfin
+// as a constant (the adjustments become adds of 2 on one side only); KF < 0 reads the
+// adjustments from the table.  Member characters come from the lane's LDS copy, the probe's
+// from the shared buffer; the row limit is folded into the last row's threshold, so a row
+// costs one wave vote.
+template <int MAXW, int KF, bool YROWS, int TS>
+__device__ inline void vsp_lane(LdsChars U, int lu, LdsLaneChars V, int lv, int t,
+                                const __attribute__((address_space(3))) int* tab, bool act,
+                                int& cells, int& res)
+{
+    static_assert(MAXW <= 9 && KF < MAXW, "rotating window of at most 9 columns");
+    const int nr = YROWS ? lv : lu;
+    const int nc = YROWS ? lu : lv;
+    const int delta = nc - nr;
+    cells = 0;
+    res = t + 1;
+    if (delta > t) return;
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;              // kfin: band index of cell (nr, nc)
+    constexpr int BIG = 1 << 20;
+    int D[MAXW], w[MAXW], cu[MAXW], cl[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        D[k] = act ? tab[3 * TS + k] : BIG;
+        if (KF < 0) {
+            cu[k] = __builtin_amdgcn_readfirstlane(tab[4 * TS + k]);
+            cl[k] = __builtin_amdgcn_readfirstlane(tab[5 * TS + k]);
+        }
+        // column window before row 1: column k - a (any byte outside 1..nc)
+        w[k] = YROWS ? tab[2 * TS + k] : V[k - a];
+    }
+    int passes = 0;                              // rows passed before row nr
+    if (nr > 0) {
+        int done_rows = 0;
+        for (;;) {
+            // rows s+1 .. s+MAXW: row characters at s + u, entering column characters at
+            // MAXW - a + s + u; the rotating window as in vsp_seg
+            const int s = __builtin_amdgcn_readfirstlane(done_rows);
+            const int lim = nr - 1 - s;          // steps u < lim are rows before row nr
+            const auto rp = YROWS ? V.p + s : U.p + s;
+            const auto cp = YROWS ? U.p + (MAXW - a) + s : V.p + (MAXW - a) + s;
+            // the block's characters are read up front, so one LDS round trip serves MAXW rows
+            // (past row nr they are padding or other lanes' bytes, never used)
+            int rc[MAXW], cc[MAXW];
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                rc[u] = rp[u];
+                cc[u] = cp[u];
+            }
+            bool stop = false;
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                const int ai = rc[u];
+                const int cin = cc[u];
+                int left = BIG;
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) {
+                    const int up = (k + 1 < MAXW) ? D[(k + 1) < MAXW ? k + 1 : k] : BIG;
+                    const int dg = D[k] + ((ai != w[(u + k) % MAXW]) ? 1 : 0);
+                    int upa, lfa;
+                    if constexpr (KF >= 0) {
+                        upa = k < KF ? up + 2 : up;
+                        lfa = k > KF ? left + 2 : left;
+                    } else {
+                        upa = up + cu[k];
+                        lfa = left + cl[k];
+                    }
+                    const int v = min(min(upa, lfa), dg);
+                    D[k] = v;
+                    left = v;
+                }
+                int emin = D[0];
+#pragma unroll
+                for (int k = 1; k + 1 < MAXW; k += 2) emin = min(emin, min(D[k], D[k + 1]));
+                if ((MAXW & 1) == 0) emin = min(emin, D[MAXW - 1]);
+                // row nr counts as failed: the vote then ends the loop there
+                const int th = u < lim ? t : -1;
+                const bool pass = emin <= th;
+                passes += pass ? 1 : 0;
+                if (__builtin_amdgcn_ballot_w64(pass) == 0) {
+                    stop = true;
+                    break;
+                }
+                w[u] = cin;
+            }
+            if (stop) break;
+            done_rows = s + MAXW;
+        }
+    }
+    // a lane that passed every row before row nr evaluated all nr rows and its distance is D
+    // at kfin; otherwise it evaluated the rows it passed and one more (cells from the table)
+    const int rows = min(passes + 1, nr);
+    int dk;
+    if constexpr (KF >= 0) dk = D[KF];
+    else dk = D[__builtin_amdgcn_readfirstlane(b)];
+    res = (act && passes >= nr - 1) ? min(dk, t + 1) : t + 1;
+    cells = act ? tab[6 * TS + rows] : 0;
 }
 
 // Two candidates per lane (members of one list, so one band geometry), packed as the low and

@@ -537,6 +537,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         nbig = J.nhits - nsmall;
     }
 
+    const Hit* bigp = J.hits + nsmall;
+
     // candidate prefix sums of the (small) lists, list segments of the big ones
     J.prefix = (unsigned long long*)W.get("join.prefix",
                                           sizeof(unsigned long long) * (size_t)(nsmall + 1));
@@ -550,7 +552,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     if (nbig > 0) {
         uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
         segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + 1));
-        hip_check(launch_seg_counts(J.hits + nsmall, nbig,
+        hip_check(launch_seg_counts(bigp, nbig,
                                     seg_members(Y.lmax, tau, J.tp.lane_cands), segs, st),
                   "seg_counts");
         size_t sb = scan_tmp_bytes(nbig);
@@ -619,7 +621,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     const uint64_t waves = std::min<uint64_t>(
                         nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
                     const int s0 = tm.mark();
-                    hip_check(launch_verify_segs(vp, J.hits + nsmall, segp, nbig, nseg, first,
+                    hip_check(launch_verify_segs(vp, bigp, segp, nbig, nseg, first,
                                                  J.tp.seg_chunk, J.tp.lane_cands,
                                                  (int)((waves + 3) / 4), st),
                               "verify_segs");
