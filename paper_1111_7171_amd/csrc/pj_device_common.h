@@ -252,13 +252,17 @@ __device__ inline int vsp_global(const uint8_t* r, int lr, const uint8_t* s, int
     return res;
 }
 
-// Branch-free VerifyStringPair for the batched path: the same arithmetic, orientation, band,
-// saturation, early stop and cell count as vsp_global, written so that a row issues no branch
-// and no dependent load: the band's column characters B[j-1] (j = i - a + k) sit in a register
-// window w[k] that shifts by one per row, the character entering the window and the next row
-// character are loaded one row ahead, out-of-band or out-of-matrix cells are masked with
-// selects, and the row's recurrence-cell count is computed from the band bounds.
-// Characters outside the string read as 256, which equals no byte.
+// Cells of rows 1..s of the band (closed form, defined below).
+__device__ inline int band_cells(int s, int nc, int a, int b);
+
+// VerifyStringPair for the batched path (one candidate per lane, each lane with its own
+// strings and band): the same orientation, band, early stop, result and cell count as
+// vsp_global, computed as vsp_lane does, on expected distances D = M + |kfin - k| with the
+// neighbour adjustments cu, cl (0 or 2) and no masks (the argument given for vsp_seg covers the
+// BIG borders, the unmasked band indices past a + b and the characters outside 1..nc, which
+// read as 256 here).  The band's column characters sit in a register window that shifts by one
+// per row; the character entering it and the next row character are loaded a row ahead.  The
+// cells of the rows evaluated follow in closed form.
 template <int MAXW>
 __device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
                                int* cells)
@@ -272,55 +276,44 @@ __device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int l
     *cells = 0;
     if (delta > t) return t + 1;
     const int a = (t - delta) >> 1;
-    const int b = (t + delta) >> 1;
-    const int W = a + b + 1;
-    const int INF = t + 1;
+    const int b = (t + delta) >> 1;              // kfin: band index of cell (nr, nc)
     constexpr int BIG = 1 << 20;
-    int R[MAXW], w[MAXW], ek[MAXW];
+    int D[MAXW], w[MAXW], cu[MAXW], cl[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) {
-        const int j = k - a;
-        R[k] = (k < W && j >= 0 && j <= nc) ? (j < INF ? j : INF) : INF;
-        const int idx = k - a;                       // B index of column j = 1 - a + k, row 1
-        w[k] = ((unsigned)idx < (unsigned)nc) ? (int)B[idx] : 256;
-        const int dd = delta + a - k;
-        ek[k] = dd < 0 ? -dd : dd;
+        const int j = k - a;                     // column of band index k in row 0
+        const int ek = b > k ? b - k : k - b;
+        D[k] = (j >= 0 && j <= min(nc, b)) ? j + ek : BIG;
+        w[k] = ((unsigned)j < (unsigned)nc) ? (int)B[j] : 256;   // B index of row 1's column
+        cu[k] = k < b ? 2 : 0;
+        cl[k] = k > b ? 2 : 0;
     }
-    // character entering the window at row 2, and the row characters of rows 1 and 2
-    int idx_in = MAXW - a;                           // B index of column j = 2 - a + MAXW - 1
+    int idx_in = MAXW - a;                       // B index entering the window after row 1
     int cin = ((unsigned)idx_in < (unsigned)nc) ? (int)B[idx_in] : 256;
     int ai = nr > 0 ? (int)A[0] : 256;
     int ai_next = nr > 1 ? (int)A[1] : 256;
-    int ncell = 0;
-    int res = -1;
+    int rows = nr;
+    bool failed = false;
     for (int i = 1; i <= nr; ++i) {
         // loads for the next row first, so their latency overlaps this row's arithmetic
         const int idx2 = idx_in + 1;
         const int cin_next = ((unsigned)idx2 < (unsigned)nc) ? (int)B[idx2] : 256;
         const int ai_next2 = (i + 1 < nr) ? (int)A[i + 1] : 256;
-        const int j0 = i - a;
-        int left = INF;
-        int emin = BIG;
+        int left = BIG;
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) {
-            const int j = j0 + k;
-            const bool valid = (k < W) && j >= 0 && j <= nc;
-            const int up = (k + 1 < MAXW) ? R[(k + 1) < MAXW ? k + 1 : k] : INF;
-            const int upk = (k + 1 < W) ? up : INF;
-            const int d = (ai != w[k]) ? 1 : 0;
-            int v = min(min(upk, left) + 1, R[k] + d);
-            v = min(v, INF);
-            v = (j == 0) ? min(i, INF) : v;
-            v = valid ? v : INF;
-            emin = min(emin, valid ? v + ek[k] : BIG);
-            R[k] = v;
+            const int up = (k + 1 < MAXW) ? D[(k + 1) < MAXW ? k + 1 : k] : BIG;
+            const int dg = D[k] + ((ai != w[k]) ? 1 : 0);
+            const int v = min(min(up + cu[k], left + cl[k]), dg);
+            D[k] = v;
             left = v;
         }
-        // recurrence cells of this row: j in [max(1, i - a), min(nc, i - a + W - 1)]
-        const int lo = max(1, j0), hi = min(nc, j0 + W - 1);
-        ncell += max(0, hi - lo + 1);
+        int emin = D[0];
+#pragma unroll
+        for (int k = 1; k < MAXW; ++k) emin = min(emin, D[k]);
         if (emin > t) {
-            res = t + 1;
+            rows = i;
+            failed = true;
             break;
         }
 #pragma unroll
@@ -331,13 +324,12 @@ __device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int l
         ai = ai_next;
         ai_next = ai_next2;
     }
-    *cells = ncell;
-    if (res >= 0) return res;
-    int out = INF;
+    *cells = band_cells(rows, nc, a, b);
+    if (failed) return t + 1;
+    int out = BIG;
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k)
-        if (k == delta + a) out = R[k];
-    return out;
+    for (int k = 0; k < MAXW; ++k) out = (k == b) ? D[k] : out;
+    return min(out, t + 1);
 }
 
 // VerifyStringPair for a wave whose lanes share the probe string's part and the band geometry
@@ -432,7 +424,6 @@ constexpr uint32_t kBig16 = 0x4000u;
 // offsets (BIG outside the band), and the neighbour adjustments 1 + ek(k) - ek(k + 1) and
 // 1 + ek(k) - ek(k - 1) (each 0 or 2); with ct > 0 they are followed by ct entries holding the
 // band's cells in rows 1..s for s = 0 .. ct-1 (s <= nr), from which a DP reads its count.
-__device__ inline int band_cells(int s, int nc, int a, int b);
 __device__ inline void band_table(LdsChars U, int lu, int lv, int t, int lane, int ts,
                                   bool packed, __attribute__((address_space(3))) int* tab,
                                   int ct = 0)
