@@ -1245,46 +1245,39 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
                     const uint32_t member = sidx * SEG + slot;
                     ok[c] = from_queue ? slot < k : member < count;
-                    // the two sources in separate uniform branches (one merged load would be a
-                    // flat load of LDS or global memory)
-                    // the queue holds index entries (inline copies) or string positions
-                    gy[c] = 0;
-                    ent[c] = 0;
-                    if (from_queue) {
-                        const uint32_t q = sq[slot];          // slot < 2 * SEG: in bounds
-                        if (yinl) {
-                            ent[c] = ok[c] ? q : 0u;
-                            if (ok[c]) gy[c] = vals[q];
-                        } else {
-                            gy[c] = ok[c] ? q : 0u;
-                        }
-                    } else if (ok[c]) {
-                        ent[c] = start + member;
-                        // string positions are needed to load the string (no inline copies)
-                        // or to emit the pair; a queued survivor is kept as its entry
-                        if (!yinl || right || right_trivial) gy[c] = vals[start + member];
+                    // every lane takes a valid candidate (an inactive one repeats the first
+                    // queued candidate, k >= 1, or the hit's last member, count >= 1), so the
+                    // loads below need no per-lane branch; only active lanes count.  The queue
+                    // holds index entries (inline copies) or string positions.
+                    uint32_t src;
+                    if (from_queue) src = sq[ok[c] ? slot : 0u];     // slot < 2 * SEG
+                    else src = start + (ok[c] ? member : count - 1u);
+                    if (yinl) {
+                        ent[c] = src;
+                        // string positions are needed only to emit pairs
+                        gy[c] = (right || right_trivial) ? vals[src] : 0u;
+                    } else {
+                        ent[c] = 0;
+                        gy[c] = from_queue ? src : vals[src];
                     }
-                    y[c] = V.y_arena;
-                    if (ok[c]) {
-                        y[c] = load_y(gy[c], ent[c], yr[c]);
-                        if (!from_queue && sgm.len > V.exact_len) {
-                            // hashed key: compare the segment bytes before extension
-                            // verification, which skips the segment
-                            const LdsChars xs{xl8 + (p - 1)};
-                            bool same = true;
-                            if constexpr (LANE) {
-                                const LdsLaneChars yc{ys8 + (sgm.p - 1)};
-                                for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
-                            } else if constexpr (REGY > 0) {
-                                const RegChars yc{yr[c], sgm.p - 1};
-                                for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
-                            } else {
-                                for (int q = 0; q < sgm.len; ++q)
-                                    same &= (xs[q] == (int)y[c][sgm.p - 1 + q]);
-                            }
-                            my_miss += same ? 0 : 1;
-                            ok[c] = same;
+                    y[c] = load_y(gy[c], ent[c], yr[c]);
+                    if (!from_queue && sgm.len > V.exact_len) {
+                        // hashed key: compare the segment bytes before extension
+                        // verification, which skips the segment
+                        const LdsChars xs{xl8 + (p - 1)};
+                        bool same = true;
+                        if constexpr (LANE) {
+                            const LdsLaneChars yc{ys8 + (sgm.p - 1)};
+                            for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
+                        } else if constexpr (REGY > 0) {
+                            const RegChars yc{yr[c], sgm.p - 1};
+                            for (int q = 0; q < sgm.len; ++q) same &= (xs[q] == yc[q]);
+                        } else {
+                            for (int q = 0; q < sgm.len; ++q)
+                                same &= (xs[q] == (int)y[c][sgm.p - 1 + q]);
                         }
+                        my_miss += (ok[c] && !same) ? 1 : 0;
+                        ok[c] = ok[c] && same;
                     }
                     anyok = anyok || ok[c];
                 }
