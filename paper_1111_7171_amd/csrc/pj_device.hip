@@ -1322,29 +1322,26 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                     ++sg_i;
                 }
                 if (from_queue) {
-                    // move the rest of the queue to its front (all reads before the writes)
+                    // move the rest of the queue (entries SEG .. qn-1) to its front, all reads
+                    // before the writes; every lane moves a word, those past the rest are free
                     const uint32_t rest = qn - k;
                     uint32_t mv[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
-                        mv[c] = slot < rest ? sq[SEG + slot] : 0u;
-                    }
+                    for (int c = 0; c < NC; ++c) mv[c] = sq[SEG + (uint32_t)(c * 64 + lane)];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const uint32_t slot = (uint32_t)c * 64u + (uint32_t)lane;
-                        if (slot < rest) sq[slot] = mv[c];
-                    }
+                    for (int c = 0; c < NC; ++c) sq[(uint32_t)(c * 64 + lane)] = mv[c];
                     qn = rest;
                 } else if (!right && !right_trivial) {
+                    // survivors appended in lane order; a left step starts with qn < SEG, so
+                    // the last word, 2 * SEG - 1, is never an entry and takes the other lanes'
+                    // writes
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         const uint64_t surv = __builtin_amdgcn_ballot_w64(ok[c]);
-                        if (ok[c])
-                            sq[qn + __builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(surv >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u))] =
-                                yinl ? ent[c] : gy[c];
+                        const uint32_t at = qn + __builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(surv >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)surv, 0u));
+                        sq[ok[c] ? at : 2u * SEG - 1u] = yinl ? ent[c] : gy[c];
                         qn += (uint32_t)__builtin_popcountll(surv);
                     }
                 }
