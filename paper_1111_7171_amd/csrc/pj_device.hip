@@ -822,9 +822,8 @@ __device__ inline uint64_t wave_or64(uint64_t v)
 
 // VerifyStringPair with the band width fixed at compile time when the threshold is the same on
 // every active lane of the wave (t <= 8), else the generic width class GMAXW.
-template <int GMAXW>
-__device__ inline int vsp_dispatch(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
-                                   int* cells)
+template <int GMAXW, typename P>
+__device__ inline int vsp_dispatch(P r, int lr, P s, int ls, int t, int* cells)
 {
     const int t0 = __builtin_amdgcn_readfirstlane(t);
     if (t0 <= 8 && __ballot(t != t0) == 0) {
@@ -843,14 +842,27 @@ __device__ inline int vsp_dispatch(const uint8_t* r, int lr, const uint8_t* s, i
     return vsp_fast<GMAXW>(r, lr, s, ls, t, cells);
 }
 
-template <int GMAXW>
+// STG: every lane copies its candidate's two strings into LDS slots of its own first (probe
+// string x up to kStgX - 4 bytes, indexed string y up to kStgY - 4), so the band DP reads LDS
+// instead of global memory byte by byte.  Launched for indexed strings of at most 48 bytes and
+// tau <= 8: a hit pairs x with lists of lengths within tau of |x|, so |x| <= 56.
+constexpr int kStgX = 60, kStgY = 52;     // slot strides: odd word counts, conflict-free
+
+template <int GMAXW, int STG>
 __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div div,
                                                            const uint32_t* __restrict__ first,
                                                            uint64_t nchunks)
 {
     __shared__ uint64_t s_acc[kWaves][kAppendCap];
+    __shared__ uint32_t s_str[kWaves][STG ? 64 * (kStgX + kStgY) / 4 : 1];
     WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
+    using LdsBytes = const __attribute__((address_space(3))) uint8_t*;
+    __attribute__((address_space(3))) uint32_t* xsw =
+        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + lane * (kStgX / 4);
+    __attribute__((address_space(3))) uint32_t* ysw =
+        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + 64 * (kStgX / 4) +
+        lane * (kStgY / 4);
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
     uint64_t my_cells = 0, my_miss = 0;
@@ -900,23 +912,55 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
                 const uint8_t* y = V.y_arena + V.y_gbase[l] +
                                    (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
                 const Seg sg = partition_seg(l, i, tau, dv);
-                bool same = true;
-                if (sg.len > V.exact_len)
-                    for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
-                if (!same) {
-                    my_miss += 1;
-                } else {
+                auto verify = [&](auto xp, auto yp) {
+                    bool same = true;
+                    if (sg.len > V.exact_len)
+                        for (int k = 0; k < sg.len; ++k) same &= (xp[p - 1 + k] == yp[sg.p - 1 + k]);
+                    if (!same) {
+                        my_miss += 1;
+                        return;
+                    }
                     int cl = 0;
                     const int tl = i - 1, tr = tau + 1 - i;
-                    const int dl = vsp_dispatch<GMAXW>(y, sg.p - 1, x, p - 1, tl, &cl);
+                    const int dl = vsp_dispatch<GMAXW>(yp, sg.p - 1, xp, p - 1, tl, &cl);
                     my_cells += cl;
                     if (dl <= tl) {
                         int cr = 0;
                         const int ry = sg.p - 1 + sg.len, rx = p - 1 + sg.len;
-                        const int dr = vsp_dispatch<GMAXW>(y + ry, l - ry, x + rx, n - rx, tr, &cr);
+                        const int dr =
+                            vsp_dispatch<GMAXW>(yp + ry, l - ry, xp + rx, n - rx, tr, &cr);
                         my_cells += cr;
                         pass = dr <= tr;
                     }
+                };
+                if constexpr (STG > 0) {
+                    // both strings' words (16-byte aligned slots in the arenas), loads first
+                    const uint4* xq = reinterpret_cast<const uint4*>(x);
+                    const uint4* yq = reinterpret_cast<const uint4*>(y);
+                    uint4 xv[(kStgX + 15) / 16], yv[(kStgY + 15) / 16];
+#pragma unroll
+                    for (int q = 0; q < (kStgX + 15) / 16; ++q)
+                        if (q * 16 < n) xv[q] = xq[q];
+#pragma unroll
+                    for (int q = 0; q < (kStgY + 15) / 16; ++q)
+                        if (q * 16 < l) yv[q] = yq[q];
+#pragma unroll
+                    for (int d = 0; d < kStgX / 4; ++d) {
+                        const uint4 v = xv[d >> 2];
+                        const uint32_t w = (d & 3) == 0 ? v.x : (d & 3) == 1 ? v.y
+                                         : (d & 3) == 2 ? v.z : v.w;
+                        if (d * 4 < n) xsw[d] = w;
+                    }
+#pragma unroll
+                    for (int d = 0; d < kStgY / 4; ++d) {
+                        const uint4 v = yv[d >> 2];
+                        const uint32_t w = (d & 3) == 0 ? v.x : (d & 3) == 1 ? v.y
+                                         : (d & 3) == 2 ? v.z : v.w;
+                        if (d * 4 < l) ysw[d] = w;
+                    }
+                    verify((LdsBytes)(xsw), (LdsBytes)(ysw));
+                } else {
+                    verify(x, y);
                 }
             }
             acc.push(pass, ((uint64_t)gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
@@ -1609,8 +1653,12 @@ template <int W>
 static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint64_t nchunks,
                              int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_verify_batched<W>), dim3(grid), dim3(kBlock), 0, s, V,
-                       make_div(V.tau + 1), first, nchunks);
+    if (W == 9 && V.tau <= 8 && V.y_maxlen <= kStgY - 4)
+        hipLaunchKernelGGL((k_verify_batched<W, (W == 9 ? 1 : 0)>), dim3(grid), dim3(kBlock), 0,
+                           s, V, make_div(V.tau + 1), first, nchunks);
+    else
+        hipLaunchKernelGGL((k_verify_batched<W, 0>), dim3(grid), dim3(kBlock), 0, s, V,
+                           make_div(V.tau + 1), first, nchunks);
 }
 
 uint64_t batched_chunks(uint64_t ncand, int rounds)

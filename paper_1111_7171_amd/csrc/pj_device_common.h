@@ -262,13 +262,13 @@ __device__ inline int band_cells(int s, int nc, int a, int b);
 // BIG borders, the unmasked band indices past a + b and the characters outside 1..nc, which
 // read as 256 here).  The band's column characters sit in a register window that shifts by one
 // per row; the character entering it and the next row character are loaded a row ahead.  The
-// cells of the rows evaluated follow in closed form.
-template <int MAXW>
-__device__ inline int vsp_fast(const uint8_t* r, int lr, const uint8_t* s, int ls, int t,
-                               int* cells)
+// cells of the rows evaluated follow in closed form.  P is a byte pointer into global memory
+// or LDS.
+template <int MAXW, typename P>
+__device__ inline int vsp_fast(P r, int lr, P s, int ls, int t, int* cells)
 {
-    const uint8_t* A;
-    const uint8_t* B;
+    P A;
+    P B;
     int nr, nc;
     if (lr <= ls) { A = r; nr = lr; B = s; nc = ls; }
     else          { A = s; nr = ls; B = r; nc = lr; }
