@@ -68,6 +68,7 @@ __device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) -
 // is this wave's region of CAP items; `fill` is wave-uniform.
 template <typename T, int CAP>
 struct WaveAppender {
+    static_assert(CAP >= 64, "a push adds up to 64 items after at most one flush");
     T* buf;
     int fill;
 
