@@ -213,8 +213,8 @@ int pj_server_stop(pj_server* srv);
  * an inverted list is verified a wave at a time instead of candidate by candidate, the probe
  * grid (blocks per compute unit), and how many members of one list each lane verifies at once. */
 typedef struct {
-    int32_t verify_waves_per_cu;   /* 8, 16, 32, 64, 128, 256 or 512 (default 32) */
-    int32_t seg_chunk;             /* 1, 2, 4, ..., 512, powers of two (default 4) */
+    int32_t verify_waves_per_cu;   /* 8, 16, 32, ..., 1024, powers of two (default 32) */
+    int32_t seg_chunk;             /* 1, 2, 4, ..., 2048, powers of two (default 4) */
     int32_t big_list;              /* 16, 32, 64 or 128 (default 32) */
     int32_t probe_blocks_per_cu;   /* 4, 8 or 16 (default 8) */
     int32_t lane_cands;            /* list-segment candidates per lane: 1 or 2 (default 2) */

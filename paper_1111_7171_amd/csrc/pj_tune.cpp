@@ -47,8 +47,8 @@ std::mutex g_mu;
 std::map<Key, Entry> g_local;                  // tuned in this process without a cache file
 std::map<std::string, FileState> g_files;      // cache file path -> parsed contents
 
-const int kWavesOpts[] = {8, 16, 32, 64, 128, 256, 512};
-const int kChunkOpts[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512};
+const int kWavesOpts[] = {8, 16, 32, 64, 128, 256, 512, 1024};
+const int kChunkOpts[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048};
 const int kBigOpts[] = {16, 32, 64, 128};
 const int kProbeOpts[] = {4, 8, 16};
 const int kLaneOpts[] = {1, 2};

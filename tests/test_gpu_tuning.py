@@ -43,8 +43,8 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     cache = str(tmp_path / "tune.txt")
     _say("pj_tune cfg2 n=20000 tau=3")
     r = P.pj_tune(col, 3, tune_cache=cache)
-    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128, 256, 512)
-    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
+    assert r["verify_waves_per_cu"] in (8, 16, 32, 64, 128, 256, 512, 1024)
+    assert r["seg_chunk"] in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048)
     assert r["big_list"] in (16, 32, 64, 128)
     assert r["probe_blocks_per_cu"] in (4, 8, 16)
     assert r["lane_cands"] in (1, 2)
