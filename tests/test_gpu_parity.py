@@ -277,3 +277,57 @@ def test_batched_chunk_sizes(rounds, monkeypatch):
         _same(got, pj.pairs, f"rounds={rounds} tau={tau}")
         assert st["candidates"] == pj.candidates
         assert st["cells"] == pj.cells
+
+
+def _clusters(seed, nbase, per, lmin, lmax, kmax):
+    """nbase random base strings over a-z (lengths U{lmin..lmax}), each with per - 1 copies
+    carrying U{0..kmax} random edits kept within [lmin, lmax]: the members of a cluster share
+    most segments, so inverted lists are long."""
+    rng = np.random.default_rng(seed)
+    alpha = b"abcdefghijklmnopqrstuvwxyz"
+    out = []
+    for _ in range(nbase):
+        size = int(rng.integers(lmin, lmax + 1))
+        base = bytes(alpha[int(c)] for c in rng.integers(0, 26, size=size))
+        out.append(base)
+        for _ in range(per - 1):
+            b = bytearray(base)
+            for _ in range(int(rng.integers(0, kmax + 1))):
+                op, pos = int(rng.integers(0, 3)), int(rng.integers(0, len(b)))
+                if op == 0:
+                    b[pos] = alpha[int(rng.integers(0, 26))]
+                elif op == 1 and len(b) < lmax:
+                    b.insert(pos, alpha[int(rng.integers(0, 26))])
+                elif len(b) > lmin:
+                    del b[pos]
+            out.append(bytes(b))
+    perm = rng.permutation(len(out))
+    return W.from_list([out[k] for k in perm])
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lmin,lmax", [(20, 40), (44, 64)])
+def test_list_kernel_wide_bands(lanes, lmin, lmax, tmp_path, monkeypatch):
+    # the list-segment kernel on every band class up to 9 wide (tau 1..8, parts with t up to
+    # 8, the final diagonal a constant for t <= 4 and a runtime value above), indexed strings
+    # of up to 48 and of up to 64 bytes, one or two candidates per lane
+    monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
+    col = _clusters(5 + lmin, 40, 60, lmin, lmax, 8)
+    cache = str(tmp_path / "tune.txt")
+    P.pj_tune(W.cfg2(2_000, seed=23), 0, tune_cache=cache)    # learns this GPU's architecture
+    arch = [ln.split()[0] for ln in open(cache) if not ln.startswith("#")][0]
+    mean = (col.offsets[-1] - col.offsets[0]) / col.n
+    lb = int(mean + 0.5).bit_length()
+    with open(cache, "w") as f:
+        f.write("# passjoin tune cache v2\n")
+        for tau in range(0, 9):
+            f.write(f"{arch} {tau} {lb} 32 4 16 4 {lanes} 1.0\n")
+    for tau in (1, 2, 4, 5, 6, 7, 8):
+        _say("wide bands lanes", lanes, "lengths", lmin, lmax, "tau", tau)
+        pj = O.self_join_pj(col, tau)
+        got = P.pj_self_join(col, tau, mode=P.MODE_BATCHED, tune_cache=cache)
+        st = P.pj_last_stats()
+        _same(got, pj.pairs, f"lanes={lanes} len {lmin}-{lmax} tau={tau}")
+        assert st["candidates"] == pj.candidates
+        assert st["cells"] == pj.cells
+        assert st["ms_list_kernel"] > 0          # the list-segment kernel ran
