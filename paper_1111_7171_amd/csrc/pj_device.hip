@@ -849,8 +849,11 @@ __device__ inline int vsp_dispatch(P r, int lr, P s, int ls, int t, int* cells)
 // tau <= 8: a hit pairs x with lists of lengths within tau of |x|, so |x| <= 56.
 constexpr int kStgX = 60, kStgY = 52;     // slot strides: odd word counts, conflict-free
 
+// With STG the LDS slots allow 4 blocks per CU; the register budget is held to match
+// (128 VGPRs, no spills), so 4 waves per SIMD hide the candidates' dependent loads.
 template <int GMAXW, int STG>
-__global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div div,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(STG ? 4 : 1))) void k_verify_batched(VerifyParams V, Div div,
                                                            const uint32_t* __restrict__ first,
                                                            uint64_t nchunks)
 {
@@ -935,29 +938,27 @@ __global__ __launch_bounds__(kBlock) void k_verify_batched(VerifyParams V, Div d
                     }
                 };
                 if constexpr (STG > 0) {
-                    // both strings' words (16-byte aligned slots in the arenas), loads first
                     const uint4* xq = reinterpret_cast<const uint4*>(x);
                     const uint4* yq = reinterpret_cast<const uint4*>(y);
-                    uint4 xv[(kStgX + 15) / 16], yv[(kStgY + 15) / 16];
 #pragma unroll
-                    for (int q = 0; q < (kStgX + 15) / 16; ++q)
-                        if (q * 16 < n) xv[q] = xq[q];
-#pragma unroll
-                    for (int q = 0; q < (kStgY + 15) / 16; ++q)
-                        if (q * 16 < l) yv[q] = yq[q];
-#pragma unroll
-                    for (int d = 0; d < kStgX / 4; ++d) {
-                        const uint4 v = xv[d >> 2];
-                        const uint32_t w = (d & 3) == 0 ? v.x : (d & 3) == 1 ? v.y
-                                         : (d & 3) == 2 ? v.z : v.w;
-                        if (d * 4 < n) xsw[d] = w;
+                    for (int q = 0; q < (kStgX + 15) / 16; ++q) {
+                        if (q * 16 < n) {
+                            const uint4 v = xq[q];
+                            if (4 * q < kStgX / 4) xsw[4 * q] = v.x;
+                            if (4 * q + 1 < kStgX / 4) xsw[4 * q + 1] = v.y;
+                            if (4 * q + 2 < kStgX / 4) xsw[4 * q + 2] = v.z;
+                            if (4 * q + 3 < kStgX / 4) xsw[4 * q + 3] = v.w;
+                        }
                     }
 #pragma unroll
-                    for (int d = 0; d < kStgY / 4; ++d) {
-                        const uint4 v = yv[d >> 2];
-                        const uint32_t w = (d & 3) == 0 ? v.x : (d & 3) == 1 ? v.y
-                                         : (d & 3) == 2 ? v.z : v.w;
-                        if (d * 4 < l) ysw[d] = w;
+                    for (int q = 0; q < (kStgY + 15) / 16; ++q) {
+                        if (q * 16 < l) {
+                            const uint4 v = yq[q];
+                            if (4 * q < kStgY / 4) ysw[4 * q] = v.x;
+                            if (4 * q + 1 < kStgY / 4) ysw[4 * q + 1] = v.y;
+                            if (4 * q + 2 < kStgY / 4) ysw[4 * q + 2] = v.z;
+                            if (4 * q + 3 < kStgY / 4) ysw[4 * q + 3] = v.w;
+                        }
                     }
                     verify((LdsBytes)(xsw), (LdsBytes)(ysw));
                 } else {
