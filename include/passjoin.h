@@ -226,7 +226,7 @@ typedef struct {
 
 /* Searches the launch parameters for the self-join of S (host memory) at tau by coordinate
  * descent (repeated until a pass changes nothing, at most 3 passes), timing the probe and
- * verification kernels (best of two runs per setting), and
+ * verification phases on the device (best of two runs per setting), and
  * records the best setting under (this GPU's architecture, tau, length bucket of S's mean
  * length).  The record is kept for the rest of the process; when opt->tune_cache names a file
  * it is also merged into that file (plain text, one setting per line), which later calls with

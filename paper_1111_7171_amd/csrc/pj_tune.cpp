@@ -4,7 +4,7 @@
 //
 // Parameters are kept per (GPU architecture, tau, length bucket), the bucket being the bit
 // length of the probe set's rounded mean string length.  pj_tune searches them by coordinate
-// descent on a caller-supplied workload, timing the probe and verification kernels with hip
+// descent on a caller-supplied workload, timing the probe and verification phases with hip
 // events; the result goes to an in-process table and, when pj_options.tune_cache names a file,
 // to that file, which later calls read back.  The file is plain text:
 //
@@ -173,7 +173,7 @@ TuneParams tune_lookup(const char* cache, int tau, double mean_len)
     return it != g_local.end() ? it->second.p : TuneParams{};
 }
 
-// Device time (ms) of the probe and verification kernels of one self-join under p; the pairs
+// Device time (ms) of the probe and verification phases of one self-join under p; the pairs
 // are checked against the first run's count, since no parameter may change the result.
 static double time_one(const pj_strings* S, int32_t tau, const pj_options* base,
                        const TuneParams& p, int64_t* pairs);
@@ -299,8 +299,10 @@ static double time_one(const pj_strings* S, int32_t tau, const pj_options* base,
     if (rc != PJ_OK) throw Error(rc, "%s", t_last_error.c_str());
     *pairs = out.count;
     pj_pairs_free(&out);
+    // the probe and verification phases (kernels plus the bucketing, scans and chunk set-up
+    // between them, which the list-size threshold and the grids also change)
     const pj_stats& st = t_last_ok_stats;
-    return st.ms_probe_kernel + st.ms_verify_kernel;
+    return st.ms_probe + st.ms_verify;
 }
 
 }  // namespace pj
