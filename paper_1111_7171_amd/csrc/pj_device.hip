@@ -1123,12 +1123,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
     // NC candidates per lane: a list segment has 64 * NC members
     constexpr int NC = (REGY > 0 && GMAXW <= 9) ? NCT : 1;
     constexpr uint32_t SEG = 64u * NC;
-    // one candidate per lane with the indexed strings in registers: each lane also copies its
-    // string into an LDS slot, from which the band DP reads it (vsp_lane)
+    // one candidate per lane and indexed strings of at most REGY bytes: each lane copies its
+    // string into an LDS slot of its own, from which the band DP reads it (vsp_lane)
     constexpr bool LANE = REGY > 0 && NC == 1 && GMAXW <= 9;
     // slot stride REGY + 4 bytes, an odd number of words, so a wave's reads at one offset hit
     // distinct banks; 16 bytes before the first slot and after the last absorb the reads of
-    // columns outside the string (at most 4 before a string and 2 * 9 - 2 - 4 after it)
+    // columns outside the string (at most 4 bytes before a string, at most 12 after it: a DP
+    // block reads up to 2 * MAXW - 2 - kfin past the part, with kfin >= t / 2)
     constexpr int SL = REGY + 4, YPAD = 16, YTAIL = 16;
     constexpr int kCap = 96;                               // pairs buffered per wave
     __shared__ uint64_t s_acc[kWaves][kCap];
