@@ -19,6 +19,7 @@ Functions (paper sections in brackets):
   self_join_pj       Pass-Join self-join with candidate/cell counts, any   [Alg. 1-3, Sec. 4]
                      of the four substring-selection methods
   join_pj            Pass-Join join of two sets                            [Sec. 3.2]
+  *_parallel         the two runs split over processes by probe string (disjoint shares)
 """
 from __future__ import annotations
 
@@ -90,9 +91,9 @@ def _load():
         lib.orc_join_bf.restype = rp
         lib.orc_partners_bf.argtypes = [u8p, i32p, i64, i32p, i64, i32, i32]
         lib.orc_partners_bf.restype = rp
-        lib.orc_self_join_pj.argtypes = [u8p, i32p, i64, i32, i32, i32, i32, i32]
+        lib.orc_self_join_pj.argtypes = [u8p, i32p, i64, i32, i32, i32, i32, i32, i32]
         lib.orc_self_join_pj.restype = rp
-        lib.orc_join_pj.argtypes = [u8p, i32p, i64, u8p, i32p, i64, i32, i32, i32]
+        lib.orc_join_pj.argtypes = [u8p, i32p, i64, u8p, i32p, i64, i32, i32, i32, i32, i32]
         lib.orc_join_pj.restype = rp
         lib.orc_result_free.argtypes = [rp]
         lib.orc_result_free.restype = None
@@ -222,20 +223,91 @@ def partners_bf(col, xs, tau: int, nthreads: int = 0) -> np.ndarray:
 
 
 def self_join_pj(col, tau: int, tiebreak: int = 0, probe_stride: int = 1,
-                 keep_cands: bool = False, method: int = SEL_MULTIMATCH) -> JoinResult:
+                 keep_cands: bool = False, method: int = SEL_MULTIMATCH,
+                 probe_offset: int = 0) -> JoinResult:
     """Pass-Join self-join; tiebreak 0 visits equal lengths by id, 1 by bytes (the paper's
-    alphabetical order).  probe_stride > 1 lets only every k-th visited string probe.  method
-    is the substring selection (SEL_*; multi-match, Sec. 4.2, by default)."""
+    alphabetical order).  With probe_stride k > 1 only the strings at visiting ranks
+    r = probe_offset (mod k) probe; every string is still indexed.  method is the substring
+    selection (SEL_*; multi-match, Sec. 4.2, by default)."""
     ch, of = _arena(col)
     rp = _load().orc_self_join_pj(ch.ctypes.data, of.ctypes.data, col.n, tau, tiebreak,
-                                  probe_stride, int(keep_cands), int(method))
+                                  probe_stride, probe_offset, int(keep_cands), int(method))
     return _take(rp, keep_cands)
 
 
 def join_pj(R, S, tau: int, keep_cands: bool = False,
-            method: int = SEL_MULTIMATCH) -> JoinResult:
+            method: int = SEL_MULTIMATCH, probe_stride: int = 1,
+            probe_offset: int = 0) -> JoinResult:
+    """Pass-Join join of two sets; with probe_stride k > 1 only the r = probe_offset (mod k)
+    probe."""
     rc, ro = _arena(R)
     sc, so = _arena(S)
     rp = _load().orc_join_pj(rc.ctypes.data, ro.ctypes.data, R.n, sc.ctypes.data,
-                             so.ctypes.data, S.n, tau, int(keep_cands), int(method))
+                             so.ctypes.data, S.n, tau, int(keep_cands), int(method),
+                             probe_stride, probe_offset)
     return _take(rp, keep_cands)
+
+
+# ---- the same runs split over processes --------------------------------------------------
+#
+# The probe strings are dealt round-robin to k worker processes (probe offset w of stride k).
+# Each worker runs the unchanged sequential algorithm: it indexes every string in visiting order
+# and probes only with its own share.  A pair is found only by its later-visited string (self-
+# join) or by its r (join), so the shares' pair lists are disjoint and their counters add up to
+# the single-process run's.
+
+_SHARED: dict = {}
+
+
+def _self_share(args):
+    tau, k, w, method = args
+    r = self_join_pj(_SHARED["col"], tau, probe_stride=k, probe_offset=w, method=method)
+    return r.pairs, r.candidates, r.cells, r.selected, r.side_pairs
+
+
+def _join_share(args):
+    tau, k, w, method = args
+    r = join_pj(_SHARED["R"], _SHARED["S"], tau, method=method, probe_stride=k, probe_offset=w)
+    return r.pairs, r.candidates, r.cells, r.selected, r.side_pairs
+
+
+def _run_shares(fn, shared: dict, tau: int, procs: int, method: int, shares: int | None = None,
+                only: list | None = None) -> JoinResult:
+    import multiprocessing as mp
+    k = max(1, int(shares or procs))
+    todo = list(range(k)) if only is None else list(only)
+    _SHARED.clear()
+    _SHARED.update(shared)
+    _load()
+    try:
+        if procs <= 1 or len(todo) <= 1:
+            parts = [fn((tau, k, w, method)) for w in todo]
+        else:
+            ctx = mp.get_context("fork")        # workers inherit the arena without copying it
+            with ctx.Pool(min(procs, len(todo))) as pool:
+                parts = pool.map(fn, [(tau, k, w, method) for w in todo], chunksize=1)
+    finally:
+        _SHARED.clear()
+    pairs = np.concatenate([p[0] for p in parts]) if parts else np.empty((0, 2), np.int32)
+    if len(pairs):
+        key = pairs[:, 0].astype(np.int64) << 32 | pairs[:, 1].astype(np.int64)
+        order = np.argsort(key, kind="stable")
+        pairs = pairs[order]
+    return JoinResult(np.ascontiguousarray(pairs, dtype=np.int32),
+                      sum(int(p[1]) for p in parts), sum(int(p[2]) for p in parts),
+                      sum(int(p[3]) for p in parts), sum(int(p[4]) for p in parts))
+
+
+def self_join_pj_parallel(col, tau: int, procs: int = 0, method: int = SEL_MULTIMATCH,
+                          shares: int | None = None, only: list | None = None) -> JoinResult:
+    """self_join_pj split over `procs` processes (default: every CPU).  `shares` (default procs)
+    is the number of probe offsets; `only` restricts the run to some of them (a sample)."""
+    procs = procs or os.cpu_count() or 1
+    return _run_shares(_self_share, {"col": col}, tau, procs, method, shares, only)
+
+
+def join_pj_parallel(R, S, tau: int, procs: int = 0, method: int = SEL_MULTIMATCH,
+                     shares: int | None = None, only: list | None = None) -> JoinResult:
+    """join_pj split over `procs` processes (default: every CPU)."""
+    procs = procs or os.cpu_count() or 1
+    return _run_shares(_join_share, {"R": R, "S": S}, tau, procs, method, shares, only)

@@ -595,15 +595,19 @@ static int cmp_visit(const void* u, const void* v, void* arg)
  * reachable through the index (footnote to Sec. 3.1); they are found by a direct distance
  * computation against the earlier-visited strings within the length filter.
  *
- * probe_stride > 1 samples the probe step: only strings at visiting rank 0, k, 2k, ... probe
- * (and take part in the direct path); every string is still indexed.
+ * probe_stride > 1 restricts the probe step: only strings at visiting ranks r with
+ * r % probe_stride == probe_offset probe (and take part in the direct path); every string is
+ * still indexed in visiting order.  Each pair is reported by its later-visited string, so the
+ * runs for offsets 0 .. probe_stride-1 are disjoint, their pairs together are the whole result
+ * and their counters add up to the whole run's (this is how the work is split over processes).
  * keep_cands = 1 records every candidate (y, x, i, p) with its verdict and cells. */
 orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t n, int32_t tau,
-                             int32_t tiebreak, int32_t probe_stride, int32_t keep_cands,
-                             int32_t method)
+                             int32_t tiebreak, int32_t probe_stride, int32_t probe_offset,
+                             int32_t keep_cands, int32_t method)
 {
     orc_result* R = res_new();
     if (probe_stride < 1) probe_stride = 1;
+    if (probe_offset < 0 || probe_offset >= probe_stride) probe_offset = 0;
     int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t k = 0; k < n; ++k) order[k] = (int32_t)k;
     sort_ctx ctx = {chars, offs, tiebreak};
@@ -619,7 +623,7 @@ orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t 
         int32_t x = order[rank];
         const uint8_t* xs = chars + offs[x];
         int32_t xl = offs[x + 1] - offs[x];
-        if (rank % probe_stride == 0) {
+        if (rank % probe_stride == probe_offset) {
             if (xl >= tau + 1)
                 probe_string(&X, chars, offs, x, xs, xl, xl - tau, xl, tau, 1, keep_cands, method,
                              R);
@@ -645,12 +649,15 @@ orc_result* orc_self_join_pj(const uint8_t* chars, const int32_t* offs, int64_t 
 /* Join of two distinct sets (Sec. 3.2): the strings of S are indexed; each r of R probes the
  * indices of lengths |r|-tau .. |r|+tau, with the windows of Sec. 4.2 taken at the signed
  * Delta = |r| - l.  Strings of S shorter than tau+1 are compared with every r directly.
- * Pairs are (r, s). */
+ * Pairs are (r, s).  Only the r with r % probe_stride == probe_offset probe (probe_stride = 1:
+ * all of them); the runs for the offsets 0 .. probe_stride-1 split the result disjointly. */
 orc_result* orc_join_pj(const uint8_t* rc, const int32_t* ro, int64_t rn, const uint8_t* sc,
                         const int32_t* so, int64_t sn, int32_t tau, int32_t keep_cands,
-                        int32_t method)
+                        int32_t method, int32_t probe_stride, int32_t probe_offset)
 {
     orc_result* R = res_new();
+    if (probe_stride < 1) probe_stride = 1;
+    if (probe_offset < 0 || probe_offset >= probe_stride) probe_offset = 0;
     orc_index X;
     index_init(&X, sn * (tau + 1));
     /* strings of S shorter than tau+1 */
@@ -661,7 +668,7 @@ orc_result* orc_join_pj(const uint8_t* rc, const int32_t* ro, int64_t rn, const 
         if (yl >= tau + 1) index_string(&X, sc + so[y], yl, tau, (int32_t)y);
         else shorts[nshort++] = (int32_t)y;
     }
-    for (int64_t x = 0; x < rn; ++x) {
+    for (int64_t x = probe_offset; x < rn; x += probe_stride) {
         const uint8_t* xs = rc + ro[x];
         int32_t xl = ro[x + 1] - ro[x];
         probe_string(&X, sc, so, (int32_t)x, xs, xl, xl - tau, xl + tau, tau, 0, keep_cands,

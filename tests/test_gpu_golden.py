@@ -1,0 +1,131 @@
+"""Exact parity at the full workload sizes, in the configuration the benchmark times.
+
+Every (workload, tau) of the five workloads runs at its stated size on the GPU: the self-joins
+with inputs and outputs in HBM and launch parameters tuned on the workload first (as bench.py
+does), the serving stream through pj_query and through a server with every batch in flight.
+The sorted pair list must hash to the oracle's (tests/golden/fullsize.json, written by
+tests/golden/make_fullsize.py from the unchanged oracle split over processes), and the pair,
+selected-substring, candidate, cell and side-path counts must equal the oracle's.  The result
+of Definition 1 is a set with one canonical order (Theorem 6), so the hash pins the whole list.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1111_7171_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "fullsize.json")) as _f:
+    GOLD = json.load(_f)
+
+SELF_CASES = [(c, t) for c in (1, 2, 3, 4) for t in W.TAUS[c]]
+_COLS = {}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _sha(pairs: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(pairs, dtype="<i4").tobytes()).hexdigest()
+
+
+def _col(cfg: int):
+    if cfg not in _COLS:
+        _COLS.clear()                       # one full-size workload in host memory at a time
+        _COLS[cfg] = W.CONFIGS[cfg]()
+    return _COLS[cfg]
+
+
+@pytest.fixture(scope="module")
+def tune_cache(tmp_path_factory):
+    return str(tmp_path_factory.mktemp("tune") / "tune.txt")
+
+
+def _check_set(pairs: np.ndarray, n: int, self_join: bool):
+    assert pairs.ndim == 2 and pairs.shape[1] == 2
+    a, b = pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64)
+    if len(pairs):
+        assert a.min() >= 0 and b.min() >= 0
+    if self_join:
+        assert np.all(a < b) and (len(pairs) == 0 or b.max() < n)
+    key = a << 32 | b
+    assert np.all(np.diff(key) > 0), "not sorted / not unique"
+
+
+def _check_counts(st: dict, e: dict, what: str):
+    for k in ("selected", "candidates", "cells", "side_pairs"):
+        assert st[k] == e[k], f"{what}: {k} {st[k]} != oracle {e[k]}"
+
+
+@pytest.mark.parametrize("cfg,tau", SELF_CASES)
+def test_self_join_full_size_matches_oracle(cfg, tau, tune_cache):
+    import torch
+    g = GOLD[f"cfg{cfg}"]
+    e = g["taus"][str(tau)]
+    col = _col(cfg)
+    assert col.n == g["n"] and col.sha256() == g["arena_sha256"], "workload generator changed"
+    _say(f"cfg{cfg} tau={tau}: tuning on the workload")
+    P.pj_tune(col, tau, tune_cache=tune_cache)
+    _say(f"cfg{cfg} tau={tau}: self-join of {col.n} strings (device inputs and outputs, tuned)")
+    chars = torch.from_numpy(col.chars.copy()).cuda()
+    offs = torch.from_numpy(col.offsets.copy()).cuda()
+    dp = P.pj_self_join((chars, offs), tau, outputs_on_device=True, tune_cache=tune_cache)
+    try:
+        st = P.pj_last_stats()
+        pairs = dp.to_numpy()
+    finally:
+        dp.free()
+    _say(f"  pairs {len(pairs)} (oracle {e['pairs']}), candidates {st['candidates']}")
+    _check_set(pairs, col.n, True)
+    assert len(pairs) == e["pairs"] and st["pairs"] == e["pairs"]
+    assert _sha(pairs) == e["pairs_sha256"]
+    _check_counts(st, e, f"cfg{cfg} tau={tau}")
+    # a sample of the reported pairs, re-checked by the textbook DP (independent of Pass-Join)
+    rng = np.random.default_rng(1000 * cfg + tau)
+    for k in rng.choice(len(pairs), size=min(200, len(pairs)), replace=False):
+        assert O.ed_full(col.get(int(pairs[k, 0])), col.get(int(pairs[k, 1]))) <= tau
+
+
+def test_serving_stream_full_size_matches_oracle():
+    g = GOLD["cfg5"]
+    S = W.cfg5_index()
+    assert S.n == g["index_n"] and S.sha256() == g["index_sha256"], "index generator changed"
+    batches = W.cfg5_queries(S, g["batches"])
+    Q = W.concat([q for q, _ in batches])
+    taus = np.concatenate([t for _, t in batches]).astype(np.int32)
+    assert Q.sha256() == g["queries_sha256"]
+    assert hashlib.sha256(taus.astype("<i4").tobytes()).hexdigest() == g["taus_sha256"]
+    _say(f"cfg5: index of {S.n} strings, tau 1..8; {Q.n} queries in {len(batches)} batches")
+    idx = P.pj_build_index(S, 1, 8)
+    try:
+        got = P.pj_query(idx, Q, taus)
+        st = P.pj_last_stats()
+        _say(f"  pj_query: {len(got)} pairs (oracle {g['pairs']})")
+        _check_set(got, S.n, False)
+        assert len(got) == g["pairs"] and _sha(got) == g["pairs_sha256"]
+        _check_counts(st, g, "cfg5 pj_query")
+        # the same stream through the server, every batch submitted before any is waited for
+        for eager in (False, True):
+            with P.Server(idx, slots=4, max_batch_queries=512, mem_budget=8 << 30,
+                          eager=eager) as srv:
+                rids = [srv.submit(q, t) for q, t in batches]
+                parts, base = [], 0
+                for (q, _), rid in zip(batches, rids):
+                    pr, _ = srv.wait(rid)
+                    pr = pr.copy()
+                    pr[:, 0] += base
+                    base += q.n
+                    parts.append(pr)
+            allp = np.concatenate(parts)
+            _say(f"  server (eager={eager}): {len(allp)} pairs")
+            assert len(allp) == g["pairs"] and _sha(allp) == g["pairs_sha256"], eager
+    finally:
+        idx.free()

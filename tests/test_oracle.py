@@ -276,6 +276,42 @@ def test_early_termination_paper_rows(golden):
     assert cells == e1["cells_per_row"] * e1["stop_row"]
 
 
+def test_length_aware_cells_paper_example(golden):
+    """The cells of the Sec. 5.1 example (a 3-wide band, Delta = 2), derived by hand from the
+    printed band bounds: the band edges and the stopping row are counted as the paper states."""
+    e0 = golden["early_termination"][0]
+    r, s, t = b(e0["r"]), b(e0["s"]), e0["tau"]
+    delta = len(s) - len(r)
+    assert (t - delta) // 2 == e0["band_left"] and (t + delta) // 2 == e0["band_right"]
+    d, cells, rows = O.verify_pair(r, s, t)
+    assert rows == e0["length_aware_stop_row"] and cells == e0["length_aware_cells"]
+
+
+def test_length_aware_cells_full_pass_closed_form():
+    """No early stop when r is a prefix of s (every diagonal cell has E = Delta <= t), so every
+    row of the band is computed.  The band j in [i - a, i + b], a = floor((t-D)/2),
+    b = floor((t+D)/2), clipped to 1..|s| holds |r|(a+b+1) cells less the triangle cut off at
+    column 0 (a(a+1)/2) and the one past column |s| (c(c+1)/2 with c = b - D): a count derived
+    from the band's geometry, not by walking it as the oracle does.  A miscount at column 0, at
+    the right edge or in a band wider than one cell fails here."""
+    rng = random.Random(5)
+    checked = 0
+    for _ in range(600):
+        t = rng.randint(0, 12)
+        D = rng.randint(0, t)
+        a, bb = (t - D) // 2, (t + D) // 2
+        c = bb - D
+        nr = rng.randint(max(a, c), max(a, c) + 30)
+        r = bytes(rng.choice(b"abcd") for _ in range(nr))
+        s = r + bytes(rng.choice(b"abcd") for _ in range(D))
+        expect = nr * (a + bb + 1) - a * (a + 1) // 2 - c * (c + 1) // 2
+        for x, y in ((r, s), (s, r)):          # the shorter part gives the rows either way
+            d, cells, rows = O.verify_pair(x, y, t)
+            assert d == D and rows == nr and cells == expect, (t, D, nr)
+        checked += 1
+    assert checked == 600
+
+
 def test_extension_split_paper_example(golden):
     e = golden["extension"]
     r, s, w = b(e["r"]), b(e["s"]), b(e["shared"])
@@ -558,3 +594,30 @@ def test_probe_stride_samples_subset():
     samp = O.self_join_pj(col, 2, probe_stride=5)
     assert {tuple(p) for p in samp.pairs.tolist()} <= full
     assert 0 < samp.candidates < O.self_join_pj(col, 2).candidates
+
+
+def test_probe_shares_partition_the_run():
+    """The runs for probe offsets 0..k-1 of stride k (how the full-size golden values are made
+    over several processes) have disjoint pairs whose union is the single run's, and their
+    counters add up to the single run's."""
+    col = W.cfg1()
+    full = O.self_join_pj(col, 2)
+    k = 7
+    parts = [O.self_join_pj(col, 2, probe_stride=k, probe_offset=w) for w in range(k)]
+    allp = np.concatenate([p.pairs for p in parts])
+    assert len({tuple(p) for p in allp.tolist()}) == len(allp)          # disjoint
+    key = allp[:, 0].astype(np.int64) << 32 | allp[:, 1]
+    assert np.array_equal(allp[np.argsort(key)], full.pairs)
+    for f in ("candidates", "cells", "selected", "side_pairs"):
+        assert sum(getattr(p, f) for p in parts) == getattr(full, f), f
+    par = O.self_join_pj_parallel(col, 2, procs=3, shares=k)
+    assert np.array_equal(par.pairs, full.pairs) and par.cells == full.cells
+    # the join of two sets, with strings shorter than tau+1 on both sides
+    rng = np.random.default_rng(21)
+    R = W.random_small(rng, 400, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.4)
+    S = W.random_small(rng, 500, alphabet=b"abc", lmin=0, lmax=12, dup_frac=0.4)
+    jf = O.join_pj(R, S, 3)
+    jp = O.join_pj_parallel(R, S, 3, procs=2, shares=5)
+    assert np.array_equal(jp.pairs, jf.pairs) and np.array_equal(jf.pairs, O.join_bf(R, S, 3, 2))
+    for f in ("candidates", "cells", "selected", "side_pairs"):
+        assert getattr(jp, f) == getattr(jf, f), f

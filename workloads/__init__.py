@@ -309,6 +309,24 @@ def cfg5_batch(rng, index: Collection, mean: float = 64.0, tau_max: int = 8):
     return from_list(out, name="serving-batch"), taus
 
 
+def cfg5_queries(index: Collection, batches: int = 32, seed: int | None = None):
+    """A fixed serving stream for parity checks: `batches` batches drawn by cfg5_batch from one
+    seeded generator (seed 71715 + 100 by default).  Returns the list of (Collection, taus)."""
+    rng = np.random.default_rng(BASE_SEED + 105 if seed is None else seed)
+    return [cfg5_batch(rng, index) for _ in range(batches)]
+
+
+def concat(parts) -> Collection:
+    """The collections' strings back to back (ids renumbered in order)."""
+    chars = np.concatenate([p.chars for p in parts]) if parts else np.empty(0, np.uint8)
+    offs = [np.zeros(1, dtype=np.int64)]
+    base = 0
+    for p in parts:
+        offs.append(p.offsets[1:].astype(np.int64) + base)
+        base += int(p.offsets[-1])
+    return Collection(chars.astype(np.uint8), np.concatenate(offs).astype(np.int32), "concat")
+
+
 def random_small(rng, n: int, alphabet: bytes = b"ab", lmin: int = 0, lmax: int = 8,
                  dup_frac: float = 0.3, kmax: int = 2) -> Collection:
     """Tiny collections over a small alphabet with many repeats and near-duplicates, for
