@@ -24,7 +24,11 @@
  *    [0, PJ_TAU_MAX].
  *  - Inputs are borrowed for the duration of the call; they are host pointers unless
  *    pj_options.inputs_on_device is set, in which case they are device pointers on the current
- *    HIP device.  The call returns when its results are complete.
+ *    HIP device.  Device inputs are checked before any kernel reads them: both pointers must
+ *    be device (or managed) memory of the current device, the allocation holding `offsets`
+ *    must hold n + 1 entries and the one holding `bytes` at least offsets[n] bytes (`bytes`
+ *    may be NULL only when offsets[n] == 0); otherwise PJ_EINVAL.  The call returns when its
+ *    results are complete.
  *  - Outputs are owned by the caller and released with pj_pairs_free / pj_index_free.
  *  - Results are sets with one canonical order, so a given input has exactly one correct output.
  *  - Calls are thread-safe with respect to each other; error text and statistics are kept per
@@ -102,7 +106,8 @@ typedef struct {
     int64_t index_entries; /* (string, slot) entries in the segment index */
     int64_t selected;      /* substrings selected by the multi-match windows and looked up */
     int64_t hits;          /* selected substrings that found a non-empty inverted list */
-    int64_t candidates;    /* (y, x, i, p) candidates after the visiting-order filter */
+    int64_t candidates;    /* (y, x, i, p) candidates after the visiting-order filter: x[p, l_i]
+                              equals segment i of y */
     int64_t cells;         /* DP cells evaluated by extension verification (Sec. 5.1 band) */
     int64_t accepted;      /* candidates that passed, before deduplication */
     int64_t side_pairs;    /* pairs examined directly because a string is shorter than tau+1 */
@@ -114,6 +119,9 @@ typedef struct {
     double ms_list_kernel;     /* device time of the list-segment verification launches */
     int64_t list_cells;        /* cells evaluated by the list-segment verification */
     int64_t list_launches;     /* list-segment verification launches */
+    int64_t key_collisions;    /* lookups whose hashed segment key matched a list of other
+                                  bytes: rejected by the byte comparison before verification and
+                                  not counted in candidates */
 } pj_stats;
 
 /* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with
@@ -173,7 +181,12 @@ typedef struct pj_server pj_server;
 typedef struct {
     int32_t slots;              /* device batches in flight at once, >= 1 */
     int32_t max_batch_queries;  /* queries merged into one device batch, >= 1 */
-    int64_t mem_budget_bytes;   /* bound on the summed footprint estimates in flight; 0 = none */
+    int64_t mem_budget_bytes;   /* bound on the summed footprint estimates in flight plus the
+                                   slots' fixed buffers (captured mode: about 33 MB per slot,
+                                   taken off the budget at start; PJ_ENOMEM if they do not fit);
+                                   0 = none.  The estimate leaves out each batch's accepted-
+                                   candidate buffer (8 B per candidate, known only after the
+                                   probe), so it bounds the other device memory only */
     const char* tune_cache;     /* autotune cache file read by the batches (see pj_tune); NULL =
                                    none.  The string is copied by pj_server_start. */
     int32_t eager;              /* 0: each slot replays one captured hipGraph of the device phases
@@ -186,7 +199,9 @@ typedef struct {
     double t_submit_ms;         /* pj_server_submit accepted the request */
     double t_admit_ms;          /* the scheduler placed it in a device batch */
     double t_done_ms;           /* its pairs were ready in host memory */
-    int64_t footprint_bytes;    /* admission estimate: 16 B per selectable substring + arena */
+    int64_t footprint_bytes;    /* admission estimate: 48 B per selectable substring (hit
+                                   record, its bucketed copy, prefix sum, count and scan
+                                   scratch) + twice the query bytes */
     int32_t batch_requests;     /* requests in the same device batch */
     int32_t slot;               /* slot that ran it */
 } pj_request_info;
@@ -196,11 +211,14 @@ int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server*
 
 /* Submits a request: Q (host memory, copied) with one threshold per query in the index's
  * range.  Returns a request id >= 0, or a negative PJ_E* code (PJ_ENOMEM when the request's own
- * footprint exceeds the budget).  Never blocks on device work. */
+ * footprint exceeds the budget left after the slots' fixed buffers).  Never blocks on device
+ * work. */
 int64_t pj_server_submit(pj_server* srv, const pj_strings* Q, const int32_t* taus);
 
 /* Blocks until the request is done; its (q, s) pairs (sorted, q local to the request) go to
- * *out (host memory) and its timing to *info (may be NULL).  Each id can be waited once. */
+ * *out (host memory) and its timing to *info (may be NULL).  Each id can be collected once:
+ * if several threads wait on one id, the first to return collects it and the others get
+ * PJ_EINVAL. */
 int pj_server_wait(pj_server* srv, int64_t request, pj_pairs* out, pj_request_info* info);
 
 /* Stops admitting, finishes the work in flight and queued, then frees the server. */

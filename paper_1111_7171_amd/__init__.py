@@ -64,7 +64,8 @@ class PjStats(C.Structure):
                                           "ms_output", "ms_total", "ms_probe_kernel",
                                           "ms_verify_kernel")] + \
                [("verify_launches", C.c_int64), ("ms_list_kernel", C.c_double),
-                ("list_cells", C.c_int64), ("list_launches", C.c_int64)]
+                ("list_cells", C.c_int64), ("list_launches", C.c_int64),
+                ("key_collisions", C.c_int64)]
 
 
 class PjServerConfig(C.Structure):
@@ -174,13 +175,22 @@ class _Marshalled:
             chars, offs = strings.chars, strings.offsets
         else:
             chars, offs = strings
-        self.on_device = _is_torch(offs) and offs.is_cuda
+        self.on_device = (_is_torch(offs) and offs.is_cuda) or \
+            (_is_torch(chars) and chars.is_cuda)
         if self.on_device:
             import torch
+            # both arrays on the same device (the library also checks the pointers and the
+            # allocation sizes before any kernel reads them)
+            if not (_is_torch(chars) and _is_torch(offs) and chars.is_cuda and offs.is_cuda):
+                raise PassJoinError(PJ_EINVAL, "chars and offsets must both be device tensors")
+            if chars.device != offs.device:
+                raise PassJoinError(PJ_EINVAL, "chars and offsets are on different devices")
             if chars.dtype != torch.uint8 or offs.dtype != torch.int32:
                 raise PassJoinError(PJ_EINVAL, "device strings must be uint8 chars, int32 offsets")
             if not (chars.is_contiguous() and offs.is_contiguous()):
                 raise PassJoinError(PJ_EINVAL, "device strings must be contiguous")
+            if offs.dim() != 1 or offs.numel() < 1:
+                raise PassJoinError(PJ_EINVAL, "offsets must be a 1-D tensor of n+1 entries")
             self.keep = (chars, offs)
             self.s = PjStrings(offs.numel() - 1, chars.data_ptr() if chars.numel() else None,
                                offs.data_ptr())

@@ -205,15 +205,50 @@ void validate_host_strings(const pj_strings* S, const char* what)
     if (S->offsets[S->n] > 0 && !S->bytes) throw Error(PJ_EINVAL, "%s: null bytes", what);
 }
 
+// Bytes of device memory readable from p: the rest of the allocation that holds p.  Throws
+// PJ_EINVAL when p is not device (or managed) memory of the current device, so no kernel is
+// ever handed a host, unregistered or foreign pointer.
+static size_t device_extent(const void* p, const std::string& what)
+{
+    hipPointerAttribute_t attr{};
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(PJ_EINVAL, "%s: not a device pointer", what.c_str());
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        throw Error(PJ_EINVAL, "%s: not device memory (memory type %d)", what.c_str(),
+                    (int)attr.type);
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (attr.type == hipMemoryTypeDevice && attr.device != dev)
+        throw Error(PJ_EINVAL, "%s: memory of device %d, the current device is %d", what.c_str(),
+                    attr.device, dev);
+    void* base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        throw Error(PJ_EINVAL, "%s: no device allocation holds this pointer", what.c_str());
+    }
+    return size - (size_t)((const uint8_t*)p - (const uint8_t*)base);
+}
+
 void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
                hipStream_t st)
 {
     if (!S) throw Error(PJ_EINVAL, "%s: null pj_strings", tag.c_str());
+    size_t bytes_extent = 0;
     if (!on_device) validate_host_strings(S, tag.c_str());
     else {
         if (S->n < 0) throw Error(PJ_EINVAL, "%s: n < 0", tag.c_str());
         if (S->n >= (int64_t)INT32_MAX) throw Error(PJ_ERANGE, "%s: too many strings", tag.c_str());
         if (!S->offsets) throw Error(PJ_EINVAL, "%s: null offsets", tag.c_str());
+        // every pointer a kernel will read is checked first: device memory, large enough
+        if (device_extent(S->offsets, tag + ".offsets") < sizeof(int32_t) * (size_t)(S->n + 1))
+            throw Error(PJ_EINVAL, "%s: offsets allocation holds fewer than n + 1 entries",
+                        tag.c_str());
+        if (S->bytes) bytes_extent = device_extent(S->bytes, tag + ".bytes");
     }
     const int64_t n = S->n;
     D.n = n;
@@ -243,13 +278,25 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
     hip_check(hipMemsetAsync(lcount, 0, sizeof(int32_t) * (kLenTab + 1), st), "memset");
     hip_check(launch_length_hist(d_offs, n, lcount, lcount + kLenTab, st), "length_hist");
     std::vector<int32_t> h(kLenTab + 1);
+    int32_t dev_total = 0;
     hip_check(hipMemcpyAsync(h.data(), lcount, sizeof(int32_t) * (kLenTab + 1),
                              hipMemcpyDeviceToHost, st), "download lcount");
+    if (on_device && n > 0)
+        hip_check(hipMemcpyAsync(&dev_total, d_offs + n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 st), "download offsets[n]");
     hip_check(hipStreamSynchronize(st), "sync");
     int err = h[kLenTab];
     if (err & 1) throw Error(PJ_EINVAL, "%s: offsets[0] != 0", tag.c_str());
     if (err & 2) throw Error(PJ_EINVAL, "%s: offsets decrease", tag.c_str());
     if (err & 4) throw Error(PJ_ERANGE, "%s: a string is longer than %d", tag.c_str(), kLenMax);
+    if (on_device && dev_total > 0) {
+        // the bytes the arena kernel will read: offsets[n] of them from S->bytes
+        if (!d_bytes) throw Error(PJ_EINVAL, "%s: null bytes with offsets[n] = %d", tag.c_str(),
+                                  dev_total);
+        if ((size_t)dev_total > bytes_extent)
+            throw Error(PJ_EINVAL, "%s: offsets[n] = %d exceeds the %zu bytes of the bytes "
+                        "allocation", tag.c_str(), dev_total, bytes_extent);
+    }
 
     int64_t pos = 0, bytes = 0;
     D.lmin = kLenTab;
@@ -648,6 +695,11 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     }
     int t_verify1 = tm.mark();
     J.naccepted = c[3];
+    // a hashed key can match a list whose segment bytes differ (a 40-bit collision): the byte
+    // guard rejects such a lookup before verification, and it is no candidate of the paper's
+    // (x[p, l_i] equal to the member's segment i), so it leaves the candidate count
+    stats.candidates -= (int64_t)c[5];
+    stats.key_collisions += (int64_t)c[5];
     stats.accepted += (int64_t)c[3];
     stats.cells += (int64_t)(c[4] + c[7]);
     stats.list_cells += (int64_t)c[7];
@@ -951,6 +1003,7 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.ms_list_kernel += t_stats.ms_list_kernel;
         acc.list_cells += t_stats.list_cells;
         acc.list_launches += t_stats.list_launches;
+        acc.key_collisions += t_stats.key_collisions;
         a = b + 1;
     }
     // k-way merge of the windows' sorted runs straight into the output arrays

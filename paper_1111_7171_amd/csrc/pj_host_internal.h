@@ -127,7 +127,43 @@ const DevSet& index_set(const pj_index* idx);
 const IndexRef* index_refs(const pj_index* idx);
 SymMap index_sym(const pj_index* idx);
 bool index_has_entries(const pj_index* idx);
+int index_device(const pj_index* idx);
 int64_t query_selections(const pj_index* idx, int n, int tau);
+
+// Fixed-capacity buffers of one mixed-tau query batch run by launch_graph_batch: the layout of
+// the batch tables (nx | lenstart | gbase | perm | q_tau | slen, packed on the host), the arena
+// and the device work buffers.  Used by the serving slots' captured pipelines (allocated) and
+// by pj_query_noalloc (carved out of a static device array).
+struct BatchLayout {
+    int64_t qcap = 0, bcap = 0;             // queries, arena bytes
+    uint64_t hcap = 0, chunk_cap = 0, acc_cap = 0;
+    size_t off_lenstart = 0, off_gbase = 0, off_perm = 0, off_qtau = 0, off_slen = 0;
+    size_t tables_bytes = 0, arena_bytes = 0;
+    size_t result_bytes = 0;                // [counters 8 | bcounts 4 | out_n | out kGraphSortCap]
+};
+struct BatchBuffers {
+    uint8_t* tables = nullptr;
+    uint8_t* arena = nullptr;
+    Hit* hits = nullptr;
+    unsigned long long* prefix = nullptr;
+    uint32_t* first = nullptr;
+    uint64_t* acc = nullptr;
+    uint8_t* result = nullptr;
+};
+enum class PackStatus { kOk, kTooManyQueries, kTauOutOfRange, kTooManySelections, kTooManyBytes };
+BatchLayout batch_layout(int max_queries, uint64_t hcap, uint64_t chunk_cap, uint64_t acc_cap);
+size_t batch_device_bytes(const BatchLayout& L);
+BatchBuffers carve_batch_buffers(const BatchLayout& L, uint8_t* base);
+void setup_graph_batch(const pj_index* idx, const BatchLayout& L, const BatchBuffers& B,
+                       const TuneParams& tp, GraphBatch& G);
+// Packs Q into the host mirrors of the tables and the arena; *arena_used = arena bytes to upload.
+PackStatus pack_query_batch(const pj_index* idx, const BatchLayout& L, const pj_strings* Q,
+                            const int32_t* taus, uint8_t* h_tables, uint8_t* h_arena,
+                            int64_t* arena_used);
+// Reads a batch result block: adds its counters to stats, returns the number of sorted
+// (query << 32 | indexed id) pairs at *pairs; *flags != 0 means a capacity overflowed.
+uint32_t batch_result(const uint8_t* h_result, pj_stats& stats, const uint64_t** pairs,
+                      unsigned long long* flags);
 
 // A serving slot's captured query pipeline (pj_graph.cpp): fixed-capacity device buffers, one
 // instantiated hipGraph of the device phases, pinned staging for the batch and its result.
@@ -135,6 +171,7 @@ struct GraphPlan;
 GraphPlan* graph_plan_create(const pj_index* idx, int max_queries, hipStream_t st,
                              const char* tune_cache);
 void graph_plan_destroy(GraphPlan* g);
+int64_t graph_plan_device_bytes(int max_queries);
 // Runs one batch through the graph; false when the batch does not fit the plan's capacities or
 // a device-side capacity overflowed (the caller then runs it with run_query_batch).  pairs get
 // (query << 32 | indexed id), sorted.

@@ -25,6 +25,7 @@ struct pj_index {
     std::vector<pj::DevIndex> X;
     pj::IndexRef* refs = nullptr;    // device [kTauMax + 1], entries for tau_min .. tau_max
     bool has_entries = false;
+    int device = 0;                  // the HIP device the index lives on
 };
 
 namespace pj {
@@ -35,6 +36,7 @@ const DevSet& index_set(const pj_index* idx) { return idx->S; }
 const IndexRef* index_refs(const pj_index* idx) { return idx->refs; }
 SymMap index_sym(const pj_index* idx) { return idx->X.front().sym; }
 bool index_has_entries(const pj_index* idx) { return idx->has_entries; }
+int index_device(const pj_index* idx) { return idx->device; }
 const DevIndex& index_for(const pj_index* idx, int tau) { return idx->X[tau - idx->tau_min]; }
 void index_taus(const pj_index* idx, int* lo, int* hi)
 {
@@ -136,11 +138,13 @@ int64_t query_selections(const pj_index* idx, int n, int tau)
     return sel;
 }
 
-// Admission estimate of one query: 16 bytes per hit record it may produce, plus its bytes twice
-// (the uploaded and the length-sorted arena).
+// Admission estimate of one query: per substring it may select, a hit record (16 B), its
+// bucketed copy (16 B), the candidate prefix sum (8 B), the per-hit count and scan scratch
+// (8 B); plus its bytes twice (the uploaded and the length-sorted arena).  The accepted-
+// candidate buffer (8 B per candidate found) is not known before the probe and is not counted.
 int64_t query_footprint(const pj_index* idx, int n, int tau)
 {
-    return 16 * query_selections(idx, n, tau) + 2 * (int64_t)stride_of(n) + 64;
+    return 48 * query_selections(idx, n, tau) + 2 * (int64_t)stride_of(n) + 64;
 }
 
 }  // namespace pj
@@ -167,6 +171,7 @@ int pj_build_index(const pj_strings* S, int32_t tau_min, int32_t tau_max, const 
         idx->tau_min = tau_min;
         idx->tau_max = tau_max;
         idx->mem.budget = opt ? opt->mem_budget_bytes : 0;
+        hip_check(hipGetDevice(&idx->device), "hipGetDevice");
         thread_workspace().begin_call(0);
         build_set(S, on_dev, idx->mem, "I", idx->S, st);
         idx->X.resize((size_t)(tau_max - tau_min + 1));

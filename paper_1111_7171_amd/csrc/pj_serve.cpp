@@ -72,6 +72,7 @@ struct pj_server {
     std::thread scheduler;
     int64_t next_id = 0;
     int64_t inflight_bytes = 0;
+    int64_t admit_budget = 0;            // the budget less the slots' fixed buffers (0: none)
     bool stopping = false;
     bool sched_done = false;
     int device = 0;
@@ -187,7 +188,7 @@ static void scheduler_main(pj_server* S)
                 free_slot = s.get();
                 break;
             }
-        const int64_t budget = S->cfg.mem_budget_bytes;
+        const int64_t budget = S->admit_budget;
         bool head_fits = !S->queue.empty() &&
                          (budget <= 0 || S->inflight_bytes + S->queue.front()->footprint <= budget);
         if (free_slot && head_fits) {
@@ -240,6 +241,17 @@ int pj_server_start(const pj_index* idx, const pj_server_config* cfg, pj_server*
         if (c.tune_cache) S->tune_cache = c.tune_cache;
         S->cfg.tune_cache = nullptr;
         index_taus(idx, &S->tau_min, &S->tau_max);
+        if (c.mem_budget_bytes > 0) {
+            // each slot's captured pipeline holds fixed-capacity buffers for the server's
+            // lifetime: they come off the budget before any request is admitted
+            const int64_t fixed = c.eager ? 0 : (int64_t)c.slots *
+                                                    graph_plan_device_bytes(c.max_batch_queries);
+            if (fixed >= c.mem_budget_bytes)
+                throw Error(PJ_ENOMEM, "memory budget %lld does not hold the %d slots' fixed "
+                            "buffers (%lld bytes)", (long long)c.mem_budget_bytes, c.slots,
+                            (long long)fixed);
+            S->admit_budget = c.mem_budget_bytes - fixed;
+        }
         S->t0 = std::chrono::steady_clock::now();
         hip_check(hipGetDevice(&S->device), "hipGetDevice");
         for (int k = 0; k < c.slots; ++k) {
@@ -280,9 +292,10 @@ int64_t pj_server_submit(pj_server* S, const pj_strings* Q, const int32_t* taus)
                             (long long)q, taus[q], S->tau_min, S->tau_max);
             r->footprint += query_footprint(S->idx, Q->offsets[q + 1] - Q->offsets[q], taus[q]);
         }
-        if (S->cfg.mem_budget_bytes > 0 && r->footprint > S->cfg.mem_budget_bytes)
-            throw Error(PJ_ENOMEM, "request footprint %lld exceeds the server budget %lld",
-                        (long long)r->footprint, (long long)S->cfg.mem_budget_bytes);
+        if (S->admit_budget > 0 && r->footprint > S->admit_budget)
+            throw Error(PJ_ENOMEM, "request footprint %lld exceeds the server budget %lld "
+                        "(after the slots' fixed buffers)", (long long)r->footprint,
+                        (long long)S->admit_budget);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             if (S->stopping) throw Error(PJ_EINVAL, "server is stopping");
@@ -324,8 +337,15 @@ int pj_server_wait(pj_server* S, int64_t request, pj_pairs* out, pj_request_info
             return PJ_EINVAL;
         }
         r = it->second;
+        // the wait releases the mutex: submits may rehash `live` meanwhile, so no iterator is
+        // kept across it; of two waiters on one id only the first to return collects it
         S->cv_done.wait(lk, [&] { return r->done; });
-        S->live.erase(it);
+        auto again = S->live.find(request);
+        if (again == S->live.end() || again->second != r) {
+            t_last_error = "request already collected by another waiter";
+            return PJ_EINVAL;
+        }
+        S->live.erase(again);
     }
     if (info) *info = r->info;
     if (r->status != PJ_OK) {

@@ -97,3 +97,37 @@ def test_tune_rejects_invalid_arguments_on_host():
     r = P.PjTuneResult()
     assert lib.pj_tune(C.byref(s), 1, C.byref(o), C.byref(r)) == P.PJ_EINVAL
     assert "host" in P.pj_last_error()
+
+
+def test_device_flag_with_host_pointers_rejected():
+    """inputs_on_device = 1 with host arrays: the library checks every pointer before a kernel
+    reads it, so host memory (or, without a GPU, any pointer) is refused, never dereferenced."""
+    lib = P.load()
+    chars = np.frombuffer(b"abcabc", np.uint8).copy()
+    offs = np.array([0, 3, 6], np.int32)
+    s = P.PjStrings(2, chars.ctypes.data, offs.ctypes.data)
+    o = P.PjOptions()
+    o.inputs_on_device = 1
+    raw = P.PjPairs()
+    rc = lib.pj_self_join(C.byref(s), 1, C.byref(o), C.byref(raw))
+    assert rc in (P.PJ_EINVAL, P.PJ_EDEVICE) and raw.count == 0 and not raw.a
+    rc = lib.pj_join(C.byref(s), C.byref(s), 1, C.byref(o), C.byref(raw))
+    assert rc in (P.PJ_EINVAL, P.PJ_EDEVICE) and raw.count == 0
+
+
+def test_binding_rejects_mixed_host_and_device_arrays():
+    """The binding refuses a set whose two arrays are not both device tensors (checked before
+    any library call; torch CPU tensors stand in for a mismatched pair here)."""
+    import torch
+
+    class FakeDev:
+        """A CPU tensor claiming to be on a device: the check must not trust one array alone."""
+        __module__ = "torch"
+
+        def __init__(self, t):
+            self.t = t
+            self.is_cuda = True
+
+    chars = torch.from_numpy(np.frombuffer(b"abcabc", np.uint8).copy())
+    offs = torch.tensor([0, 3, 6], dtype=torch.int32)
+    assert _err(P.pj_self_join, (chars, FakeDev(offs)), 1) == P.PJ_EINVAL

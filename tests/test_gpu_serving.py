@@ -82,7 +82,13 @@ def test_tiny_budget_admits_one_at_a_time(served):
         probe = srv.submit(*batches[0])
         fp = srv.wait(probe)[1]["footprint_bytes"]
     budget = int(fp * 3)
-    with P.Server(idx, slots=4, max_batch_queries=1000, mem_budget=budget) as srv:
+    # a captured server keeps fixed buffers per slot, taken off the budget at start: a budget
+    # below them is refused
+    with pytest.raises(P.PassJoinError) as ei:
+        P.Server(idx, slots=4, max_batch_queries=1000, mem_budget=budget)
+    assert ei.value.code == P.PJ_ENOMEM and "fixed buffers" in str(ei.value)
+    # uncaptured slots hold no fixed buffers: the whole budget goes to admission
+    with P.Server(idx, slots=4, max_batch_queries=1000, mem_budget=budget, eager=True) as srv:
         ok_ids = []
         for q, t in batches:
             try:
@@ -100,7 +106,7 @@ def test_tiny_budget_admits_one_at_a_time(served):
 
 def test_oversize_request_rejected(served):
     S, idx, batches, alone = served
-    with P.Server(idx, slots=1, max_batch_queries=10, mem_budget=1024) as srv:
+    with P.Server(idx, slots=1, max_batch_queries=10, mem_budget=1024, eager=True) as srv:
         with pytest.raises(P.PassJoinError) as ei:
             srv.submit(*batches[0])
         assert ei.value.code == P.PJ_ENOMEM
