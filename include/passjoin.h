@@ -166,6 +166,24 @@ int pj_index_info(const pj_index* idx, int64_t* n, int32_t* tau_min, int32_t* ta
 int pj_query(const pj_index* idx, const pj_strings* Q, const int32_t* taus, const pj_options* opt,
              pj_pairs* out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): pj_query that makes no device allocation and, on success,
+ * no host allocation.  Its device work buffers are one static device array per GPU (8 MiB,
+ * held until the process ends) and its host staging is static; the results go to the caller's
+ * host arrays out_q[k], out_s[k] (k < out_cap), sorted by (q, s), and *out_count receives the
+ * number of pairs.  Q and taus are host memory (opt->inputs_on_device and
+ * opt->outputs_on_device must be 0); the index must live on the current device.  Capacities:
+ * at most 512 queries whose padded strings hold at most 256 KiB, at most 2^18 selected
+ * substrings (the Lemma 2 bound, checked before any device work), at most 2^24 candidates and
+ * 8,192 accepted candidates (checked on the device); beyond them, or when the pairs exceed
+ * out_cap (then *out_count still holds their number), the call returns PJ_ERANGE.  Calls on
+ * one process are serialised by the library; the static array keeps the last call's contents
+ * and every call resets what must start at zero.  The pairs and all counters equal pj_query's.
+ * Errors as pj_query, plus PJ_ERANGE for the capacities above. */
+int pj_query_noalloc(const pj_index* idx, const pj_strings* Q, const int32_t* taus,
+                     const pj_options* opt, int32_t* out_q, int32_t* out_s, int64_t out_cap,
+                     int64_t* out_count);
+
 /* ---- Serving: a request loop over a resident index ------------------------------------------
  *
  * A server owns worker slots, each with its own HIP stream (default priority) and device

@@ -22,7 +22,7 @@ __all__ = [
     "PassJoinError", "load", "pj_self_join", "pj_join", "pj_build_index", "pj_query",
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
     "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX", "Server", "Index",
-    "pj_tune",
+    "pj_tune", "pj_query_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -138,6 +138,9 @@ def load():
         lib.pj_server_wait.restype = C.c_int
         lib.pj_server_stop.argtypes = [C.c_void_p]
         lib.pj_server_stop.restype = C.c_int
+        lib.pj_query_noalloc.argtypes = [C.c_void_p, sp, C.c_void_p, op, C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+        lib.pj_query_noalloc.restype = C.c_int
         lib.pj_tune.argtypes = [sp, C.c_int32, op, C.POINTER(PjTuneResult)]
         lib.pj_tune.restype = C.c_int
         _lib = lib
@@ -390,6 +393,30 @@ def pj_query(index: Index, queries, taus, *, outputs_on_device: bool = False,
     _check(lib.pj_query(index.handle, C.byref(q.s), t.ctypes.data if t.size else None,
                         C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
+
+
+def pj_query_noalloc(index: Index, queries, taus, out_q: np.ndarray, out_s: np.ndarray, *,
+                     stream=None) -> int:
+    """pj_query into caller-owned int32 arrays, with no allocation in the library (static
+    device scratch).  Returns the number of pairs written to out_q[:m], out_s[:m]."""
+    lib = load()
+    q = _Marshalled(queries)
+    if q.on_device:
+        raise PassJoinError(PJ_EINVAL, "pj_query_noalloc takes host queries")
+    t = np.ascontiguousarray(taus, dtype=np.int32)
+    if t.size != q.s.n:
+        raise PassJoinError(PJ_EINVAL, "one tau per query is required")
+    for a in (out_q, out_s):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.int32 and a.flags.c_contiguous
+                and a.flags.writeable):
+            raise PassJoinError(PJ_EINVAL, "outputs must be writable contiguous int32 arrays")
+    cap = min(out_q.size, out_s.size)
+    o = _options(False, False, MODE_AUTO, 0, stream, None)
+    m = C.c_int64(0)
+    _check(lib.pj_query_noalloc(index.handle, C.byref(q.s), t.ctypes.data if t.size else None,
+                                C.byref(o), out_q.ctypes.data, out_s.ctypes.data, cap,
+                                C.byref(m)))
+    return int(m.value)
 
 
 class Server:
