@@ -222,6 +222,9 @@ typedef struct {
                                    scratch) + twice the query bytes */
     int32_t batch_requests;     /* requests in the same device batch */
     int32_t slot;               /* slot that ran it */
+    int32_t deferrals;          /* 1 if it reached the head of the queue and could not start at
+                                   once (no free slot, or the budget held no room), else 0 */
+    int32_t deferred_by_memory; /* 1 if that wait was for memory while a slot was free */
 } pj_request_info;
 
 /* Starts a server over idx (which must outlive the server).  cfg NULL = {2, 256, 0, NULL, 0}. */

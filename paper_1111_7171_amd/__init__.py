@@ -84,7 +84,8 @@ class PjTuneResult(C.Structure):
 class PjRequestInfo(C.Structure):
     _fields_ = [("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
                 ("t_done_ms", C.c_double), ("footprint_bytes", C.c_int64),
-                ("batch_requests", C.c_int32), ("slot", C.c_int32)]
+                ("batch_requests", C.c_int32), ("slot", C.c_int32),
+                ("deferrals", C.c_int32), ("deferred_by_memory", C.c_int32)]
 
 
 _lib = None

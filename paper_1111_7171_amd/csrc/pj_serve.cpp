@@ -35,6 +35,7 @@ struct Request {
     int status = PJ_OK;
     std::string error;
     bool done = false;
+    bool waiting_noted = false;    // its current wait at the head of the queue is counted
     pj_request_info info{};
 };
 
@@ -191,6 +192,13 @@ static void scheduler_main(pj_server* S)
         const int64_t budget = S->admit_budget;
         bool head_fits = !S->queue.empty() &&
                          (budget <= 0 || S->inflight_bytes + S->queue.front()->footprint <= budget);
+        if (!S->queue.empty() && !(free_slot && head_fits) && !S->queue.front()->waiting_noted) {
+            // the head of the queue has to wait: for a slot, or (a slot being free) for memory
+            auto& h = S->queue.front();
+            h->waiting_noted = true;
+            h->info.deferrals += 1;
+            if (free_slot) h->info.deferred_by_memory = 1;
+        }
         if (free_slot && head_fits) {
             std::unique_ptr<Batch> B(new Batch());
             const double t_admit = S->now_ms();
