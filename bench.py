@@ -267,7 +267,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="default: 1,000,000 (cfg2)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2"] + sorted(OTHER_WORKLOADS),
                     help="cfg2 (the default benchmark) or another synthetic workload")
-    ap.add_argument("--mode", type=int, default=0, help="0 auto, 1 plain, 2 batched")
+    ap.add_argument("--mode", type=int, default=0,
+                    help="0 auto, 1 plain, 2 batched, 3 batched with shared-prefix lists")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
@@ -405,6 +406,8 @@ def main():
             "ms_index": round(s["ms_index"], 3), "ms_probe": round(s["ms_probe"], 3),
             "ms_verify": round(s["ms_verify"], 3), "ms_output": round(s["ms_output"], 3),
             "ms_verify_kernel": round(s["ms_verify_kernel"], 3),
+            "shared_rows": s["shared_rows"], "shared_cells": s["shared_cells"],
+            "key_collisions": s["key_collisions"],
             "candidates_per_s": s["candidates"] / max(s["ms_total"], 1e-9) * 1e3,
             "gcups": s["cells"] / max(s["ms_verify_kernel"], 1e-9) / 1e6,
         }

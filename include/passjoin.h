@@ -56,6 +56,14 @@ extern "C" {
 #define PJ_MODE_AUTO     0   /* the fastest available: currently PJ_MODE_BATCHED */
 #define PJ_MODE_PLAIN    1   /* one kernel per phase, candidates materialised, host-sized */
 #define PJ_MODE_BATCHED  2   /* length-bucketed persistent probe/verify, graph-captured phases */
+#define PJ_MODE_SHARE_PREFIX 3 /* PJ_MODE_BATCHED with the big inverted lists verified by
+                                  sharing computations on common prefixes (Sec. 5.3): list
+                                  members in content order, each lane verifying a chain of
+                                  consecutive members and resuming every DP after the rows the
+                                  member shares with its predecessor (up to 16 stored rows).
+                                  Same pairs and counters; pj_stats.shared_rows/shared_cells
+                                  count the work taken over.  For tau <= 8 (larger tau: as
+                                  PJ_MODE_BATCHED) */
 
 /* A borrowed string set (see the conventions above). */
 typedef struct {
@@ -122,6 +130,10 @@ typedef struct {
     int64_t key_collisions;    /* lookups whose hashed segment key matched a list of other
                                   bytes: rejected by the byte comparison before verification and
                                   not counted in candidates */
+    int64_t shared_rows;       /* PJ_MODE_SHARE_PREFIX: DP rows taken from the previous member
+                                  of a content-ordered list instead of being computed (Sec. 5.3) */
+    int64_t shared_cells;      /* the cells of those rows (included in cells, which counts every
+                                  cell of the method's band; cells - shared_cells were computed) */
 } pj_stats;
 
 /* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with

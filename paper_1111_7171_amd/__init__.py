@@ -21,7 +21,8 @@ import numpy as np
 __all__ = [
     "PassJoinError", "load", "pj_self_join", "pj_join", "pj_build_index", "pj_query",
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
-    "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "PJ_TAU_MAX", "PJ_LEN_MAX", "Server", "Index",
+    "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "MODE_SHARE_PREFIX", "PJ_TAU_MAX", "PJ_LEN_MAX",
+    "Server", "Index",
     "pj_tune", "pj_query_noalloc",
 ]
 
@@ -30,7 +31,7 @@ LIB_PATH = os.path.join(_HERE, "libpassjoin.so")
 
 PJ_OK, PJ_EINVAL, PJ_ERANGE, PJ_ENOMEM, PJ_EDEVICE = 0, -1, -2, -3, -4
 PJ_TAU_MAX, PJ_LEN_MAX = 63, 2047
-MODE_AUTO, MODE_PLAIN, MODE_BATCHED = 0, 1, 2
+MODE_AUTO, MODE_PLAIN, MODE_BATCHED, MODE_SHARE_PREFIX = 0, 1, 2, 3
 SELECT_MULTIMATCH, SELECT_POSITION, SELECT_SHIFT, SELECT_LENGTH = 0, 1, 2, 3
 _CODES = {PJ_EINVAL: "EINVAL", PJ_ERANGE: "ERANGE", PJ_ENOMEM: "ENOMEM", PJ_EDEVICE: "EDEVICE"}
 
@@ -65,7 +66,8 @@ class PjStats(C.Structure):
                                           "ms_verify_kernel")] + \
                [("verify_launches", C.c_int64), ("ms_list_kernel", C.c_double),
                 ("list_cells", C.c_int64), ("list_launches", C.c_int64),
-                ("key_collisions", C.c_int64)]
+                ("key_collisions", C.c_int64), ("shared_rows", C.c_int64),
+                ("shared_cells", C.c_int64)]
 
 
 class PjServerConfig(C.Structure):

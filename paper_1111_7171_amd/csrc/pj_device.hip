@@ -1413,6 +1413,177 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
 // two short strings is taken once (from the later one).
 // ------------------------------------------------------------------------------------------
 
+// ------------------------------------------------------------------------------------------
+// Shared-prefix verification (Sec. 5.3).  The paper walks an inverted list in alphabetical
+// order and lets each member's DP start from the rows its left (right) part shares with the
+// previous member's.  In a wave the 64 lanes advance row by row together, so sharing rows
+// between lanes saves nothing; here a lane walks a chain of kChainMembers consecutive members
+// of a content-ordered list on its own, as the paper's loop does, keeping its previous
+// member's first kShareRows rows per side in LDS.  Lanes of a wave take consecutive chains
+// (the same list, or the next big lists).
+// ------------------------------------------------------------------------------------------
+
+// chains of one big hit: the whole list is walked in content order, so for a self-join's list
+// of the probe string's own length the members visited after it are skipped one by one
+__global__ __launch_bounds__(kBlock) void k_chain_counts(const Hit* __restrict__ big, uint64_t nbig,
+                                                         const uint16_t* __restrict__ x_slen,
+                                                         const uint32_t* __restrict__ runlen,
+                                                         int self, uint32_t* __restrict__ chains)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nbig) return;
+    const Hit h = big[k];
+    const int l = (int)(h.meta >> 17);
+    const uint32_t full = (self && l == (int)x_slen[h.gx]) ? runlen[h.start] : h.count;
+    chains[k] = (full + kChainMembers - 1u) / kChainMembers;
+}
+
+template <int MAXW>
+__global__ __launch_bounds__(kBlock) void k_verify_chains(VerifyParams V, Div div,
+                                                          const Hit* __restrict__ big,
+                                                          const unsigned long long* __restrict__ cprefix,
+                                                          uint64_t nbig, uint64_t nchains,
+                                                          const uint32_t* __restrict__ first,
+                                                          uint64_t nchunks)
+{
+    constexpr int NW = (MAXW + 7) / 8;
+    __shared__ uint64_t s_acc[kWaves][kAppendCap];
+    __shared__ uint32_t s_mat[kWaves][2][kShareRows * NW * 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    WaveAppender<uint64_t, kAppendCap> acc{s_acc[wv], 0};
+    __attribute__((address_space(3))) uint32_t* matL =
+        (__attribute__((address_space(3))) uint32_t*)(s_mat[wv][0]) + lane;
+    __attribute__((address_space(3))) uint32_t* matR =
+        (__attribute__((address_space(3))) uint32_t*)(s_mat[wv][1]) + lane;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    uint64_t my_cells = 0, my_miss = 0, my_srows = 0, my_scells = 0;
+    const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
+        const uint64_t c0 = ch * 64ull;
+        const uint64_t h = first[ch];
+        // the chain of each lane: boundaries of hits h .. h + 63 inside [c0, c0 + 64)
+        const uint64_t hk = h + (uint64_t)lane;
+        const unsigned long long bk = (hk < nbig) ? cprefix[hk + 1] : ~0ull;
+        const uint64_t rel = bk - c0;
+        const uint64_t M = wave_or64(rel < 64 ? (1ull << rel) : 0ull);
+        const int off = __popcll(M & le_mask);
+        const unsigned long long bprev = __shfl(bk, off > 0 ? off - 1 : 0, 64);
+        const unsigned long long hs = (off == 0) ? cprefix[h] : bprev;
+        const uint64_t c = c0 + (uint64_t)lane;
+        const bool valid = c < nchains;
+        Hit hit{0, 0, 0, 0};
+        int n = 0, l = 0, p = 1, i = 1;
+        uint32_t m0 = 0, m1 = 0;
+        const uint8_t* x = nullptr;
+        Seg sg{1, 0};
+        if (valid) {
+            hit = big[h + (uint64_t)off];
+            p = (int)(hit.meta & 2047u) + 1;
+            i = (int)((hit.meta >> 11) & 63u) + 1;
+            l = (int)(hit.meta >> 17);
+            n = V.x_slen[hit.gx];
+            x = V.x_arena + V.x_gbase[n] + (int64_t)(hit.gx - V.x_lenstart[n]) * stride_of(n);
+            const uint32_t full = (V.self && l == n) ? V.runlen[hit.start] : hit.count;
+            m0 = (uint32_t)(c - hs) * (uint32_t)kChainMembers;
+            m1 = min(m0 + (uint32_t)kChainMembers, full);
+            sg = partition_seg(l, i, V.tau, div);
+        }
+        const int tl = i - 1, tr = V.tau + 1 - i;
+        const int ry = sg.p - 1 + sg.len, rx = p - 1 + sg.len;
+        SharePrev pl{nullptr, 0, 0, 0, 0}, pr{nullptr, 0, 0, 0, 0};
+        for (int it = 0; it < kChainMembers; ++it) {
+            const uint32_t m = m0 + (uint32_t)it;
+            bool cand = valid && m < m1;
+            uint32_t gy = 0;
+            if (cand) {
+                gy = V.svals[hit.start + m];
+                if (V.self && l == n && gy >= hit.gx) cand = false;    // visited after x
+            }
+            bool pass = false;
+            if (cand) {
+                const uint8_t* y = V.y_arena + V.y_gbase[l] +
+                                   (int64_t)(gy - V.y_lenstart[l]) * stride_of(l);
+                bool same = true;
+                if (sg.len > V.exact_len)
+                    for (int k = 0; k < sg.len; ++k) same &= (x[p - 1 + k] == y[sg.p - 1 + k]);
+                if (!same) {
+                    my_miss += 1;
+                } else {
+                    const int dl = share_part<MAXW>(y, sg.p - 1, x, p - 1, tl, pl, matL, my_cells,
+                                                    my_srows, my_scells);
+                    if (dl <= tl) {
+                        const int dr = share_part<MAXW>(y + ry, l - ry, x + rx, n - rx, tr, pr,
+                                                        matR, my_cells, my_srows, my_scells);
+                        pass = dr <= tr;
+                    }
+                }
+            }
+            acc.push(pass, ((uint64_t)hit.gx << 32) | gy, V.out, V.out_cap, &V.counters[3]);
+        }
+    }
+    acc.flush(V.out, V.out_cap, &V.counters[3]);
+    my_cells = wave_sum(my_cells);
+    my_miss = wave_sum(my_miss);
+    my_srows = wave_sum(my_srows);
+    my_scells = wave_sum(my_scells);
+    if (lane == 0) {
+        if (my_cells) atomicAdd(&V.counters[4], (unsigned long long)my_cells);
+        if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
+        if (my_srows) atomicAdd(&V.counters[8], (unsigned long long)my_srows);
+        if (my_scells) atomicAdd(&V.counters[9], (unsigned long long)my_scells);
+    }
+}
+
+// Content order of the index entries: the first 8 bytes of each entry's string, big-endian,
+// so that comparing keys compares the strings' first 8 bytes; idx = entry number.
+__global__ __launch_bounds__(kBlock) void k_prefix8_keys(const uint32_t* __restrict__ vals, int64_t E,
+                                                         const uint8_t* __restrict__ sarena,
+                                                         const uint16_t* __restrict__ slen,
+                                                         const int32_t* __restrict__ lenstart,
+                                                         const int64_t* __restrict__ gbase,
+                                                         uint64_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ idx)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= E) return;
+    const uint32_t g = vals[e];
+    const int l = slen[g];
+    const uint8_t* w = sarena + gbase[l] + (int64_t)(g - lenstart[l]) * stride_of(l);
+    uint64_t k = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) k = (k << 8) | (uint64_t)(b < l ? w[b] : 0);
+    keys[e] = k;
+    idx[e] = (uint32_t)e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_keys(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ idx, int64_t E,
+                                                        uint64_t* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < E) out[e] = keys[idx[e]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_vals(const uint32_t* __restrict__ vals,
+                                                        const uint32_t* __restrict__ idx, int64_t E,
+                                                        uint32_t* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < E) out[e] = vals[idx[e]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_run_lengths(const uint32_t* __restrict__ runstart,
+                                                        uint32_t nruns, uint32_t E,
+                                                        uint32_t* __restrict__ runlen)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nruns) return;
+    const uint32_t st = runstart[r];
+    runlen[st] = ((r + 1 < nruns) ? runstart[r + 1] : E) - st;
+}
+
 template <int MAXW>
 __global__ __launch_bounds__(kBlock) void k_short(const uint8_t* __restrict__ x_arena,
                                                   const uint16_t* __restrict__ x_slen,
@@ -1754,6 +1925,70 @@ hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint3
     else if (w <= 17) verify_segs_w<17>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
     else if (w <= 33) verify_segs_w<33>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
     else verify_segs_w<64>(V, big, segp, nbig, nseg, first, nchunks, c, lc, grid, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_counts(const Hit* big, uint64_t nbig, const uint16_t* x_slen,
+                               const uint32_t* runlen, int self, uint32_t* chains, hipStream_t s)
+{
+    if (nbig == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain_counts, dim3(blocks_for(nbig)), dim3(kBlock), 0, s, big, nbig,
+                       x_slen, runlen, self, chains);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_chains(const VerifyParams& V, const Hit* big,
+                                const unsigned long long* cprefix, uint64_t nbig,
+                                uint64_t nchains, uint32_t* first, int grid, hipStream_t s)
+{
+    if (nbig == 0 || nchains == 0) return hipSuccess;
+    if (grid < 1 || V.tau + 1 > kShareMaxW || !V.svals || !V.runlen) return hipErrorInvalidValue;
+    const uint64_t nchunks = (nchains + 63) / 64;
+    hipLaunchKernelGGL(k_chunk_starts, dim3(blocks_for(nchunks)), dim3(kBlock), 0, s, cprefix,
+                       nbig, nchunks, 64ull, first);
+    const Div div = make_div(V.tau + 1);
+    if (V.tau + 1 <= 5)
+        hipLaunchKernelGGL((k_verify_chains<5>), dim3(grid), dim3(kBlock), 0, s, V, div, big,
+                           cprefix, nbig, nchains, first, nchunks);
+    else
+        hipLaunchKernelGGL((k_verify_chains<9>), dim3(grid), dim3(kBlock), 0, s, V, div, big,
+                           cprefix, nbig, nchains, first, nchunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix8_keys(const DevSet& S, const uint32_t* vals, int64_t E, uint64_t* keys,
+                               uint32_t* idx, hipStream_t s)
+{
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prefix8_keys, dim3(blocks_for((uint64_t)E)), dim3(kBlock), 0, s, vals,
+                       E, S.sarena, S.slen, S.lenstart, S.gbase, keys, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_keys(const uint64_t* keys, const uint32_t* idx, int64_t E,
+                              uint64_t* out, hipStream_t s)
+{
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_keys, dim3(blocks_for((uint64_t)E)), dim3(kBlock), 0, s, keys,
+                       idx, E, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_vals(const uint32_t* vals, const uint32_t* idx, int64_t E, uint32_t* out,
+                              hipStream_t s)
+{
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_vals, dim3(blocks_for((uint64_t)E)), dim3(kBlock), 0, s, vals,
+                       idx, E, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_lengths(const uint32_t* runstart, uint32_t nruns, uint32_t E,
+                              uint32_t* runlen, hipStream_t s)
+{
+    if (nruns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_lengths, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, runstart,
+                       nruns, E, runlen);
     return hipGetLastError();
 }
 

@@ -837,4 +837,164 @@ __device__ inline void vsp_seg2(LdsChars U, int lu, const RegChars (&V)[2], int 
     res[1] = (act[1] && all1) ? out1 : t + 1;
 }
 
+// ------------------------------------------------------------------------------------------
+// Sharing computations on common prefixes (Sec. 5.3)
+// ------------------------------------------------------------------------------------------
+
+// Rows of a part's DP a lane keeps for the next member of its chain, as 4-bit values
+// min(D, 15): with t <= 8, min(v, 15) commutes with the recurrence (min and non-negative
+// additions) and every decision compares with t < 15, so a DP resumed from the clamped row
+// takes the same early stop and returns the same min(t+1, distance).
+constexpr int kShareRows = 16;
+
+// The last member of a chain whose part DP ran, per side (left / right part).
+struct SharePrev {
+    const uint8_t* part;   // its part's bytes (nullptr: none yet)
+    int rows;              // rows evaluated, including a stopping row
+    int failed;            // stopped early (every expected distance of a row above t)
+    int result;            // min(t+1, distance) when it did not stop early
+    int stored;            // rows 1..stored of its DP are in the lane's matrix
+};
+
+// VerifyStringPair (Sec. 5.1, the function of Algorithm 3) of a member's part mp (length lm)
+// against the probe string's part xp (length lx), sharing the rows it has in common with the
+// previous member of the chain (pv): members of one list have parts of equal length and the
+// same band.  With rows = the member's part (lm <= lx), row i depends on the member's first i
+// bytes, so the rows within the common prefix c of the two parts are identical; with rows =
+// the probe's part, row i reads the member's first min(i + b, lm) bytes, so rows up to c - b
+// are.  The shared rows come from the lane's matrix (rows 1..min(shared, stored)) and the DP
+// resumes after them; an early stop inside the shared rows, or identical parts, are inherited
+// without any row.  Cells and the result are those of the unshared call (vsp_fast's
+// recurrence on expected distances); cells of rows taken over are added to shared_cells.
+// mat: the lane's matrix for this side, row r (1-based) at mat[(r - 1) * NW * 64 + w * 64].
+template <int MAXW>
+__device__ inline int share_part(const uint8_t* mp, int lm, const uint8_t* xp, int lx, int t,
+                                 SharePrev& pv, __attribute__((address_space(3))) uint32_t* mat,
+                                 uint64_t& cells, uint64_t& shared_rows, uint64_t& shared_cells)
+{
+    constexpr int NW = (MAXW + 7) / 8;
+    constexpr int BIG = 1 << 20;
+    const bool mrows = lm <= lx;
+    const uint8_t* A = mrows ? mp : xp;
+    const uint8_t* B = mrows ? xp : mp;
+    const int nr = mrows ? lm : lx;
+    const int nc = mrows ? lx : lm;
+    const int delta = nc - nr;
+    if (delta > t) {                          // no row is evaluated (the same for every member)
+        pv.part = mp;
+        pv.rows = 0;
+        pv.failed = 1;
+        pv.stored = 0;
+        return t + 1;
+    }
+    const int a = (t - delta) >> 1;
+    const int b = (t + delta) >> 1;
+    int sh = 0;
+    if (pv.part) {
+        int c = 0;
+        while (c < lm && pv.part[c] == mp[c]) ++c;
+        sh = (c >= lm) ? nr : (mrows ? c : max(0, c - b));
+        if (pv.failed && pv.rows <= sh) {     // stopped inside the shared rows: so does this one
+            const int cl = band_cells(pv.rows, nc, a, b);
+            cells += (uint64_t)cl;
+            shared_cells += (uint64_t)cl;
+            shared_rows += (uint64_t)pv.rows;
+            pv.part = mp;
+            return t + 1;
+        }
+        if (!pv.failed && sh >= nr) {         // identical rows throughout: the same distance
+            const int cl = band_cells(nr, nc, a, b);
+            cells += (uint64_t)cl;
+            shared_cells += (uint64_t)cl;
+            shared_rows += (uint64_t)nr;
+            pv.part = mp;
+            return pv.result;
+        }
+    }
+    const int s0 = pv.part ? min(sh, pv.stored) : 0;
+    int D[MAXW], w[MAXW], cu[MAXW], cl[MAXW];
+    if (s0 == 0) {
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) {
+            const int j = k - a;
+            const int ek = b > k ? b - k : k - b;
+            D[k] = (j >= 0 && j <= min(nc, b)) ? j + ek : BIG;
+        }
+    } else {
+        const __attribute__((address_space(3))) uint32_t* row = mat + (s0 - 1) * NW * 64;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t v = row[q * 64];
+#pragma unroll
+            for (int k = 8 * q; k < MAXW && k < 8 * q + 8; ++k) D[k] = (int)((v >> (4 * (k - 8 * q))) & 15u);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int j = s0 - a + k;             // B index of band index k in row s0 + 1
+        w[k] = ((unsigned)j < (unsigned)nc) ? (int)B[j] : 256;
+        cu[k] = k < b ? 2 : 0;
+        cl[k] = k > b ? 2 : 0;
+    }
+    int idx_in = s0 + MAXW - a;               // B index entering the window after row s0 + 1
+    int cin = ((unsigned)idx_in < (unsigned)nc) ? (int)B[idx_in] : 256;
+    int ai = (s0 < nr) ? (int)A[s0] : 256;
+    int rows = nr;
+    bool failed = false;
+    for (int i = s0 + 1; i <= nr; ++i) {
+        const int idx2 = idx_in + 1;
+        const int cin_next = ((unsigned)idx2 < (unsigned)nc) ? (int)B[idx2] : 256;
+        const int ai_next = (i < nr) ? (int)A[i] : 256;
+        int left = BIG;
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) {
+            const int up = (k + 1 < MAXW) ? D[(k + 1) < MAXW ? k + 1 : k] : BIG;
+            const int dg = D[k] + ((ai != w[k]) ? 1 : 0);
+            const int v = min(min(up + cu[k], left + cl[k]), dg);
+            D[k] = v;
+            left = v;
+        }
+        int emin = D[0];
+#pragma unroll
+        for (int k = 1; k < MAXW; ++k) emin = min(emin, D[k]);
+        if (emin > t) {
+            rows = i;
+            failed = true;
+            break;
+        }
+        if (i <= kShareRows) {                // keep the row for the next member
+            __attribute__((address_space(3))) uint32_t* row = mat + (i - 1) * NW * 64;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int k = 8 * q; k < MAXW && k < 8 * q + 8; ++k)
+                    v |= (uint32_t)min(D[k], 15) << (4 * (k - 8 * q));
+                row[q * 64] = v;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < MAXW; ++k) w[k] = w[k + 1];
+        w[MAXW - 1] = cin;
+        cin = cin_next;
+        idx_in = idx2;
+        ai = ai_next;
+    }
+    const int cl_all = band_cells(rows, nc, a, b);
+    const int cl_sh = band_cells(s0, nc, a, b);
+    cells += (uint64_t)cl_all;
+    shared_cells += (uint64_t)cl_sh;
+    shared_rows += (uint64_t)s0;
+    int out = BIG;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) out = (k == b) ? D[k] : out;
+    const int res = failed ? t + 1 : min(out, t + 1);
+    pv.part = mp;
+    pv.rows = rows;
+    pv.failed = failed ? 1 : 0;
+    pv.result = res;
+    pv.stored = min(failed ? rows - 1 : rows, kShareRows);
+    return res;
+}
+
 }  // namespace pj

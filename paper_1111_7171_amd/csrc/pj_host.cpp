@@ -351,7 +351,7 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
 // ------------------------------------------------------------------------------------------
 
 void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
-                 hipStream_t st, bool with_inline)
+                 hipStream_t st, bool with_inline, bool with_share)
 {
     const int T1 = tau + 1;
     X.tau = tau;
@@ -460,6 +460,31 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     hip_check(launch_clear_table(X.table, slots, st), "clear_table");
     hip_check(launch_insert_runs(keys, runstart, nruns, (uint32_t)E, X.table, X.mask, st),
               "insert_runs");
+    if (with_share) {
+        // content order of every list (shared-prefix verification, Sec. 5.3): entries sorted by
+        // (key, first 8 bytes of the string, g) -- by the bytes first, then stably by the key
+        uint64_t* pk = (uint64_t*)W.get("share.pk", sizeof(uint64_t) * (size_t)E);
+        uint32_t* pi = (uint32_t*)W.get("share.pi", sizeof(uint32_t) * (size_t)E);
+        uint64_t* pk2 = (uint64_t*)W.get("index.keys2", sizeof(uint64_t) * (size_t)E);
+        uint32_t* pi2 = (uint32_t*)W.get("index.vals2", sizeof(uint32_t) * (size_t)E);
+        hip_check(launch_prefix8_keys(D, vals, E, pk, pi, st), "prefix8 keys");
+        bool alt2 = false;
+        hip_check(radix_sort_u64(pk, pi, pk2, pi2, (uint64_t)E, 64, tmp, tb, &alt2, st),
+                  "radix(content)");
+        uint32_t* order = alt2 ? pi2 : pi;
+        uint32_t* order_alt = alt2 ? pi : pi2;
+        uint64_t* k1 = alt2 ? pk : pk2;               // free key buffers
+        uint64_t* k1_alt = alt2 ? pk2 : pk;
+        hip_check(launch_gather_keys(keys, order, E, k1, st), "gather keys");
+        bool alt3 = false;
+        hip_check(radix_sort_u64(k1, order, k1_alt, order_alt, (uint64_t)E, bits, tmp, tb, &alt3,
+                                 st), "radix(content key)");
+        if (alt3) order = order_alt;
+        X.svals = (uint32_t*)A.get(nm("svals").c_str(), sizeof(uint32_t) * (size_t)E);
+        X.runlen = (uint32_t*)A.get(nm("runlen").c_str(), sizeof(uint32_t) * (size_t)E);
+        hip_check(launch_gather_vals(vals, order, E, X.svals, st), "gather svals");
+        hip_check(launch_run_lengths(runstart, nruns, (uint32_t)E, X.runlen, st), "run lengths");
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -496,8 +521,10 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     const int tau = spec.tau;
     const bool self = spec.self;
     const int T1 = tau + 1;
-    J.counters = (unsigned long long*)W.get("join.counters", 8 * sizeof(unsigned long long));
-    hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
+    J.counters = (unsigned long long*)W.get("join.counters",
+                                            kJoinCounters * sizeof(unsigned long long));
+    hip_check(hipMemsetAsync(J.counters, 0, kJoinCounters * sizeof(unsigned long long), st),
+              "memset");
     int64_t probe_first = 0;
     uint64_t bound = spec.q_tau ? spec.bound
                                 : selection_bound(P, Y, tau, self, &probe_first,
@@ -511,11 +538,12 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     uint64_t hit_cap = std::min<uint64_t>(std::max<uint64_t>(bound, 1), 1ull << 26);
     const bool entries = spec.q_tau ? spec.has_entries : (spec.X && spec.X->entries > 0);
     int t_probe0 = tm.mark();
-    unsigned long long c[8];
+    unsigned long long c[kJoinCounters];
     for (int attempt = 0; attempt < 2; ++attempt) {
     J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)hit_cap);
     if (attempt > 0)
-        hip_check(hipMemsetAsync(J.counters, 0, 8 * sizeof(unsigned long long), st), "memset");
+        hip_check(hipMemsetAsync(J.counters, 0, kJoinCounters * sizeof(unsigned long long), st),
+                  "memset");
     if (nprobe > 0 && bound > 0 && entries) {
         ProbeParams pp{};
         pp.x_arena = P.sarena; pp.x_slen = P.slen; pp.x_lenstart = P.lenstart; pp.x_gbase = P.gbase;
@@ -596,7 +624,29 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         void* stmp = W.get("scan.tmp", sb);
         hip_check(scan_u32_to_u64(counts, J.prefix, nsmall, stmp, sb, st), "scan(prefix)");
     }
-    if (nbig > 0) {
+    // shared-prefix verification of the big lists (Sec. 5.3): chains of list members
+    const bool share = J.mode == PJ_MODE_SHARE_PREFIX && spec.X && spec.X->svals && nbig > 0;
+    unsigned long long* cprefix = nullptr;
+    uint64_t nchains = 0;
+    if (share) {
+        uint32_t* chains = (uint32_t*)W.get("join.chains", sizeof(uint32_t) * (size_t)nbig);
+        cprefix = (unsigned long long*)W.get("join.cprefix",
+                                             sizeof(unsigned long long) * (size_t)(nbig + 1));
+        hip_check(launch_chain_counts(bigp, nbig, P.slen, spec.X->runlen, self ? 1 : 0, chains,
+                                      st), "chain_counts");
+        size_t sb = scan_tmp_bytes(nbig);
+        void* stmp = W.get("scan.tmp2", sb);
+        hip_check(scan_u32_to_u64(chains, cprefix, nbig, stmp, sb, st), "scan(chains)");
+        unsigned long long cs = 0, nc = 0;
+        hip_check(hipMemcpyAsync(&nc, cprefix + nbig, sizeof nc, hipMemcpyDeviceToHost, st),
+                  "nchains");
+        if (nsmall > 0)
+            hip_check(hipMemcpyAsync(&cs, J.prefix + nsmall, sizeof cs, hipMemcpyDeviceToHost, st),
+                      "ncand small");
+        hip_check(hipStreamSynchronize(st), "sync");
+        nchains = nc;
+        ncand_small = cs;
+    } else if (nbig > 0) {
         uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
         segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + 1));
         hip_check(launch_seg_counts(bigp, nbig,
@@ -620,7 +670,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     uint64_t cap = std::min<uint64_t>(J.ncand + 4096, 1ull << 28);
     for (int attempt = 0; attempt < 2; ++attempt) {
         J.out = (uint64_t*)W.get("join.out", sizeof(uint64_t) * (size_t)cap);
-        hip_check(hipMemsetAsync(J.counters + 3, 0, 5 * sizeof(unsigned long long), st), "memset");
+        hip_check(hipMemsetAsync(J.counters + 3, 0, (kJoinCounters - 3) * sizeof(unsigned long long),
+                                 st), "memset");
         J.kernel_marks.erase(std::remove_if(J.kernel_marks.begin(), J.kernel_marks.end(),
                                             [](const JoinScratch::Mark& m) { return m.kind != 0; }),
                              J.kernel_marks.end());
@@ -662,6 +713,23 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                               "verify_batched");
                     stats.verify_launches += 1;
                 }
+                if (share && nchains > 0) {
+                    vp.svals = spec.X->svals;
+                    vp.runlen = spec.X->runlen;
+                    vp.self = self ? 1 : 0;
+                    const uint64_t nchunks = (nchains + 63) / 64;
+                    uint32_t* first = (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)nchunks);
+                    const uint64_t waves = std::min<uint64_t>(
+                        nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
+                    const int s0 = tm.mark();
+                    hip_check(launch_verify_chains(vp, bigp, cprefix, nbig, nchains, first,
+                                                   (int)((waves + 3) / 4), st),
+                              "verify_chains");
+                    const int s1 = tm.mark();
+                    J.kernel_marks.push_back({s0, s1, 2});
+                    stats.verify_launches += 1;
+                    stats.list_launches += 1;
+                }
                 if (nseg > 0) {
                     const uint64_t nchunks = seg_chunks(nseg, J.tp.seg_chunk);
                     uint32_t* first = (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)nchunks);
@@ -702,6 +770,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     stats.key_collisions += (int64_t)c[5];
     stats.accepted += (int64_t)c[3];
     stats.cells += (int64_t)(c[4] + c[7]);
+    stats.shared_rows += (int64_t)c[8];
+    stats.shared_cells += (int64_t)c[9];
     stats.list_cells += (int64_t)c[7];
     stats.side_pairs += (int64_t)c[6];
     J.guard_misses = c[5];
@@ -855,7 +925,7 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     if (!out) throw Error(PJ_EINVAL, "null output");
     zero_pairs(out);
     check_tau(tau);
-    if (opt && (opt->mode < PJ_MODE_AUTO || opt->mode > PJ_MODE_BATCHED))
+    if (opt && (opt->mode < PJ_MODE_AUTO || opt->mode > PJ_MODE_SHARE_PREFIX))
         throw Error(PJ_EINVAL, "unknown mode %d", opt->mode);
     if (opt && (opt->selection < PJ_SELECT_MULTIMATCH || opt->selection > PJ_SELECT_LENGTH))
         throw Error(PJ_EINVAL, "unknown selection method %d", opt->selection);
@@ -877,7 +947,9 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     const DevSet& YY = self ? P : Y;
     int e1 = tm.mark();
     DevIndex X;
-    build_index(YY, tau, W, "X", X, st, !(opt && opt->mode == PJ_MODE_PLAIN));
+    const int mode = opt ? opt->mode : PJ_MODE_AUTO;
+    build_index(YY, tau, W, "X", X, st, mode != PJ_MODE_PLAIN,
+                mode == PJ_MODE_SHARE_PREFIX && tau + 1 <= kShareMaxW);
     int e2 = tm.mark();
     t_stats.strings = P.n + (self ? 0 : Y.n);
     t_stats.index_entries = X.entries;
@@ -1004,6 +1076,8 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.list_cells += t_stats.list_cells;
         acc.list_launches += t_stats.list_launches;
         acc.key_collisions += t_stats.key_collisions;
+        acc.shared_rows += t_stats.shared_rows;
+        acc.shared_cells += t_stats.shared_cells;
         a = b + 1;
     }
     // k-way merge of the windows' sorted runs straight into the output arrays

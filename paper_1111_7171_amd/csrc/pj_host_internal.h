@@ -94,7 +94,7 @@ struct JoinScratch {
 void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
                hipStream_t st);
 void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
-                 hipStream_t st, bool with_inline = false);
+                 hipStream_t st, bool with_inline = false, bool with_share = false);
 // What to probe: a uniform tau against one index, or per-probe thresholds (q_tau, by sorted
 // position of the probe set) against the per-tau indices in refs.
 struct ProbeSpec {

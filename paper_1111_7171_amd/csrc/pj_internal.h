@@ -68,6 +68,11 @@ struct DevIndex {
     // bytes; nullptr otherwise): entry j of length l at inl + inl_base[l] + j * stride_of(l)
     uint8_t* inl = nullptr;
     int64_t* inl_base = nullptr;        // [kLenTab] device
+    // shared-prefix verification (Sec. 5.3): every list's members in content order (sorted by
+    // the first 8 bytes of the string, then g), at the list's positions; and the full length of
+    // each list at its first entry (other entries unused).  nullptr when not built.
+    uint32_t* svals = nullptr;          // [entries]
+    uint32_t* runlen = nullptr;         // [entries]
 };
 
 // Per-threshold view of a multi-tau index (serving): the bucket table and list entries of the
@@ -132,7 +137,16 @@ struct VerifyParams {
     const unsigned long long* dev_counts;
     int exact_len;              // segments up to this length have exact keys (no byte guard)
     int wave_rounds;            // batched verification: rounds of 64 candidates per wave chunk
+    // shared-prefix verification: content-ordered lists and list lengths (DevIndex::svals,
+    // runlen), and whether this is a self-join (lists of the probe's own length are then
+    // filtered to the members visited before it, member by member)
+    const uint32_t* svals;
+    const uint32_t* runlen;
+    int self;
 };
+// counters [8] rows and [9] cells that shared-prefix verification took from an earlier
+// member's DP instead of computing them
+constexpr int kJoinCounters = 12;
 
 // ---- launchers (pj_device.hip) ----
 hipError_t launch_length_hist(const int32_t* offs, int64_t n, int32_t* lcount, int32_t* err,
@@ -178,6 +192,27 @@ hipError_t launch_verify_segs(const VerifyParams& V, const Hit* big, const uint3
                               uint64_t nbig, uint64_t nseg, uint32_t* first, int chunk,
                               int lane_cands, int grid, hipStream_t s);
 uint64_t seg_chunks(uint64_t nseg, int chunk);
+// shared-prefix verification (Sec. 5.3) of the big lists: a lane takes a chain of up to
+// kChainMembers consecutive members of a content-ordered list.  chains: per big hit, its chain
+// count (u32, launch_chain_counts); cprefix: exclusive u64 scan of it (nbig + 1); first:
+// (nchains + 63) / 64 u32 of scratch.  Supports tau + 1 <= kShareMaxW (the caller checks).
+constexpr int kChainMembers = 16;
+constexpr int kShareMaxW = 9;
+hipError_t launch_chain_counts(const Hit* big, uint64_t nbig, const uint16_t* x_slen,
+                               const uint32_t* runlen, int self, uint32_t* chains, hipStream_t s);
+hipError_t launch_verify_chains(const VerifyParams& V, const Hit* big,
+                                const unsigned long long* cprefix, uint64_t nbig,
+                                uint64_t nchains, uint32_t* first, int grid, hipStream_t s);
+// content order of the entries: (key, first 8 bytes of the string, g) -> svals; list lengths at
+// each list's first entry -> runlen
+hipError_t launch_prefix8_keys(const DevSet& S, const uint32_t* vals, int64_t E, uint64_t* keys,
+                               uint32_t* idx, hipStream_t s);
+hipError_t launch_gather_keys(const uint64_t* keys, const uint32_t* idx, int64_t E,
+                              uint64_t* out, hipStream_t s);
+hipError_t launch_gather_vals(const uint32_t* vals, const uint32_t* idx, int64_t E, uint32_t* out,
+                              hipStream_t s);
+hipError_t launch_run_lengths(const uint32_t* runstart, uint32_t nruns, uint32_t E,
+                              uint32_t* runlen, hipStream_t s);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
 // wave chunks of 64 * rounds candidates (rounds in [1, kBatchedRoundsMax])
 uint64_t batched_chunks(uint64_t ncand, int rounds);

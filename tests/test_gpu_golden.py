@@ -94,6 +94,29 @@ def test_self_join_full_size_matches_oracle(cfg, tau, tune_cache):
         assert O.ed_full(col.get(int(pairs[k, 0])), col.get(int(pairs[k, 1]))) <= tau
 
 
+@pytest.mark.parametrize("cfg,tau", [(2, 4), (3, 8)])
+def test_share_prefix_full_size_matches_oracle(cfg, tau):
+    """The shared-prefix mode (Sec. 5.3) at full size: same pairs and counts as the oracle."""
+    import torch
+    g = GOLD[f"cfg{cfg}"]
+    e = g["taus"][str(tau)]
+    col = _col(cfg)
+    chars = torch.from_numpy(col.chars.copy()).cuda()
+    offs = torch.from_numpy(col.offsets.copy()).cuda()
+    dp = P.pj_self_join((chars, offs), tau, outputs_on_device=True, mode=P.MODE_SHARE_PREFIX)
+    try:
+        st = P.pj_last_stats()
+        pairs = dp.to_numpy()
+    finally:
+        dp.free()
+    _say(f"cfg{cfg} tau={tau} shared-prefix: pairs {len(pairs)}, shared cells "
+         f"{st['shared_cells']} of {st['cells']}, shared rows {st['shared_rows']}")
+    _check_set(pairs, col.n, True)
+    assert len(pairs) == e["pairs"] and _sha(pairs) == e["pairs_sha256"]
+    _check_counts(st, e, f"cfg{cfg} tau={tau} shared-prefix")
+    assert st["shared_rows"] > 0
+
+
 def test_serving_stream_full_size_matches_oracle():
     g = GOLD["cfg5"]
     S = W.cfg5_index()
