@@ -515,6 +515,18 @@ __global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restri
     }
 }
 
+// One thread per list: sets its key's filter bit.
+__global__ __launch_bounds__(kBlock) void k_filter_keys(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ runstart,
+                                                        uint32_t nruns, uint32_t* __restrict__ filter,
+                                                        uint32_t fmask)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nruns) return;
+    const uint64_t h = table_slot(keys[runstart[r]]);
+    atomicOr(&filter[filter_word(h, fmask)], filter_bits(h));
+}
+
 // ------------------------------------------------------------------------------------------
 // Probe: multi-match substring selection + bucket lookup (Sec. 4.2, Algorithm 2)
 // ------------------------------------------------------------------------------------------
@@ -522,9 +534,12 @@ __global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restri
 // One thread per (probe string x, probed length l, slot i).  The thread walks the window
 // [bot_i, top_i] with a rolling hash of x[p, l_i], looks each substring up, trims the list to
 // the members visited before x (self-join, l == |x|), and appends non-empty lookups as hits.
+constexpr int kProbeStage = 2048;    // bytes of probe strings a wave stages in LDS
+
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
 {
     __shared__ Hit s_hits[kWaves][kAppendCap];
+    __shared__ uint4 s_xs[kWaves][kProbeStage / 16];
     __shared__ uint16_t s_sym[256];
     s_sym[threadIdx.x] = P.sym.code[threadIdx.x];
     __syncthreads();
@@ -537,10 +552,37 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
     uint64_t my_sel = 0, my_cand = 0;
     // grid-stride over (probe string, length, slot) triples; the loop bound is block-uniform so
     // every lane takes part in the wave-level appends
+    using LdsU8 = const __attribute__((address_space(3))) uint8_t*;
+    const LdsU8 stage = (LdsU8)(s_xs[threadIdx.x >> 6]);
+    const uint64_t per = (uint64_t)P.nl * T1;
     for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock; t0 < nthreads;
          t0 += (uint64_t)gridDim.x * kBlock) {
         const uint64_t t = t0 + threadIdx.x;
         bool valid = t < nthreads;
+        // the wave's threads cover consecutive probe strings; when they are of one length and
+        // their padded bytes fit the stage, the wave copies them to LDS with 16-byte loads and
+        // every byte of the window walk below is read from there (wave-uniform decision)
+        const uint64_t tw = t0 + (threadIdx.x & ~63u);
+        uint32_t g_first = 0;
+        bool staged = false;
+        if (tw < nthreads) {
+            const uint64_t tl = min(tw + 63, nthreads - 1);
+            g_first = P.g_begin + (uint32_t)(tw / per);
+            const uint32_t g_last = P.g_begin + (uint32_t)(tl / per);
+            const int n0 = P.x_slen[g_first];
+            const int64_t bytes = (int64_t)(g_last - g_first + 1) * stride_of(n0);
+            if (P.x_slen[g_last] == n0 && bytes <= kProbeStage) {
+                staged = true;
+                const uint4* src = reinterpret_cast<const uint4*>(
+                    P.x_arena + P.x_gbase[n0] + (int64_t)(g_first - P.x_lenstart[n0]) * stride_of(n0));
+                // the previous iteration's reads of the stage were issued before these writes,
+                // and a wave's LDS requests complete in order
+                for (int q = lane; q < (int)(bytes >> 4); q += 64) s_xs[threadIdx.x >> 6][q] = src[q];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
         int n = 0, l = 0, i = 0, lo = 1, hi = 0, tau = P.tau;
         uint32_t gx = 0;
         Seg sg{1, 0};
@@ -548,8 +590,9 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         const uint4* table = P.table;
         const uint32_t* vals = P.vals;
         uint64_t mask = P.mask;
+        const uint32_t* filter = P.filter;
+        uint32_t fmask = P.filter_mask;
         if (valid) {
-            const uint64_t per = (uint64_t)P.nl * T1;
             gx = P.g_begin + (uint32_t)(t / per);
             const uint32_t rem = (uint32_t)(t % per);
             i = (int)(rem % T1) + 1;
@@ -562,6 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
                 table = ref.table;
                 vals = ref.vals;
                 mask = ref.mask;
+                filter = ref.filter;
+                fmask = ref.filter_mask;
                 dv.d = (uint32_t)(tau + 1);
                 dv.m = ref.div_m;
             }
@@ -584,6 +629,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
             if (valid)
                 x = P.x_arena + P.x_gbase[n] + (int64_t)(gx - P.x_lenstart[n]) * stride_of(n);
         }
+        const LdsU8 xs = stage + (int64_t)(gx - g_first) * stride_of(n);   // when staged
+        auto rd = [&](int k) -> uint8_t { return staged ? xs[k] : x[k]; };
         uint64_t h = 0, top = 0;
         if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
         // the window has at most tau+1 positions for multi-match, more for the other methods;
@@ -594,11 +641,22 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
             if (__ballot(active) == 0) break;
             uint32_t start = 0, count = 0;
             if (active) {
-                const uint8_t* w = x + p - 1;
-                if (s == 0) h = seg_code(w, sg.len, s_sym, sym_bits, exact_len);
-                else h = roll_code(h, sg.len, w[-1], w[sg.len - 1], top, s_sym, sym_bits, exact_len);
+                const int w0 = p - 1;
+                if (s == 0) {
+                    h = 0;
+                    if (sg.len <= exact_len)
+                        for (int k = 0; k < sg.len; ++k) h = (h << sym_bits) | (uint64_t)s_sym[rd(w0 + k)];
+                    else
+                        for (int k = 0; k < sg.len; ++k) h = h * kHashBase + (uint64_t)rd(w0 + k) + 1ull;
+                } else {
+                    h = roll_code(h, sg.len, rd(w0 - 1), rd(w0 + sg.len - 1), top, s_sym, sym_bits,
+                                  exact_len);
+                }
                 const uint64_t key = make_key(l, i, tau, sg.len, h, exact_len);
-                if (table_lookup(table, mask, key, &start, &count)) {
+                // hashed (long) segments rarely match: the filter, small enough for L2, turns
+                // most of those lookups away before the table read
+                const bool maybe = !(filter && sg.len > exact_len) || filter_has(filter, fmask, key);
+                if (maybe && table_lookup(table, mask, key, &start, &count)) {
                     if (P.self && l == n) {
                         // keep members with g < gx (lists are ascending in g)
                         uint32_t a = 0, b = count;
@@ -1782,6 +1840,15 @@ hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid,
     if (E <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_runstart, dim3(blocks_for(E)), dim3(kBlock), 0, s, flags, runid, E,
                        runstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_keys(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                              uint32_t* filter, uint32_t filter_mask, hipStream_t s)
+{
+    if (nruns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter_keys, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, keys, runstart,
+                       nruns, filter, filter_mask);
     return hipGetLastError();
 }
 

@@ -161,6 +161,20 @@ __device__ inline uint64_t make_key(int l, int i, int tau, int len, uint64_t cod
 
 __device__ inline uint64_t table_slot(uint64_t key) { return mix64(key ^ 0x5851F42D4C957F2Dull); }
 
+// Key filter: two bits of one 32-bit word per key, all from the slot hash's bits 30.. (the
+// table uses the low bits); fmask + 1 = bits in the filter, a multiple of 32.
+__device__ inline uint32_t filter_word(uint64_t h, uint32_t fmask) { return (uint32_t)(h >> 45) & (fmask >> 5); }
+__device__ inline uint32_t filter_bits(uint64_t h)
+{
+    return (1u << ((uint32_t)(h >> 35) & 31u)) | (1u << ((uint32_t)(h >> 30) & 31u));
+}
+__device__ inline bool filter_has(const uint32_t* __restrict__ filter, uint32_t fmask, uint64_t key)
+{
+    const uint64_t h = table_slot(key);
+    const uint32_t b = filter_bits(h);
+    return (filter[filter_word(h, fmask)] & b) == b;
+}
+
 __device__ inline bool table_lookup(const uint4* __restrict__ table, uint64_t mask, uint64_t key,
                                     uint32_t* start, uint32_t* count)
 {

@@ -460,6 +460,17 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     hip_check(launch_clear_table(X.table, slots, st), "clear_table");
     hip_check(launch_insert_runs(keys, runstart, nruns, (uint32_t)E, X.table, X.mask, st),
               "insert_runs");
+    if (X.sym.exact_len < kLenMax) {
+        // key filter for hashed segments: 8 bits per list, 2^16 .. 2^24 bits (2 MB, which stays
+        // in an XCD's 4 MB L2)
+        uint64_t fbits = 1ull << 16;
+        while (fbits < 8ull * nruns && fbits < (1ull << 24)) fbits <<= 1;
+        X.filter_mask = (uint32_t)(fbits - 1);
+        X.filter = (uint32_t*)A.get(nm("filter").c_str(), (size_t)(fbits / 8));
+        hip_check(hipMemsetAsync(X.filter, 0, (size_t)(fbits / 8), st), "memset filter");
+        hip_check(launch_filter_keys(keys, runstart, nruns, X.filter, X.filter_mask, st),
+                  "filter keys");
+    }
     if (with_share) {
         // content order of every list (shared-prefix verification, Sec. 5.3): entries sorted by
         // (key, first 8 bytes of the string, g) -- by the bytes first, then stably by the key
@@ -557,6 +568,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         if (spec.X) {
             pp.keys = spec.X->keys; pp.vals = spec.X->vals; pp.table = spec.X->table;
             pp.mask = spec.X->mask;
+            pp.filter = spec.X->filter;
+            pp.filter_mask = spec.X->filter_mask;
         }
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;

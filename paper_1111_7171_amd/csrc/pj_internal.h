@@ -64,6 +64,11 @@ struct DevIndex {
     uint32_t* vals = nullptr;           // [entries] sorted position g of the string
     uint4* table = nullptr;             // [mask + 1] {key lo, key hi, start, count}
     uint64_t mask = 0;
+    // membership filter of the keys: bit (slot hash >> 40) & filter_mask is set for every key,
+    // so a clear bit proves a key absent without reading the table (long, hashed segments rarely
+    // match, and the table is far larger than an XCD's L2 while the filter is not)
+    uint32_t* filter = nullptr;         // [(filter_mask + 1) / 32]
+    uint32_t filter_mask = 0;
     // inline copies of the members' strings in index order (strings of at most kInlineMaxLen
     // bytes; nullptr otherwise): entry j of length l at inl + inl_base[l] + j * stride_of(l)
     uint8_t* inl = nullptr;
@@ -83,6 +88,8 @@ struct IndexRef {
     uint64_t mask;
     uint32_t div_m;     // ceil(2^21 / (tau + 1)), see Div
     uint32_t present;   // 1 if an index for this tau exists
+    const uint32_t* filter;   // DevIndex::filter / filter_mask
+    uint32_t filter_mask;
 };
 
 // One selected substring that found a non-empty list: candidates (vals[start + m], x, i, p).
@@ -106,6 +113,7 @@ struct ProbeParams {
     // index side
     const int32_t* y_lenstart;  // to know which lengths are present
     const uint64_t* keys; const uint32_t* vals; const uint4* table; uint64_t mask;
+    const uint32_t* filter; uint32_t filter_mask;   // key filter (nullptr: none)
     int tau;                    // uniform tau, or the largest tau of a mixed batch
     int ymin, ymax;             // indexed lengths present
     // output
@@ -170,6 +178,9 @@ hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid,
 hipError_t launch_clear_table(uint4* table, uint64_t slots, hipStream_t s);
 hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
                               uint32_t E, uint4* table, uint64_t mask, hipStream_t s);
+// sets the filter bit of every list's key (filter zeroed by the caller)
+hipError_t launch_filter_keys(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                              uint32_t* filter, uint32_t filter_mask, hipStream_t s);
 hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
