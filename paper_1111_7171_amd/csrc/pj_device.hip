@@ -898,6 +898,18 @@ __device__ inline int vsp_dispatch(P r, int lr, P s, int ls, int t, int* cells)
         default: return vsp_fast<9>(r, lr, s, ls, t, cells);
         }
     }
+    // wider uniform thresholds (long strings, tau up to 32): a class of at most 3 extra columns
+    if constexpr (GMAXW > 9 && GMAXW <= 33) {
+        if (__ballot(t != t0) == 0) {
+            if (t0 + 1 <= 13) return vsp_fast<13>(r, lr, s, ls, t, cells);
+            if constexpr (GMAXW > 17) {
+                if (t0 + 1 <= 17) return vsp_fast<17>(r, lr, s, ls, t, cells);
+                if (t0 + 1 <= 21) return vsp_fast<21>(r, lr, s, ls, t, cells);
+                if (t0 + 1 <= 25) return vsp_fast<25>(r, lr, s, ls, t, cells);
+                if (t0 + 1 <= 29) return vsp_fast<29>(r, lr, s, ls, t, cells);
+            }
+        }
+    }
     return vsp_fast<GMAXW>(r, lr, s, ls, t, cells);
 }
 
@@ -1642,6 +1654,378 @@ __global__ __launch_bounds__(kBlock) void k_run_lengths(const uint32_t* __restri
     runlen[st] = ((r + 1 < nruns) ? runstart[r + 1] : E) - st;
 }
 
+// ------------------------------------------------------------------------------------------
+// Long-string verification by row blocks.  A candidate's part DP runs for hundreds of rows
+// when it passes and stops after a few when it does not, so 64 candidates in lockstep leave
+// most lanes idle.  Here the candidates of the small lists are materialised in slot order (one
+// (tau_l, tau_r) per slot, so a wave's 64 tasks share the band width class), and the DPs run in
+// passes: a pass takes up to K rows of every live task, and the tasks still running after them
+// go, with their band row (values min(M, t+1) in bytes: min(., t+1) commutes with the
+// recurrence and every decision compares with t), to a compacted queue for the next pass.
+// Left parts run first; candidates whose left part passes become right-part tasks (Algorithm
+// 3 examines right parts only after the left parts pass).  A pass stages its rows' characters
+// in LDS first, so the row loop reads no global memory.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kContMaxRows = 64;     // rows of one pass (at most)
+constexpr int kContW = 33;           // widest band class
+// 16-byte blocks staged per lane and pass: A needs K + 15 bytes, B up to kContW + K + 15 + 15
+constexpr int kStageA = (kContMaxRows + 15 + 15) / 16;
+constexpr int kStageB = (kContW + kContMaxRows + 15 + 15) / 16;
+
+// A task: {gx, gy, meta, n} and the byte offsets of x and y in their arenas.
+struct LongRec {
+    uint4 a;        // gx, gy, meta (p, i, l), n = |x|
+    uint4 b;        // x offset (lo, hi), y offset (lo, hi)
+};
+// A task that continues: the task, the rows done, its band row as bytes.
+struct ContRec {
+    LongRec rec;
+    uint4 st[3];    // st[0].x = rows done; bytes 4 .. 4 + kContW - 1 = min(M[k], t + 1)
+};
+
+// per slot (i - 1): number of candidates of the small-list hits
+__global__ __launch_bounds__(kBlock) void k_long_slot_counts(const Hit* __restrict__ hits, uint64_t nh,
+                                                             uint32_t* __restrict__ slot_cnt)
+{
+    __shared__ uint32_t s_cnt[64];
+    if (threadIdx.x < 64) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < nh;
+         k += (uint64_t)gridDim.x * kBlock)
+        atomicAdd(&s_cnt[(hits[k].meta >> 11) & 63u], hits[k].count);
+    __syncthreads();
+    if (threadIdx.x < 64 && s_cnt[threadIdx.x]) atomicAdd(&slot_cnt[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// one wave: exclusive scan of the 64 slot counts into off[0..64], cursor = off
+__global__ void k_long_slot_offsets(const uint32_t* __restrict__ slot_cnt, uint32_t* __restrict__ off,
+                                    uint32_t* __restrict__ cursor)
+{
+    const int lane = threadIdx.x;
+    const uint32_t c = slot_cnt[lane];
+    const uint32_t incl = wave_incl_scan(c);
+    off[lane] = incl - c;
+    cursor[lane] = incl - c;
+    if (lane == 63) off[64] = incl;
+}
+
+// Candidates of the small-list hits to their slots' regions.  A block walks a contiguous range
+// of hits twice: first counting its candidates per slot in LDS, then, after reserving each
+// slot's share with one global atomic, writing them (a global atomic per hit on the 64 slot
+// cursors would serialise).
+__global__ __launch_bounds__(kBlock) void k_long_scatter(const Hit* __restrict__ hits, uint64_t nh,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const uint16_t* __restrict__ x_slen,
+                                                         const int32_t* __restrict__ x_lenstart,
+                                                         const int64_t* __restrict__ x_gbase,
+                                                         const int32_t* __restrict__ y_lenstart,
+                                                         const int64_t* __restrict__ y_gbase,
+                                                         uint32_t* __restrict__ cursor,
+                                                         LongRec* __restrict__ cands)
+{
+    __shared__ uint32_t s_cnt[64];
+    __shared__ uint32_t s_pos[64];
+    const uint64_t per = (nh + gridDim.x - 1) / gridDim.x;
+    const uint64_t h0 = (uint64_t)blockIdx.x * per;
+    const uint64_t h1 = min(h0 + per, nh);
+    if (threadIdx.x < 64) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t k = h0 + threadIdx.x; k < h1; k += kBlock) {
+        const Hit h = hits[k];
+        atomicAdd(&s_cnt[(h.meta >> 11) & 63u], h.count);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64)
+        s_pos[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], s_cnt[threadIdx.x]) : 0u;
+    __syncthreads();
+    for (uint64_t k = h0 + threadIdx.x; k < h1; k += kBlock) {
+        const Hit h = hits[k];
+        const int n = x_slen[h.gx];
+        const int l = (int)(h.meta >> 17);
+        const uint64_t xo = (uint64_t)(x_gbase[n] + (int64_t)(h.gx - x_lenstart[n]) * stride_of(n));
+        const uint32_t base = atomicAdd(&s_pos[(h.meta >> 11) & 63u], h.count);
+        for (uint32_t m = 0; m < h.count; ++m) {
+            const uint32_t gy = vals[h.start + m];
+            const uint64_t yo = (uint64_t)(y_gbase[l] + (int64_t)(gy - y_lenstart[l]) * stride_of(l));
+            LongRec r;
+            r.a = make_uint4(h.gx, gy, h.meta, (uint32_t)n);
+            r.b = make_uint4((uint32_t)xo, (uint32_t)(xo >> 32), (uint32_t)yo, (uint32_t)(yo >> 32));
+            cands[base + m] = r;
+        }
+    }
+}
+
+// The tasks [b0, b1) of one slot for one wave (one task per lane): up to K rows of each task's
+// part DP on M values in diagonal coordinates (band index k holds column j = i - a + k of row i;
+// up = index k + 1, left = k - 1 of this row, diagonal = k; cells outside the band or left of
+// column 0 start large and only see large inputs, so column 0 follows from the recurrence;
+// indices right of column nc never feed a cell inside the matrix).  The expected distance of
+// index k is M + |b - k| (b = a + Delta, the final cell's index); a row whose smallest one
+// exceeds t stops the DP (Lemma 4).  The characters come from the lane's LDS stage (element q at
+// stage[q * 64]): A[row + q] for q < kContMaxRows, then B[row - a + q] (256 outside B).
+template <int MAXW>
+__device__ inline void cont_chunk(const VerifyParams& V, const Div& div, int side, int slot,
+                                  bool fresh, const LongRec* __restrict__ fin,
+                                  const ContRec* __restrict__ cin, uint32_t b0, uint32_t b1, int K,
+                                  ContRec* __restrict__ cout, uint32_t* __restrict__ cout_cnt,
+                                  LongRec* __restrict__ rout, uint32_t* __restrict__ rout_cnt,
+                                  uint32_t qbase,
+                                  __attribute__((address_space(3))) uint32_t* stage32,
+                                  WaveAppender<uint64_t, kAppendCap>& acc, uint64_t& my_cells,
+                                  uint64_t& my_miss)
+{
+    constexpr int BIG = 1 << 20;
+    const int lane = threadIdx.x & 63;
+    // the lane's 16-byte blocks: block q at byte (q * 64 + lane) * 16 of the wave's stage
+    const __attribute__((address_space(3))) uint8_t* stage8 =
+        (const __attribute__((address_space(3))) uint8_t*)stage32;
+    const int i = slot + 1;
+    const int t = side == 0 ? i - 1 : V.tau + 1 - i;
+    const uint32_t k = b0 + (uint32_t)lane;
+    bool act = k < b1;
+    LongRec rec;
+    rec.a = make_uint4(0u, 0u, 0u, 0u);
+    rec.b = rec.a;
+    int M[MAXW];
+    int row = 0, nr = 0, nc = 0, a = 0, b = 0, st = 0;    // st: 0 running, 1 pass, 2 fail, 3 none
+    const uint8_t* A = nullptr;
+    const uint8_t* B = nullptr;
+    const uint8_t* A_end = nullptr;     // end of the padded slot of A's / B's string
+    const uint8_t* B_end = nullptr;
+    if (act) {
+        ContRec cr;
+        if (fresh) rec = fin[k];
+        else { cr = cin[k]; rec = cr.rec; }
+        const uint32_t meta = rec.a.z;
+        const int p = (int)(meta & 2047u) + 1;
+        const int l = (int)(meta >> 17);
+        const int n = (int)rec.a.w;
+        const uint8_t* x = V.x_arena + ((uint64_t)rec.b.y << 32 | rec.b.x);
+        const uint8_t* y = V.y_arena + ((uint64_t)rec.b.w << 32 | rec.b.z);
+        const Seg sg = partition_seg(l, i, V.tau, div);
+        const uint8_t* r = side == 0 ? y : y + sg.p - 1 + sg.len;
+        const uint8_t* s = side == 0 ? x : x + p - 1 + sg.len;
+        const int lr = side == 0 ? sg.p - 1 : l - (sg.p - 1 + sg.len);
+        const int ls = side == 0 ? p - 1 : n - (p - 1 + sg.len);
+        const uint8_t* yend = y + stride_of(l);
+        const uint8_t* xend = x + stride_of(n);
+        if (lr <= ls) { A = r; nr = lr; B = s; nc = ls; A_end = yend; B_end = xend; }
+        else          { A = s; nr = ls; B = r; nc = lr; A_end = xend; B_end = yend; }
+        const int delta = nc - nr;
+        a = (t - delta) >> 1;
+        b = (t + delta) >> 1;
+        if (fresh) {
+            bool ok = true;
+            if (side == 0 && sg.len > V.exact_len) {
+                for (int q = 0; q < sg.len; ++q) ok &= (x[p - 1 + q] == y[sg.p - 1 + q]);
+                if (!ok) my_miss += 1;
+            }
+            if (!ok) st = 3;                               // not a candidate
+            else if (delta > t) st = 2;                    // no row
+            else if (nr == 0) st = (nc <= t) ? 1 : 2;
+#pragma unroll
+            for (int q = 0; q < MAXW; ++q) {
+                const int j = q - a;
+                M[q] = (j >= 0 && j <= min(nc, b)) ? j : BIG;
+            }
+        } else {
+            row = (int)cr.st[0].x;
+            const uint32_t wv[12] = {cr.st[0].x, cr.st[0].y, cr.st[0].z, cr.st[0].w,
+                                     cr.st[1].x, cr.st[1].y, cr.st[1].z, cr.st[1].w,
+                                     cr.st[2].x, cr.st[2].y, cr.st[2].z, cr.st[2].w};
+#pragma unroll
+            for (int q = 0; q < MAXW; ++q) M[q] = (int)((wv[1 + q / 4] >> (8 * (q % 4))) & 255u);
+        }
+    }
+    // the pass's rows in sub-blocks of kContMaxRows: each stages its characters (the 16-byte
+    // blocks holding A[row .. row + 64) and B[max(row - a, 0) .. row - a + MAXW + 64), each block
+    // only if it starts inside its string's padded slot, 16-byte aligned; all loads are issued
+    // before the first LDS write) and runs its rows
+    const bool run = act && st == 0;
+    bool running = run;
+    for (int sub = 0; sub < K; sub += kContMaxRows) {
+        if (__ballot(running) == 0) break;
+        const int Ks = min(kContMaxRows, K - sub);
+        int oA = 0, oB = 0, ib0 = 0;
+        // the previous sub-block's LDS reads were issued before these writes (in order)
+        if (running) {
+            const uint8_t* pa = A + row;
+            const uint8_t* pa0 = (const uint8_t*)((uintptr_t)pa & ~(uintptr_t)15);
+            oA = (int)(pa - pa0);
+            ib0 = max(row - a, 0);
+            const uint8_t* pb = B + ib0;
+            const uint8_t* pb0 = (const uint8_t*)((uintptr_t)pb & ~(uintptr_t)15);
+            oB = (int)(pb - pb0);
+            uint4 va[kStageA], vb[kStageB];
+#pragma unroll
+            for (int q = 0; q < kStageA; ++q)
+                va[q] = (pa0 + 16 * q < A_end) ? reinterpret_cast<const uint4*>(pa0)[q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int q = 0; q < kStageB; ++q)
+                vb[q] = (pb0 + 16 * q < B_end) ? reinterpret_cast<const uint4*>(pb0)[q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int q = 0; q < kStageA; ++q) {
+                stage32[q * 256 + 0] = va[q].x; stage32[q * 256 + 1] = va[q].y;
+                stage32[q * 256 + 2] = va[q].z; stage32[q * 256 + 3] = va[q].w;
+            }
+#pragma unroll
+            for (int q = 0; q < kStageB; ++q) {
+                const int o = (kStageA + q) * 256;
+                stage32[o + 0] = vb[q].x; stage32[o + 1] = vb[q].y;
+                stage32[o + 2] = vb[q].z; stage32[o + 3] = vb[q].w;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (running) {
+            // byte q of the lane's A blocks / B blocks (lane-interleaved 16-byte blocks)
+            auto sa = [&](int q) -> int { return (int)stage8[((q >> 4) * 64) * 16 + (q & 15)]; };
+            auto sb = [&](int ib) -> int {             // B[ib], 256 outside B
+                const int q = oB + ib - ib0;
+                return ((unsigned)ib < (unsigned)nc)
+                           ? (int)stage8[((kStageA + (q >> 4)) * 64) * 16 + (q & 15)] : 256;
+            };
+            int w[MAXW];
+#pragma unroll
+            for (int q = 0; q < MAXW; ++q) w[q] = sb(row - a + q);
+            const int rowstart = row;
+            for (int r = 0; r < Ks && row < nr; ++r) {
+                const int ai = sa(oA + r);
+                int left = BIG, emin = BIG;
+#pragma unroll
+                for (int q = 0; q < MAXW; ++q) {
+                    const int up = (q + 1 < MAXW) ? M[(q + 1) < MAXW ? q + 1 : q] : BIG;
+                    const int dg = M[q] + ((ai != w[q]) ? 1 : 0);
+                    const int v = min(min(up, left) + 1, dg);
+                    M[q] = v;
+                    left = v;
+                    const uint32_t ub = (uint32_t)b, uq = (uint32_t)q;
+                    emin = min(emin, (int)(max(ub, uq) - min(ub, uq) + (uint32_t)v));
+                }
+                row = rowstart + r + 1;
+                if (emin > t) { st = 2; break; }
+                if (row == nr) {
+                    int out = BIG;
+#pragma unroll
+                    for (int q = 0; q < MAXW; ++q) out = (q == b) ? M[q] : out;
+                    st = out <= t ? 1 : 2;
+                    break;
+                }
+#pragma unroll
+                for (int q = 0; q + 1 < MAXW; ++q) w[q] = w[q + 1];
+                w[MAXW - 1] = sb(rowstart - a + MAXW + r);
+            }
+            running = st == 0;
+        }
+    }
+    if (run && (st == 1 || st == 2)) my_cells += (uint64_t)band_cells(row, nc, a, b);
+    // outcomes
+    const bool cont = run && st == 0;
+    {
+        const uint64_t m = __ballot(cont);
+        if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&cout_cnt[slot], (uint32_t)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (cont) {
+                ContRec c;
+                c.rec = rec;
+                uint32_t wds[12];
+                wds[0] = (uint32_t)row;
+#pragma unroll
+                for (int q = 1; q < 12; ++q) wds[q] = 0;
+#pragma unroll
+                for (int q = 0; q < MAXW; ++q) {
+                    const uint32_t v = (uint32_t)min(M[q], t + 1);
+                    wds[1 + q / 4] |= v << (8 * (q % 4));
+                }
+                c.st[0] = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+                c.st[1] = make_uint4(wds[4], wds[5], wds[6], wds[7]);
+                c.st[2] = make_uint4(wds[8], wds[9], wds[10], wds[11]);
+                cout[qbase + base + (uint32_t)__popcll(m & lanemask_lt())] = c;
+            }
+        }
+    }
+    if (side == 0) {
+        const bool pass = act && st == 1;
+        const uint64_t m = __ballot(pass);
+        if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&rout_cnt[slot], (uint32_t)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (pass) rout[qbase + base + (uint32_t)__popcll(m & lanemask_lt())] = rec;
+        }
+    } else {
+        acc.push(act && st == 1, ((uint64_t)rec.a.x << 32) | rec.a.y, V.out, V.out_cap,
+                 &V.counters[3]);
+    }
+}
+
+// One pass over the tasks of every slot: fresh tasks (fin, counts cnt) or continuing ones (cin,
+// counts cnt); continuing tasks go to cout (counts cout_cnt); side 0's passing tasks to rout
+// (counts rout_cnt).  Regions of every queue start at off[slot].
+__global__ __launch_bounds__(64) void k_verify_cont(VerifyParams V, Div div, int side, int fresh,
+                                                    int K, const LongRec* __restrict__ fin,
+                                                    const ContRec* __restrict__ cin,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ off,
+                                                    ContRec* __restrict__ cout,
+                                                    uint32_t* __restrict__ cout_cnt,
+                                                    LongRec* __restrict__ rout,
+                                                    uint32_t* __restrict__ rout_cnt,
+                                                    uint32_t* __restrict__ zero_cnt)
+{
+    // the counts the next pass writes: read by the previous pass only, so clear now
+    if (blockIdx.x == 0 && zero_cnt) zero_cnt[threadIdx.x] = 0u;
+    __shared__ uint64_t s_acc[kAppendCap];
+    __shared__ uint4 s_stage[(kStageA + kStageB) * 64];
+    WaveAppender<uint64_t, kAppendCap> acc{s_acc, 0};
+    const int lane = threadIdx.x & 63;
+    __attribute__((address_space(3))) uint32_t* stage =
+        (__attribute__((address_space(3))) uint32_t*)s_stage + 4 * lane;
+    uint64_t my_cells = 0, my_miss = 0;
+    const uint32_t c = lane <= V.tau ? cnt[lane] : 0u;
+    const uint32_t nch = (c + 63u) / 64u;
+    const uint32_t incl = wave_incl_scan(nch);
+    const uint32_t total = __shfl(incl, 63, 64);
+    for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+        const int slot = __popcll(__ballot(incl <= ch));
+        const uint32_t first = __shfl(incl - nch, slot, 64);
+        const uint32_t cs = __shfl(c, slot, 64);
+        const uint32_t base = off[slot];
+        const uint32_t b0 = (ch - first) * 64u;
+        const uint32_t b1 = min(b0 + 64u, cs);
+        const int t = side == 0 ? slot : V.tau - slot;
+        const LongRec* fi = fin ? fin + base : nullptr;
+        const ContRec* ci = cin ? cin + base : nullptr;
+#define PJ_CONT(W) cont_chunk<W>(V, div, side, slot, fresh != 0, fi, ci, b0, b1, K, cout,        \
+                                 cout_cnt, rout, rout_cnt, base, stage, acc, my_cells, my_miss)
+        if (t + 1 <= 5) PJ_CONT(5);
+        else if (t + 1 <= 9) PJ_CONT(9);
+        else if (t + 1 <= 13) PJ_CONT(13);
+        else if (t + 1 <= 17) PJ_CONT(17);
+        else if (t + 1 <= 21) PJ_CONT(21);
+        else if (t + 1 <= 25) PJ_CONT(25);
+        else if (t + 1 <= 29) PJ_CONT(29);
+        else PJ_CONT(33);
+#undef PJ_CONT
+    }
+    if (side == 1) acc.flush(V.out, V.out_cap, &V.counters[3]);
+    my_cells = wave_sum(my_cells);
+    my_miss = wave_sum(my_miss);
+    if (lane == 0) {
+        if (my_cells) atomicAdd(&V.counters[4], (unsigned long long)my_cells);
+        if (my_miss) atomicAdd(&V.counters[5], (unsigned long long)my_miss);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t v)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = v;
+}
+
 template <int MAXW>
 __global__ __launch_bounds__(kBlock) void k_short(const uint8_t* __restrict__ x_arena,
                                                   const uint16_t* __restrict__ x_slen,
@@ -2056,6 +2440,71 @@ hipError_t launch_run_lengths(const uint32_t* runstart, uint32_t nruns, uint32_t
     if (nruns == 0) return hipSuccess;
     hipLaunchKernelGGL(k_run_lengths, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, runstart,
                        nruns, E, runlen);
+    return hipGetLastError();
+}
+
+size_t long_scratch_bytes(uint64_t ncand)
+{
+    const uint64_t rc = (ncand * sizeof(LongRec) + 255) & ~(uint64_t)255;
+    const uint64_t cc = (ncand * sizeof(ContRec) + 255) & ~(uint64_t)255;
+    // counts: slot, offsets, cursor, right, three continuation counts (256 u32 each);
+    // candidates, right tasks, two continuation queues
+    return 7 * 256 * sizeof(uint32_t) + 2 * rc + 2 * cc;
+}
+
+hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_rows, void* scratch,
+                              int grid, hipStream_t s)
+{
+    if (V.nhits == 0 || ncand == 0) return hipSuccess;
+    if (V.tau + 1 > kContW || grid < 1 || V.q_tau || max_rows < 0) return hipErrorInvalidValue;
+    uint8_t* p = (uint8_t*)scratch;
+    uint32_t* slot_cnt = (uint32_t*)p;
+    uint32_t* off = slot_cnt + 256;
+    uint32_t* cursor = off + 256;
+    uint32_t* right_cnt = cursor + 256;
+    uint32_t* cont_cnt[3] = {right_cnt + 256, right_cnt + 512, right_cnt + 768};
+    const uint64_t rc = (ncand * sizeof(LongRec) + 255) & ~(uint64_t)255;
+    const uint64_t cc = (ncand * sizeof(ContRec) + 255) & ~(uint64_t)255;
+    uint8_t* q = p + 7 * 256 * sizeof(uint32_t);
+    LongRec* cands = (LongRec*)q;
+    LongRec* right = (LongRec*)(q + rc);
+    ContRec* cont[2] = {(ContRec*)(q + 2 * rc), (ContRec*)(q + 2 * rc + cc)};
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, slot_cnt, 7 * 256, 0u);
+    const unsigned hb = (unsigned)std::min<uint64_t>(blocks_for(V.nhits), 4096);
+    hipLaunchKernelGGL(k_long_slot_counts, dim3(hb), dim3(kBlock), 0, s, V.hits, V.nhits, slot_cnt);
+    hipLaunchKernelGGL(k_long_slot_offsets, dim3(1), dim3(64), 0, s, slot_cnt, off, cursor);
+    hipLaunchKernelGGL(k_long_scatter, dim3(hb), dim3(kBlock), 0, s, V.hits,
+                       V.nhits, V.vals, V.x_slen, V.x_lenstart, V.x_gbase, V.y_lenstart,
+                       V.y_gbase, cursor, cands);
+    const Div div = make_div(V.tau + 1);
+    // three count buffers in rotation: pass j reads cnt[j % 3], writes cnt[(j + 1) % 3] and
+    // clears cnt[(j + 2) % 3] (read by pass j - 1); the first two start cleared
+    for (int side = 0; side < 2; ++side) {
+        // pass lengths 16, 16, 32, 64, ..., 512 rows until every part's rows are covered
+        int done = 0, pass = 0;
+        while (true) {
+            const int K = pass == 0 ? 16 : std::min(512, 16 << (pass - 1));
+            const bool fresh = pass == 0;
+            uint32_t* cin_cnt = cont_cnt[pass % 3];
+            uint32_t* cout_cnt = cont_cnt[(pass + 1) % 3];
+            uint32_t* zero = cont_cnt[(pass + 2) % 3];
+            hipLaunchKernelGGL(k_verify_cont, dim3(grid), dim3(64), 0, s, V, div, side,
+                               fresh ? 1 : 0, K,
+                               fresh ? (side == 0 ? (const LongRec*)cands : (const LongRec*)right)
+                                     : (const LongRec*)nullptr,
+                               fresh ? (const ContRec*)nullptr : (const ContRec*)cont[pass % 2],
+                               (const uint32_t*)(fresh ? (side == 0 ? slot_cnt : right_cnt)
+                                                       : cin_cnt),
+                               (const uint32_t*)off, cont[(pass + 1) % 2], cout_cnt, right,
+                               right_cnt, zero);
+            done += K;
+            ++pass;
+            if (done >= max_rows) break;
+        }
+        // the next side starts with its first two count buffers cleared: the last pass left
+        // cnt[pass % 3] (written, now drained to zero tasks) and cleared cnt[(pass + 1) % 3]
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, cont_cnt[0], 3 * 256, 0u);
+    }
     return hipGetLastError();
 }
 

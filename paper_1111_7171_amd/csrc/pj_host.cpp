@@ -706,8 +706,20 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.out = J.out; vp.out_cap = cap;
             vp.counters = J.counters;
             int k0 = tm.mark();
+            // long strings: verification by row blocks with compacted continuation queues
+            bool long_path = batched && ncand_small > 0 && Y.lmax > kLongMinLen &&
+                             tau + 1 <= kLongMaxW && !spec.q_tau && ncand_small <= (1ull << 24);
+            // tests force either verification of long strings (it changes no result)
+            if (const char* e = getenv("PJ_LONG_VERIFY")) long_path = long_path && atoi(e) != 0;
+            if (long_path) {
+                void* lsc = W.get("join.long", long_scratch_bytes(ncand_small));
+                vp.nhits = nsmall;
+                hip_check(launch_verify_long(vp, ncand_small, std::max(P.lmax, Y.lmax), lsc,
+                                             device_cus() * 8, st), "verify_long");
+                stats.verify_launches += 1;
+            }
             if (batched) {
-                if (ncand_small > 0) {
+                if (ncand_small > 0 && !long_path) {
                     // at least ~32 wave chunks per CU before a wave takes more than one round
                     // of 64 candidates: a few long candidates (long strings, high tau) then
                     // still spread over the whole device

@@ -225,6 +225,16 @@ hipError_t launch_gather_vals(const uint32_t* vals, const uint32_t* idx, int64_t
 hipError_t launch_run_lengths(const uint32_t* runstart, uint32_t nruns, uint32_t E,
                               uint32_t* runlen, hipStream_t s);
 hipError_t launch_verify_batched(const VerifyParams& V, uint32_t* first, int grid, hipStream_t s);
+// long-string verification of the small-list hits (V.hits[0 .. V.nhits), ncand candidates,
+// uniform tau + 1 <= kLongMaxW, no per-query tau) by row blocks: candidates in slot order, passes
+// of at most 64 rows per task, unfinished tasks compacted into the next pass's queue, left parts
+// before right parts.  max_rows bounds a part's rows (the longest string).  grid: blocks of one
+// wave.  scratch: long_scratch_bytes(ncand) bytes.
+constexpr int kLongMinLen = 128;
+constexpr int kLongMaxW = 33;
+size_t long_scratch_bytes(uint64_t ncand);
+hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_rows, void* scratch,
+                              int grid, hipStream_t s);
 // wave chunks of 64 * rounds candidates (rounds in [1, kBatchedRoundsMax])
 uint64_t batched_chunks(uint64_t ncand, int rounds);
 // A captured query batch: every size is read from device memory, so one instantiated graph

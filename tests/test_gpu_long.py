@@ -1,0 +1,50 @@
+"""Verification of long strings by row blocks (indexed strings longer than 128 bytes, tau <= 32):
+candidates in slot order, passes of at most 64 rows per task, unfinished tasks carried to the
+next pass with their band row.  Pairs, candidates and cells equal the oracle's, with the path on
+(the default for such strings) and off (PJ_LONG_VERIFY=0, the per-candidate kernel)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1111_7171_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _long_set(seed, n, tau, lmin=150, lmax=300):
+    rng = np.random.default_rng(seed)
+    return W.random_small(rng, n, alphabet=b"abcd", lmin=lmin, lmax=lmax, dup_frac=0.6,
+                          kmax=tau + 2)
+
+
+@pytest.mark.parametrize("tau", [3, 8, 13, 20, 27, 32])
+def test_long_self_join_matches_oracle(tau, monkeypatch):
+    col = _long_set(500 + tau, 500, tau)
+    _say(f"long strings tau={tau} n={col.n}")
+    exp = O.self_join_pj(col, tau)
+    for flag in ("1", "0"):
+        monkeypatch.setenv("PJ_LONG_VERIFY", flag)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        assert np.array_equal(got, exp.pairs), flag
+        assert st["candidates"] == exp.candidates and st["cells"] == exp.cells, flag
+    _say(f"  pairs {len(got)} candidates {exp.candidates} cells {exp.cells}")
+
+
+def test_long_join_and_row_passes(monkeypatch):
+    """Two sets, and strings long enough (up to 1,500 bytes) for many passes of 64 rows."""
+    R = _long_set(61, 120, 16, lmin=600, lmax=1500)
+    S = _long_set(62, 200, 16, lmin=600, lmax=1500)
+    S = W.concat([S, R.subset(np.arange(0, R.n, 3))])        # exact copies: full-length passes
+    for tau in (8, 16, 32):
+        exp = O.join_pj(R, S, tau)
+        monkeypatch.setenv("PJ_LONG_VERIFY", "1")
+        got = P.pj_join(R, S, tau)
+        st = P.pj_last_stats()
+        assert np.array_equal(got, exp.pairs), tau
+        assert st["candidates"] == exp.candidates and st["cells"] == exp.cells, tau
