@@ -48,3 +48,29 @@ def test_long_join_and_row_passes(monkeypatch):
         st = P.pj_last_stats()
         assert np.array_equal(got, exp.pairs), tau
         assert st["candidates"] == exp.candidates and st["cells"] == exp.cells, tau
+
+
+# library method -> oracle method
+_METHODS = {P.SELECT_MULTIMATCH: O.SEL_MULTIMATCH, P.SELECT_POSITION: O.SEL_POSITION,
+            P.SELECT_SHIFT: O.SEL_SHIFT, P.SELECT_LENGTH: O.SEL_LENGTH}
+
+
+@pytest.mark.parametrize("tau", [4, 16, 32])
+def test_long_strings_all_selection_methods(tau):
+    """Long strings, hashed and exact segment keys (4 symbols: segments of up to 13 bytes are
+    keyed exactly): the oracle's selected-substring, candidate and cell counts and pairs under
+    every selection method, for a self-join and a two-set join."""
+    col = _long_set(900 + tau, 300, tau, lmin=200, lmax=420)
+    for meth, ometh in _METHODS.items():
+        exp = O.self_join_pj(col, tau, method=ometh)
+        got = P.pj_self_join(col, tau, selection=meth)
+        st = P.pj_last_stats()
+        assert np.array_equal(got, exp.pairs), meth
+        assert (st["selected"], st["candidates"], st["cells"]) == \
+            (exp.selected, exp.candidates, exp.cells), meth
+    R = _long_set(950 + tau, 80, tau, lmin=200, lmax=420)
+    jexp = O.join_pj(R, col, tau)
+    jgot = P.pj_join(R, col, tau)
+    jst = P.pj_last_stats()
+    assert np.array_equal(jgot, jexp.pairs)
+    assert (jst["selected"], jst["candidates"]) == (jexp.selected, jexp.candidates)
