@@ -412,20 +412,22 @@ def main():
             "gcups": s["cells"] / max(s["ms_verify_kernel"], 1e-9) / 1e6,
         }
 
-    # end to end (host arrays in -> sorted host pairs out; PCIe copies included), outside the
-    # timed region: median of 3 per tau, beside the device-resident time of the timed steps
+    # end to end (host arrays in -> sorted host pairs out, as the C ABI returns them; PCIe
+    # copies included), outside the timed region: median of 3 per tau, beside the
+    # device-resident time of the timed steps
     end_to_end = {}
     if not args.window_bytes and not args.no_e2e:
         for t in taus:
-            runs = []
+            runs, m = [], 0
             for _ in range(3):
                 t0 = time.perf_counter()
-                hp = P.pj_self_join(col, t, mode=args.mode, tune_cache=cache,
-                                    selection=args.selection)
+                hp = P.pj_self_join_host(col, t, mode=args.mode, tune_cache=cache,
+                                         selection=args.selection)
                 runs.append((time.perf_counter() - t0) * 1e3)
-            end_to_end[str(t)] = {"ms": round(float(np.median(runs)), 3), "pairs": int(len(hp)),
+                m = hp.count
+                hp.free()
+            end_to_end[str(t)] = {"ms": round(float(np.median(runs)), 3), "pairs": m,
                                   "device_resident_ms": per_tau[str(t)]["ms"]}
-            del hp
             log(f"end to end tau={t}: {end_to_end[str(t)]}")
 
     sha = kernel_source_sha()

@@ -73,8 +73,10 @@ typedef struct {
 } pj_strings;
 
 /* Result pairs, owned by the caller.  a[k], b[k] are ids; the list is sorted by (a, b) and has
- * no duplicates.  on_device = 1 means a and b are device pointers (pj_options.outputs_on_device).
- * Release with pj_pairs_free. */
+ * no duplicates.  on_device tells where a and b live: 0 host memory (malloc), 1 device memory
+ * (pj_options.outputs_on_device), 2 page-locked host memory (hipHostMalloc; host results of a
+ * megabyte or more per array, which the device writes at the link's full rate).  Release with
+ * pj_pairs_free whatever the kind. */
 typedef struct {
     int64_t count;
     int32_t* a;

@@ -23,7 +23,7 @@ __all__ = [
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
     "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "MODE_SHARE_PREFIX", "PJ_TAU_MAX", "PJ_LEN_MAX",
     "Server", "Index",
-    "pj_tune", "pj_query_noalloc",
+    "pj_tune", "pj_query_noalloc", "pj_self_join_host", "HostPairs",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -268,6 +268,24 @@ def _hip_d2h(host: np.ndarray, dev_ptr: int):
         raise PassJoinError(PJ_EDEVICE, f"hipMemcpy failed ({rc})")
 
 
+class HostPairs:
+    """Result pairs left in the library's host memory (pj_self_join_host): a and b are numpy
+    views of the C arrays (no copy); call free() when done."""
+
+    def __init__(self, raw: PjPairs):
+        self.raw = raw
+        m = int(raw.count)
+        self.count = m
+        self.a = np.ctypeslib.as_array(C.cast(raw.a, C.POINTER(C.c_int32)), shape=(m,)) \
+            if m else np.empty(0, np.int32)
+        self.b = np.ctypeslib.as_array(C.cast(raw.b, C.POINTER(C.c_int32)), shape=(m,)) \
+            if m else np.empty(0, np.int32)
+
+    def free(self):
+        self.a = self.b = None
+        load().pj_pairs_free(C.byref(self.raw))
+
+
 def _take_pairs(raw: PjPairs, outputs_on_device: bool):
     if outputs_on_device:
         return DevicePairs(raw)
@@ -292,6 +310,21 @@ def pj_self_join(strings, tau: int, *, mode: int = MODE_AUTO, outputs_on_device:
     raw = PjPairs()
     _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
+
+
+def pj_self_join_host(strings, tau: int, *, mode: int = MODE_AUTO, mem_budget: int = 0,
+                      stream=None, tune_cache: str | None = None, selection: int = 0) -> HostPairs:
+    """pj_self_join of a host string set returning the library's host result arrays as they
+    are (HostPairs: numpy views of a and b, released by free()), without the copy into an
+    interleaved [m, 2] array."""
+    lib = load()
+    s = _Marshalled(strings)
+    if s.on_device:
+        raise PassJoinError(PJ_EINVAL, "pj_self_join_host takes host strings")
+    o = _options(False, False, mode, mem_budget, stream, tune_cache, selection)
+    raw = PjPairs()
+    _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
+    return HostPairs(raw)
 
 
 def pj_self_join_streamed(strings, tau: int, window_bytes: int, *, mode: int = MODE_AUTO,

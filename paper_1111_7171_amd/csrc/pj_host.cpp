@@ -24,6 +24,9 @@
 
 namespace pj {
 
+// Host results of at least this many bytes per array go to page-locked memory.
+constexpr size_t kPinnedOutputMin = 1u << 20;
+
 // Inverted lists with at least this many candidates are verified a 64-member segment per wave.
 // Below this many candidates the batched path verifies the hits in probe order, in one launch.
 constexpr uint64_t kBucketMinCandidates = 1ull << 20;
@@ -866,6 +869,24 @@ void emit_output(const int32_t* da, const int32_t* db, uint64_t M, bool to_devic
             hip_check(hipMemcpyAsync(pa, da, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, st), "out");
             hip_check(hipMemcpyAsync(pb, db, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, st), "out");
         }
+    } else if (bytes >= kPinnedOutputMin) {
+        // large results: page-locked host memory, allocated in place of pageable memory (fresh
+        // pageable pages cost a fault on first touch, more than the copy itself) and filled at
+        // the link's full rate
+        void *pa = nullptr, *pb = nullptr;
+        if (hipHostMalloc(&pa, bytes, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&pb, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            if (pa) (void)hipHostFree(pa);
+            throw Error(PJ_ENOMEM, "host output allocation failed");
+        }
+        out->on_device = 2;
+        out->a = (int32_t*)pa;
+        out->b = (int32_t*)pb;
+        if (M) {
+            hip_check(hipMemcpyAsync(pa, da, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "out");
+            hip_check(hipMemcpyAsync(pb, db, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st), "out");
+        }
     } else {
         out->a = (int32_t*)malloc(bytes);
         out->b = (int32_t*)malloc(bytes);
@@ -1105,13 +1126,21 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.shared_cells += t_stats.shared_cells;
         a = b + 1;
     }
-    // k-way merge of the windows' sorted runs straight into the output arrays
+    // k-way merge of the windows' sorted runs straight into the output arrays (one run: a copy)
     size_t m = 0;
     for (const auto& r : runs) m += r.size();
     out->on_device = 0;
     out->a = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     out->b = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     if (!out->a || !out->b) throw std::bad_alloc();
+    if (runs.size() == 1) {
+        const std::vector<uint64_t>& r = runs[0];
+        for (size_t k = 0; k < m; ++k) {
+            out->a[k] = (int32_t)(r[k] >> 32);
+            out->b[k] = (int32_t)(uint32_t)r[k];
+        }
+        runs.clear();
+    }
     using Head = std::pair<uint64_t, size_t>;          // (key, run)
     std::vector<Head> heap;
     std::vector<size_t> pos(runs.size(), 0);
@@ -1119,7 +1148,7 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         if (!runs[r].empty()) heap.emplace_back(runs[r][0], r);
     auto greater = [](const Head& x, const Head& y) { return x.first > y.first; };
     std::make_heap(heap.begin(), heap.end(), greater);
-    for (size_t k = 0; k < m; ++k) {
+    for (size_t k = 0; k < m && !runs.empty(); ++k) {
         std::pop_heap(heap.begin(), heap.end(), greater);
         const Head h = heap.back();
         heap.pop_back();
@@ -1176,7 +1205,10 @@ int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_opti
 void pj_pairs_free(pj_pairs* p)
 {
     if (!p) return;
-    if (p->on_device) {
+    if (p->on_device == 2) {
+        if (p->a) (void)hipHostFree(p->a);
+        if (p->b) (void)hipHostFree(p->b);
+    } else if (p->on_device) {
         if (p->a) (void)hipFree(p->a);
         if (p->b) (void)hipFree(p->b);
     } else {

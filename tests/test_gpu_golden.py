@@ -94,6 +94,32 @@ def test_self_join_full_size_matches_oracle(cfg, tau, tune_cache):
         assert O.ed_full(col.get(int(pairs[k, 0])), col.get(int(pairs[k, 1]))) <= tau
 
 
+def test_host_inputs_and_outputs_full_size():
+    """cfg2 at tau=4 with host arrays in and out: the 41.6 million pairs come back in the
+    library's page-locked result arrays (both through the interleaved copy and as the C arrays
+    themselves) and hash to the oracle's list."""
+    e = GOLD["cfg2"]["taus"]["4"]
+    col = _col(2)
+    pairs = P.pj_self_join(col, 4)
+    st = P.pj_last_stats()
+    assert len(pairs) == e["pairs"] and _sha(pairs) == e["pairs_sha256"]
+    _check_counts(st, e, "cfg2 tau=4 host in/out")
+    del pairs
+    hp = P.pj_self_join_host(col, 4)
+    try:
+        assert hp.raw.on_device == 2 and hp.count == e["pairs"]
+        assert _sha(np.stack([hp.a, hp.b], axis=1)) == e["pairs_sha256"]
+    finally:
+        hp.free()
+    # a small result stays in ordinary host memory
+    offs = np.ascontiguousarray(col.offsets[:2001])
+    small = P.pj_self_join_host((np.ascontiguousarray(col.chars[:int(offs[-1])]), offs), 1)
+    try:
+        assert small.raw.on_device == 0
+    finally:
+        small.free()
+
+
 @pytest.mark.parametrize("cfg,tau", [(2, 4), (3, 8)])
 def test_share_prefix_full_size_matches_oracle(cfg, tau):
     """The shared-prefix mode (Sec. 5.3) at full size: same pairs and counts as the oracle."""
