@@ -1181,8 +1181,11 @@ __device__ inline T uniform_load(const T* p)
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// The 40-byte class fits 8 blocks per CU in LDS; it is compiled for 8 waves per SIMD (at
+// most 64 VGPRs) to match.
 template <int GMAXW, int REGY, int NCT>
-__global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REGY == 40 ? 8 : 1)))
+void k_verify_segs(VerifyParams V, Div div,
                                                         const Hit* __restrict__ big,
                                                         const uint32_t* __restrict__ segp,
                                                         uint64_t /* hits (unused) */,
@@ -1206,7 +1209,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
     // the current probe string; the band DP reads at most 2 * MAXW bytes past a part's end
     // (vsp_seg and vsp_lane up to width 9; the wider classes keep 128).  An indexed string of
     // at most REGY bytes has probes of at most REGY + tau bytes.
-    constexpr int XMAX = REGY > 0 ? REGY + kTauMax : kLenMax;
+    constexpr int XMAX = REGY > 0 ? REGY + (GMAXW <= 9 ? GMAXW - 1 : kTauMax) : kLenMax;
     constexpr int XPAD = GMAXW <= 9 ? 32 : 128;
     __shared__ uint32_t s_x[kWaves][(XMAX + 1 + XPAD + 3) / 4];
     __shared__ uint32_t s_q[kWaves][2 * SEG];             // left-part survivors
@@ -1305,17 +1308,22 @@ __global__ __launch_bounds__(kBlock) void k_verify_segs(VerifyParams V, Div div,
                 const uint8_t* y = yinl ? yinl + (int64_t)e * stride_of(l)
                                         : V.y_arena + ybase + (int64_t)g * stride_of(l);
                 if constexpr (LANE) {
-                    // every load first, then the writes: one wait for all of them
+                    // every load first, then the writes: one wait for all of them.  A class
+                    // of REGY = 40 loads 48 bytes (inside the 48-byte stride of its strings)
+                    // and writes the slot's 10 words only
+                    constexpr int NQ = (REGY + 15) / 16;
                     const uint4* yq = reinterpret_cast<const uint4*>(y);
-                    uint4 v[REGY / 16];
+                    uint4 v[NQ];
 #pragma unroll
-                    for (int q = 0; q < REGY / 16; ++q)
+                    for (int q = 0; q < NQ; ++q)
                         if (q * 16 < l) v[q] = yq[q];
 #pragma unroll
-                    for (int q = 0; q < REGY / 16; ++q) {
+                    for (int q = 0; q < NQ; ++q) {
                         if (q * 16 < l) {
-                            ysw[4 * q] = v[q].x; ysw[4 * q + 1] = v[q].y;
-                            ysw[4 * q + 2] = v[q].z; ysw[4 * q + 3] = v[q].w;
+                            ysw[4 * q] = v[q].x;
+                            if (16 * q + 4 < REGY) ysw[4 * q + 1] = v[q].y;
+                            if (16 * q + 8 < REGY) ysw[4 * q + 2] = v[q].z;
+                            if (16 * q + 12 < REGY) ysw[4 * q + 3] = v[q].w;
                         }
                     }
                 } else if (REGY > 0) {
@@ -2316,7 +2324,13 @@ static void verify_segs_wn(const VerifyParams& V, const Hit* big, const uint32_t
                            uint64_t nbig, uint64_t nseg, const uint32_t* first, uint64_t nchunks,
                            uint32_t chunk, int grid, hipStream_t s)
 {
-    if (V.y_maxlen <= 48)
+    // one candidate per lane with strings of at most 40 bytes: 44-byte lane slots, so that 8
+    // blocks fit a CU's LDS
+    if (NC == 1 && W <= 9 && V.y_maxlen <= 40)
+        hipLaunchKernelGGL((k_verify_segs<W, (NC == 1 && W <= 9) ? 40 : 48, NC>), dim3(grid),
+                           dim3(kBlock), 0, s, V, make_div(V.tau + 1), big, segp, nbig, nseg,
+                           first, nchunks, chunk);
+    else if (V.y_maxlen <= 48)
         hipLaunchKernelGGL((k_verify_segs<W, 48, NC>), dim3(grid), dim3(kBlock), 0, s, V,
                            make_div(V.tau + 1), big, segp, nbig, nseg, first, nchunks, chunk);
     else if (V.y_maxlen <= 64)
