@@ -2777,6 +2777,67 @@ hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, con
     return hipGetLastError();
 }
 
+// Streamed self-joins: a window's result pairs (window-local ids) as global sort keys
+// ids[a] << bbits | ids[b].  With min_len > 0 a pair of two strings shorter than min_len (both
+// in the window's halo, found again by the window that owns them) becomes the sentinel, all
+// ones in 2 * bbits bits, which no pair (a < b) reaches and which sorts after every pair; the
+// sentinels are counted.
+__global__ __launch_bounds__(kBlock) void k_window_keys(const int32_t* __restrict__ a,
+                                                       const int32_t* __restrict__ b, uint64_t m,
+                                                       const int32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ offs,
+                                                       int min_len, int bbits,
+                                                       uint64_t* __restrict__ keys,
+                                                       unsigned long long* __restrict__ dropped)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool drop = false;
+    if (k < m) {
+        const int32_t la = a[k], lb = b[k];
+        if (min_len > 0) {
+            const int na = offs[la + 1] - offs[la], nb = offs[lb + 1] - offs[lb];
+            drop = (na > nb ? na : nb) < min_len;
+        }
+        keys[k] = drop ? ((2 * bbits >= 64) ? ~0ull : (1ull << (2 * bbits)) - 1ull)
+                       : ((uint64_t)(uint32_t)ids[la] << bbits) | (uint64_t)(uint32_t)ids[lb];
+    }
+    const uint64_t dm = __ballot(drop);
+    if ((threadIdx.x & 63) == 0 && dm) atomicAdd(dropped, (unsigned long long)__popcll(dm));
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_keys(const uint64_t* __restrict__ keys,
+                                                      uint64_t m, int bbits,
+                                                      int32_t* __restrict__ a,
+                                                      int32_t* __restrict__ b)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m) {
+        const uint64_t v = keys[k];
+        a[k] = (int32_t)(v >> bbits);
+        b[k] = (int32_t)(v & ((1ull << bbits) - 1));
+    }
+}
+
+hipError_t launch_window_keys(const int32_t* a, const int32_t* b, uint64_t m, const int32_t* ids,
+                              const int32_t* offs, int min_len, int bbits, uint64_t* keys,
+                              unsigned long long* dropped, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    if (bbits < 1 || bbits > 31) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_window_keys, dim3(blocks_for(m)), dim3(kBlock), 0, s, a, b, m, ids, offs,
+                       min_len, bbits, keys, dropped);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_keys(const uint64_t* keys, uint64_t m, int bbits, int32_t* a, int32_t* b,
+                             hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    if (bbits < 1 || bbits > 31) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_split_keys, dim3(blocks_for(m)), dim3(kBlock), 0, s, keys, m, bbits, a, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
                              hipStream_t s)
 {

@@ -1057,10 +1057,81 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
     for (int64_t k = 0; k < n; ++k) len[(size_t)k] = (uint16_t)(S->offsets[k + 1] - S->offsets[k]);
     pj_options o{};
     if (opt) o = *opt;
-    o.outputs_on_device = 0;
+    o.outputs_on_device = 1;
+    const hipStream_t st = stream_of(opt);
     pj_stats acc{};
-    // each window's pairs as keys (a << 32 | b), ascending within the window
+    // Each pair comes from exactly one window.  The windows' pairs stay on the device as global
+    // keys ga << bb | gb and are sorted there once; only when they would pass key_cap (a 64th of
+    // the free device memory) is the batch held so far sorted and moved to the host as one run,
+    // and the host then merges the runs.
+    const int bb = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 0;
+    }
+    uint64_t key_cap = std::max<uint64_t>(1ull << 20, (uint64_t)(free_b / 64));
+    // tests force small batches (it changes no result)
+    if (const char* e = getenv("PJ_STREAM_KEY_CAP")) key_cap = (uint64_t)std::max(1LL, atoll(e));
+    struct Batch {
+        std::vector<std::pair<uint64_t*, uint64_t>> parts;    // device keys of each window
+        uint64_t total = 0;
+        unsigned long long* dropped = nullptr;                 // halo sentinels in the batch
+        ~Batch()
+        {
+            for (auto& q : parts) (void)hipFree(q.first);
+            if (dropped) (void)hipFree(dropped);
+        }
+    } batch;
+    if (hipMalloc((void**)&batch.dropped, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        batch.dropped = nullptr;
+        throw Error(PJ_ENOMEM, "streamed join: counter allocation failed");
+    }
+    hip_check(hipMemsetAsync(batch.dropped, 0, sizeof(unsigned long long), st), "memset");
+    // sorts the batch on the device; returns the sorted keys (valid ones first) and their count
+    Owned sorted_bufs;
+    auto sort_batch = [&](uint64_t* valid_out) -> uint64_t* {
+        const uint64_t m = batch.total;
+        uint64_t* k0 = (uint64_t*)sorted_bufs.get("stream.k0", sizeof(uint64_t) * (size_t)m);
+        uint64_t* k1 = (uint64_t*)sorted_bufs.get("stream.k1", sizeof(uint64_t) * (size_t)m);
+        uint64_t off = 0;
+        for (auto& q : batch.parts) {
+            hip_check(hipMemcpyAsync(k0 + off, q.first, sizeof(uint64_t) * (size_t)q.second,
+                                     hipMemcpyDeviceToDevice, st), "batch copy");
+            off += q.second;
+        }
+        const size_t tb = radix_tmp_bytes(m);
+        void* tmp = sorted_bufs.get("stream.tmp", tb);
+        bool alt = false;
+        hip_check(radix_sort_u64(k0, nullptr, k1, nullptr, m, 2 * bb, tmp, tb, &alt, st),
+                  "radix(stream)");
+        unsigned long long dropped = 0;
+        hip_check(hipMemcpyAsync(&dropped, batch.dropped, sizeof dropped, hipMemcpyDeviceToHost,
+                                 st), "dropped");
+        hip_check(hipStreamSynchronize(st), "sync");
+        *valid_out = m - (uint64_t)dropped;
+        return alt ? k1 : k0;
+    };
+    auto clear_batch = [&]() {
+        for (auto& q : batch.parts) (void)hipFree(q.first);
+        batch.parts.clear();
+        batch.total = 0;
+        hip_check(hipMemsetAsync(batch.dropped, 0, sizeof(unsigned long long), st), "memset");
+    };
+    // host runs (only when the batch was moved off the device)
     std::vector<std::vector<uint64_t>> runs;
+    auto spill = [&]() {
+        if (batch.total == 0) return;
+        uint64_t valid = 0;
+        const uint64_t* ks = sort_batch(&valid);
+        runs.emplace_back((size_t)valid);
+        if (valid)
+            hip_check(hipMemcpyAsync(runs.back().data(), ks, sizeof(uint64_t) * (size_t)valid,
+                                     hipMemcpyDeviceToHost, st), "spill");
+        hip_check(hipStreamSynchronize(st), "sync");
+        clear_batch();
+    };
     int lmax = -1;
     for (int l = 0; l <= kLenMax; ++l)
         if (cnt[l]) lmax = l;
@@ -1092,14 +1163,31 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         // pairs with both strings in the halo [a - tau, a) come only from the short-string
         // path, so the length filter is needed only when the window holds strings <= tau long
         const bool filter = lo <= tau;
-        runs.emplace_back();
-        std::vector<uint64_t>& run = runs.back();
-        run.reserve((size_t)part.count);
-        for (int64_t k = 0; k < part.count; ++k) {
-            const int32_t la = part.a[k], lb = part.b[k];
-            if (filter && std::max(offs[la + 1] - offs[la], offs[lb + 1] - offs[lb]) < a)
-                continue;
-            run.push_back((uint64_t)(uint32_t)ids[(size_t)la] << 32 | (uint32_t)ids[(size_t)lb]);
+        if (part.count > 0) {
+            const uint64_t m = (uint64_t)part.count;
+            if (batch.total > 0 && batch.total + m > key_cap) spill();
+            Owned win;
+            int32_t* d_ids = (int32_t*)win.get("win.ids", sizeof(int32_t) * ids.size());
+            hip_check(hipMemcpyAsync(d_ids, ids.data(), sizeof(int32_t) * ids.size(),
+                                     hipMemcpyHostToDevice, st), "ids");
+            int32_t* d_offs = nullptr;
+            if (filter) {
+                d_offs = (int32_t*)win.get("win.offs", sizeof(int32_t) * offs.size());
+                hip_check(hipMemcpyAsync(d_offs, offs.data(), sizeof(int32_t) * offs.size(),
+                                         hipMemcpyHostToDevice, st), "offs");
+            }
+            uint64_t* kp = nullptr;
+            if (hipMalloc((void**)&kp, sizeof(uint64_t) * (size_t)m) != hipSuccess) {
+                (void)hipGetLastError();
+                pj_pairs_free(&part);
+                throw Error(PJ_ENOMEM, "streamed join: key buffer of %llu pairs",
+                            (unsigned long long)m);
+            }
+            batch.parts.emplace_back(kp, m);
+            batch.total += m;
+            hip_check(launch_window_keys(part.a, part.b, m, d_ids, d_offs, filter ? a : 0, bb, kp,
+                                         batch.dropped, st), "window keys");
+            hip_check(hipStreamSynchronize(st), "sync");
         }
         pj_pairs_free(&part);
         acc.strings += t_stats.strings;
@@ -1126,21 +1214,29 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.shared_cells += t_stats.shared_cells;
         a = b + 1;
     }
-    // k-way merge of the windows' sorted runs straight into the output arrays (one run: a copy)
+    if (runs.empty()) {
+        // every window's keys on the device: split the sorted keys into the output
+        uint64_t valid = 0;
+        const uint64_t* ks = batch.total ? sort_batch(&valid) : nullptr;
+        int32_t* da = (int32_t*)sorted_bufs.get("stream.a", sizeof(int32_t) * (size_t)valid);
+        int32_t* db = (int32_t*)sorted_bufs.get("stream.b", sizeof(int32_t) * (size_t)valid);
+        hip_check(launch_split_keys(ks, valid, bb, da, db, st), "split");
+        emit_output(da, db, valid, false, out, st);
+        acc.pairs = (int64_t)valid;
+        acc.ms_total = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+        t_stats = acc;
+        return;
+    }
+    spill();
+    // k-way merge of the host runs straight into the output arrays
     size_t m = 0;
     for (const auto& r : runs) m += r.size();
     out->on_device = 0;
     out->a = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     out->b = (int32_t*)malloc(sizeof(int32_t) * std::max<size_t>(m, 1));
     if (!out->a || !out->b) throw std::bad_alloc();
-    if (runs.size() == 1) {
-        const std::vector<uint64_t>& r = runs[0];
-        for (size_t k = 0; k < m; ++k) {
-            out->a[k] = (int32_t)(r[k] >> 32);
-            out->b[k] = (int32_t)(uint32_t)r[k];
-        }
-        runs.clear();
-    }
+    const uint64_t lo_mask = (1ull << bb) - 1;
     using Head = std::pair<uint64_t, size_t>;          // (key, run)
     std::vector<Head> heap;
     std::vector<size_t> pos(runs.size(), 0);
@@ -1148,12 +1244,12 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         if (!runs[r].empty()) heap.emplace_back(runs[r][0], r);
     auto greater = [](const Head& x, const Head& y) { return x.first > y.first; };
     std::make_heap(heap.begin(), heap.end(), greater);
-    for (size_t k = 0; k < m && !runs.empty(); ++k) {
+    for (size_t k = 0; k < m; ++k) {
         std::pop_heap(heap.begin(), heap.end(), greater);
         const Head h = heap.back();
         heap.pop_back();
-        out->a[k] = (int32_t)(h.first >> 32);
-        out->b[k] = (int32_t)(uint32_t)h.first;
+        out->a[k] = (int32_t)(h.first >> bb);
+        out->b[k] = (int32_t)(h.first & lo_mask);
         const size_t r = h.second;
         if (++pos[r] < runs[r].size()) {
             heap.emplace_back(runs[r][pos[r]], r);

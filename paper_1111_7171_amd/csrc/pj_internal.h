@@ -269,6 +269,13 @@ hipError_t launch_unique_flags(const uint64_t* keys, uint64_t m, uint32_t* flags
 hipError_t launch_compact_pairs(const uint64_t* keys, const uint32_t* flags, const uint32_t* pos,
                                 uint64_t m, int bbits, int32_t* a, int32_t* b, hipStream_t s);
 
+// streamed self-joins: window pairs -> global keys (halo-only pairs as a counted sentinel that
+// sorts last); sorted keys -> pair arrays
+hipError_t launch_window_keys(const int32_t* a, const int32_t* b, uint64_t m, const int32_t* ids,
+                              const int32_t* offs, int min_len, int bbits, uint64_t* keys,
+                              unsigned long long* dropped, hipStream_t s);
+hipError_t launch_split_keys(const uint64_t* keys, uint64_t m, int bbits, int32_t* a, int32_t* b,
+                             hipStream_t s);
 hipError_t launch_gather_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
                              hipStream_t s);
 

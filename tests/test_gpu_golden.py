@@ -120,6 +120,17 @@ def test_host_inputs_and_outputs_full_size():
         small.free()
 
 
+def test_streamed_windows_full_size():
+    """cfg2 at tau=4 in four length windows (host strings in, host pairs out): the windows'
+    pairs, merged on the device, hash to the oracle's list, with the oracle's counts."""
+    e = GOLD["cfg2"]["taus"]["4"]
+    col = _col(2)
+    pairs = P.pj_self_join_streamed(col, 4, int(col.offsets[-1]) // 4)
+    st = P.pj_last_stats()
+    assert len(pairs) == e["pairs"] and _sha(pairs) == e["pairs_sha256"]
+    _check_counts(st, e, "cfg2 tau=4 streamed quarter windows")
+
+
 @pytest.mark.parametrize("cfg,tau", [(2, 4), (3, 8)])
 def test_share_prefix_full_size_matches_oracle(cfg, tau):
     """The shared-prefix mode (Sec. 5.3) at full size: same pairs and counts as the oracle."""

@@ -51,3 +51,18 @@ def test_cfg2_windows_same_pairs_and_counts(mode):
             assert np.array_equal(got, whole), (tau, parts)
             for k in ("selected", "candidates", "cells", "pairs"):
                 assert st[k] == sw[k], (tau, parts, k)
+
+
+@pytest.mark.parametrize("cap", [1, 700, 20_000])
+def test_key_batches_moved_to_host(cap, monkeypatch):
+    """Windows' pairs held on the device in batches of at most `cap` keys (a batch that would
+    pass it is sorted and moved to the host first, and the host merges the runs): the same
+    pairs as the whole-set join, for one window per batch up to every window in one batch."""
+    col = W.cfg2(20_000, seed=62)
+    arena = int(col.offsets[-1])
+    monkeypatch.setenv("PJ_STREAM_KEY_CAP", str(cap))
+    for tau in (1, 3):
+        whole = P.pj_self_join(col, tau)
+        _say("streamed key cap", cap, "tau", tau)
+        got = P.pj_self_join_streamed(col, tau, arena // 8)
+        assert np.array_equal(got, whole), (cap, tau)
