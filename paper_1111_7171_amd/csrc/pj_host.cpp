@@ -21,6 +21,7 @@
 #include "../../include/passjoin.h"
 #include "pj_internal.h"
 #include "pj_host_internal.h"
+#include "pj_validate.h"
 
 namespace pj {
 
@@ -193,19 +194,9 @@ double Timer::ms(int a, int b)
 
 void validate_host_strings(const pj_strings* S, const char* what)
 {
-    if (!S) throw Error(PJ_EINVAL, "%s: null pj_strings", what);
-    if (S->n < 0) throw Error(PJ_EINVAL, "%s: n < 0", what);
-    if (S->n >= (int64_t)INT32_MAX) throw Error(PJ_ERANGE, "%s: too many strings", what);
-    if (!S->offsets) throw Error(PJ_EINVAL, "%s: null offsets", what);
-    if (S->offsets[0] != 0) throw Error(PJ_EINVAL, "%s: offsets[0] != 0", what);
-    for (int64_t k = 0; k < S->n; ++k) {
-        int64_t l = (int64_t)S->offsets[k + 1] - S->offsets[k];
-        if (l < 0) throw Error(PJ_EINVAL, "%s: offsets decrease at %lld", what, (long long)k);
-        if (l > kLenMax)
-            throw Error(PJ_ERANGE, "%s: string %lld has length %lld > %d", what, (long long)k,
-                        (long long)l, kLenMax);
-    }
-    if (S->offsets[S->n] > 0 && !S->bytes) throw Error(PJ_EINVAL, "%s: null bytes", what);
+    char msg[256];
+    const int rc = check_host_strings(S, what, msg, sizeof msg);
+    if (rc != PJ_OK) throw Error(rc, "%s", msg);
 }
 
 // Bytes of device memory readable from p: the rest of the allocation that holds p.  Throws
@@ -1065,14 +1056,7 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
     // the free device memory) is the batch held so far sorted and moved to the host as one run,
     // and the host then merges the runs.
     const int bb = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-        (void)hipGetLastError();
-        free_b = 0;
-    }
-    uint64_t key_cap = std::max<uint64_t>(1ull << 20, (uint64_t)(free_b / 64));
-    // tests force small batches (it changes no result)
-    if (const char* e = getenv("PJ_STREAM_KEY_CAP")) key_cap = (uint64_t)std::max(1LL, atoll(e));
+    uint64_t key_cap = 0;                                      // set with the first window's keys
     struct Batch {
         std::vector<std::pair<uint64_t*, uint64_t>> parts;    // device keys of each window
         uint64_t total = 0;
@@ -1083,12 +1067,25 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
             if (dropped) (void)hipFree(dropped);
         }
     } batch;
-    if (hipMalloc((void**)&batch.dropped, sizeof(unsigned long long)) != hipSuccess) {
-        (void)hipGetLastError();
-        batch.dropped = nullptr;
-        throw Error(PJ_ENOMEM, "streamed join: counter allocation failed");
-    }
-    hip_check(hipMemsetAsync(batch.dropped, 0, sizeof(unsigned long long), st), "memset");
+    // device state, set up when the first window has pairs (an empty set touches no device)
+    auto start_batches = [&]() {
+        if (batch.dropped) return;
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        key_cap = std::max<uint64_t>(1ull << 20, (uint64_t)(free_b / 64));
+        // tests force small batches (it changes no result)
+        if (const char* e = getenv("PJ_STREAM_KEY_CAP"))
+            key_cap = (uint64_t)std::max(1LL, atoll(e));
+        if (hipMalloc((void**)&batch.dropped, sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            batch.dropped = nullptr;
+            throw Error(PJ_ENOMEM, "streamed join: counter allocation failed");
+        }
+        hip_check(hipMemsetAsync(batch.dropped, 0, sizeof(unsigned long long), st), "memset");
+    };
     // sorts the batch on the device; returns the sorted keys (valid ones first) and their count
     Owned sorted_bufs;
     auto sort_batch = [&](uint64_t* valid_out) -> uint64_t* {
@@ -1165,6 +1162,7 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         const bool filter = lo <= tau;
         if (part.count > 0) {
             const uint64_t m = (uint64_t)part.count;
+            start_batches();
             if (batch.total > 0 && batch.total + m > key_cap) spill();
             Owned win;
             int32_t* d_ids = (int32_t*)win.get("win.ids", sizeof(int32_t) * ids.size());
@@ -1214,10 +1212,23 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         acc.shared_cells += t_stats.shared_cells;
         a = b + 1;
     }
+    if (runs.empty() && batch.total == 0) {
+        // no pairs at all
+        out->on_device = 0;
+        out->count = 0;
+        out->a = (int32_t*)malloc(sizeof(int32_t));
+        out->b = (int32_t*)malloc(sizeof(int32_t));
+        if (!out->a || !out->b) throw std::bad_alloc();
+        acc.pairs = 0;
+        acc.ms_total = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+        t_stats = acc;
+        return;
+    }
     if (runs.empty()) {
         // every window's keys on the device: split the sorted keys into the output
         uint64_t valid = 0;
-        const uint64_t* ks = batch.total ? sort_batch(&valid) : nullptr;
+        const uint64_t* ks = sort_batch(&valid);
         int32_t* da = (int32_t*)sorted_bufs.get("stream.a", sizeof(int32_t) * (size_t)valid);
         int32_t* db = (int32_t*)sorted_bufs.get("stream.b", sizeof(int32_t) * (size_t)valid);
         hip_check(launch_split_keys(ks, valid, bb, da, db, st), "split");
