@@ -515,16 +515,49 @@ __global__ __launch_bounds__(kBlock) void k_insert_runs(const uint64_t* __restri
     }
 }
 
-// One thread per list: sets its key's filter bit.
-__global__ __launch_bounds__(kBlock) void k_filter_keys(const uint64_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ runstart,
-                                                        uint32_t nruns, uint32_t* __restrict__ filter,
-                                                        uint32_t fmask)
+// Key filter, blocked by (l, i) group.  First and one-past-last list of each (l, i) group (the arrays zeroed by the caller): lists are
+// in key order and the group is the key's top bits, so a group's lists are consecutive
+__global__ __launch_bounds__(kBlock) void k_filter_group_bounds(const uint64_t* __restrict__ keys,
+                                                                const uint32_t* __restrict__ runstart,
+                                                                uint32_t nruns,
+                                                                uint32_t* __restrict__ gfirst,
+                                                                uint32_t* __restrict__ gend)
 {
     const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= nruns) return;
-    const uint64_t h = table_slot(keys[runstart[r]]);
-    atomicOr(&filter[filter_word(h, fmask)], filter_bits(h));
+    const uint64_t g = keys[runstart[r]] >> kHashBits;
+    if (r == 0 || (keys[runstart[r - 1]] >> kHashBits) != g) gfirst[g] = r;
+    if (r + 1 == nruns || (keys[runstart[r + 1]] >> kHashBits) != g) gend[g] = r + 1;
+}
+
+// words of each group's block: a power of two >= lists / 2 (16 bits per list), at least one
+__global__ __launch_bounds__(kBlock) void k_filter_block_words(const uint32_t* __restrict__ gfirst,
+                                                               const uint32_t* __restrict__ gend,
+                                                               uint32_t ngroups,
+                                                               uint32_t* __restrict__ words)
+{
+    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= ngroups) return;
+    const uint32_t need = (gend[g] - gfirst[g] + 1) >> 1;
+    uint32_t w = 1;
+    while (w < need) w <<= 1;
+    words[g] = w;
+}
+
+// sets the filter bits of every list's key in its group's block (filter zeroed by the caller)
+__global__ __launch_bounds__(kBlock) void k_filter_keys(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ runstart,
+                                                        uint32_t nruns,
+                                                        const uint32_t* __restrict__ dir,
+                                                        uint32_t* __restrict__ filter)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nruns) return;
+    const uint64_t key = keys[runstart[r]];
+    const uint64_t h = table_slot(key);
+    const uint64_t g = key >> kHashBits;
+    const uint32_t base = dir[g];
+    atomicOr(&filter[base + filter_word_in(h, dir[g + 1] - base - 1u)], filter_bits(h));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -591,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         const uint32_t* vals = P.vals;
         uint64_t mask = P.mask;
         const uint32_t* filter = P.filter;
-        uint32_t fmask = P.filter_mask;
+        const uint32_t* fdir = P.filter_dir;
         if (valid) {
             gx = P.g_begin + (uint32_t)(t / per);
             const uint32_t rem = (uint32_t)(t % per);
@@ -606,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
                 vals = ref.vals;
                 mask = ref.mask;
                 filter = ref.filter;
-                fmask = ref.filter_mask;
+                fdir = ref.filter_dir;
                 dv.d = (uint32_t)(tau + 1);
                 dv.m = ref.div_m;
             }
@@ -633,6 +666,14 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         auto rd = [&](int k) -> uint8_t { return staged ? xs[k] : x[k]; };
         uint64_t h = 0, top = 0;
         if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
+        // the (l, i) group's filter block
+        const bool use_filter = valid && lo <= hi && filter && sg.len > exact_len;
+        uint32_t fb = 0, fm = 0;
+        if (use_filter) {
+            const uint32_t g = (uint32_t)((l - (tau + 1)) * (tau + 1) + (i - 1));
+            fb = fdir[g];
+            fm = fdir[g + 1] - fb - 1u;
+        }
         // the window has at most tau+1 positions for multi-match, more for the other methods;
         // the loop ends when no lane of the wave has a position left
         for (int s = 0;; ++s) {
@@ -653,9 +694,15 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
                                   exact_len);
                 }
                 const uint64_t key = make_key(l, i, tau, sg.len, h, exact_len);
-                // hashed (long) segments rarely match: the filter, small enough for L2, turns
-                // most of those lookups away before the table read
-                const bool maybe = !(filter && sg.len > exact_len) || filter_has(filter, fmask, key);
+                // hashed (long) segments rarely match: the group's filter block (one cache line
+                // for a group of up to 64 lists, read again by the lane at every position of
+                // its window) turns most of those lookups away before the table read
+                bool maybe = true;
+                if (use_filter) {
+                    const uint64_t hs = table_slot(key);
+                    const uint32_t fbits = filter_bits(hs);
+                    maybe = (filter[fb + filter_word_in(hs, fm)] & fbits) == fbits;
+                }
                 if (maybe && table_lookup(table, mask, key, &start, &count)) {
                     if (P.self && l == n) {
                         // keep members with g < gx (lists are ascending in g)
@@ -1181,10 +1228,11 @@ __device__ inline T uniform_load(const T* p)
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
-// The 40-byte class fits 8 blocks per CU in LDS; it is compiled for 8 waves per SIMD (at
-// most 64 VGPRs) to match.
+// The 40-byte class of the 5-wide band fits 8 blocks per CU in LDS; it is compiled for 8 waves
+// per SIMD (at most 64 VGPRs) to match.
 template <int GMAXW, int REGY, int NCT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REGY == 40 ? 8 : 1)))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((REGY == 40 && GMAXW <= 5) ? 8 : 1)))
 void k_verify_segs(VerifyParams V, Div div,
                                                         const Hit* __restrict__ big,
                                                         const uint32_t* __restrict__ segp,
@@ -2235,12 +2283,22 @@ hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid,
     return hipGetLastError();
 }
 
-hipError_t launch_filter_keys(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
-                              uint32_t* filter, uint32_t filter_mask, hipStream_t s)
+hipError_t launch_filter_build(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                               uint32_t ngroups, uint32_t* gfirst, uint32_t* gend, uint32_t* words,
+                               void* scan_tmp, size_t scan_bytes, uint32_t* filter_dir,
+                               uint32_t* filter, hipStream_t s)
 {
-    if (nruns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_keys, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, keys, runstart,
-                       nruns, filter, filter_mask);
+    if (ngroups == 0) return hipSuccess;
+    if (nruns > 0)
+        hipLaunchKernelGGL(k_filter_group_bounds, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, keys,
+                           runstart, nruns, gfirst, gend);
+    hipLaunchKernelGGL(k_filter_block_words, dim3(blocks_for(ngroups)), dim3(kBlock), 0, s, gfirst,
+                       gend, ngroups, words);
+    hipError_t e = scan_u32_to_u32(words, filter_dir, ngroups, scan_tmp, scan_bytes, s);
+    if (e != hipSuccess) return e;
+    if (nruns > 0)
+        hipLaunchKernelGGL(k_filter_keys, dim3(blocks_for(nruns)), dim3(kBlock), 0, s, keys,
+                           runstart, nruns, filter_dir, filter);
     return hipGetLastError();
 }
 

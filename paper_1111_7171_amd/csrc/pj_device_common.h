@@ -161,18 +161,18 @@ __device__ inline uint64_t make_key(int l, int i, int tau, int len, uint64_t cod
 
 __device__ inline uint64_t table_slot(uint64_t key) { return mix64(key ^ 0x5851F42D4C957F2Dull); }
 
-// Key filter: two bits of one 32-bit word per key, all from the slot hash's bits 30.. (the
-// table uses the low bits); fmask + 1 = bits in the filter, a multiple of 32.
-__device__ inline uint32_t filter_word(uint64_t h, uint32_t fmask) { return (uint32_t)(h >> 45) & (fmask >> 5); }
+// Key filter, blocked by (l, i) group: group g owns the words [dir[g], dir[g+1]) of the filter,
+// a power of two of them (about 16 bits per list of the group, at least one word), so the keys
+// a wave looks up for one probe string and a few (l, i) share one or two cache lines.  A key
+// sets two bits of one word of its group's block, all from the slot hash's bits 30.. (the table
+// uses the low bits): the word (h >> 45) & (block words - 1), the bits below.
 __device__ inline uint32_t filter_bits(uint64_t h)
 {
     return (1u << ((uint32_t)(h >> 35) & 31u)) | (1u << ((uint32_t)(h >> 30) & 31u));
 }
-__device__ inline bool filter_has(const uint32_t* __restrict__ filter, uint32_t fmask, uint64_t key)
+__device__ inline uint32_t filter_word_in(uint64_t h, uint32_t block_mask)
 {
-    const uint64_t h = table_slot(key);
-    const uint32_t b = filter_bits(h);
-    return (filter[filter_word(h, fmask)] & b) == b;
+    return (uint32_t)(h >> 45) & block_mask;
 }
 
 __device__ inline bool table_lookup(const uint4* __restrict__ table, uint64_t mask, uint64_t key,

@@ -455,15 +455,22 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     hip_check(launch_insert_runs(keys, runstart, nruns, (uint32_t)E, X.table, X.mask, st),
               "insert_runs");
     if (X.sym.exact_len < kLenMax) {
-        // key filter for hashed segments: 8 bits per list, 2^16 .. 2^24 bits (2 MB, which stays
-        // in an XCD's 4 MB L2)
-        uint64_t fbits = 1ull << 16;
-        while (fbits < 8ull * nruns && fbits < (1ull << 24)) fbits <<= 1;
-        X.filter_mask = (uint32_t)(fbits - 1);
-        X.filter = (uint32_t*)A.get(nm("filter").c_str(), (size_t)(fbits / 8));
-        hip_check(hipMemsetAsync(X.filter, 0, (size_t)(fbits / 8), st), "memset filter");
-        hip_check(launch_filter_keys(keys, runstart, nruns, X.filter, X.filter_mask, st),
-                  "filter keys");
+        // key filter for hashed segments, blocked by (l, i) group (16 bits per list)
+        const uint32_t ngroups = (uint32_t)((D.lmax - T1 + 1) * T1);
+        const uint64_t fwords = (uint64_t)nruns + 2ull * ngroups;
+        X.filter = (uint32_t*)A.get(nm("filter").c_str(), sizeof(uint32_t) * (size_t)fwords);
+        X.filter_dir = (uint32_t*)A.get(nm("filter_dir").c_str(),
+                                        sizeof(uint32_t) * (size_t)(ngroups + 1));
+        uint32_t* gfirst = (uint32_t*)W.get("index.gfirst", sizeof(uint32_t) * (size_t)ngroups);
+        uint32_t* gend = (uint32_t*)W.get("index.gend", sizeof(uint32_t) * (size_t)ngroups);
+        uint32_t* words = (uint32_t*)W.get("index.fwords", sizeof(uint32_t) * (size_t)ngroups);
+        hip_check(hipMemsetAsync(gfirst, 0, sizeof(uint32_t) * (size_t)ngroups, st), "memset");
+        hip_check(hipMemsetAsync(gend, 0, sizeof(uint32_t) * (size_t)ngroups, st), "memset");
+        hip_check(hipMemsetAsync(X.filter, 0, sizeof(uint32_t) * (size_t)fwords, st), "memset");
+        const size_t fsb = scan_tmp_bytes(ngroups);
+        void* fst = W.get("scan.tmp", std::max(fsb, sb));
+        hip_check(launch_filter_build(keys, runstart, nruns, ngroups, gfirst, gend, words, fst, fsb,
+                                      X.filter_dir, X.filter, st), "filter");
     }
     if (with_share) {
         // content order of every list (shared-prefix verification, Sec. 5.3): entries sorted by
@@ -563,7 +570,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             pp.keys = spec.X->keys; pp.vals = spec.X->vals; pp.table = spec.X->table;
             pp.mask = spec.X->mask;
             pp.filter = spec.X->filter;
-            pp.filter_mask = spec.X->filter_mask;
+            pp.filter_dir = spec.X->filter_dir;
         }
         pp.tau = tau;
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;

@@ -183,7 +183,7 @@ int pj_build_index(const pj_strings* S, int32_t tau_min, int32_t tau_max, const 
             entries += X.entries;
             refs[(size_t)t] = IndexRef{X.table, X.vals, X.mask,
                                        (uint32_t)(((1u << 21) + (uint32_t)t) / (uint32_t)(t + 1)), 1u,
-                                       X.filter, X.filter_mask};
+                                       X.filter, X.filter_dir};
         }
         idx->has_entries = entries > 0;
         idx->refs = (IndexRef*)idx->mem.get("I.refs", sizeof(IndexRef) * (kTauMax + 1));

@@ -64,11 +64,12 @@ struct DevIndex {
     uint32_t* vals = nullptr;           // [entries] sorted position g of the string
     uint4* table = nullptr;             // [mask + 1] {key lo, key hi, start, count}
     uint64_t mask = 0;
-    // membership filter of the keys: bit (slot hash >> 40) & filter_mask is set for every key,
-    // so a clear bit proves a key absent without reading the table (long, hashed segments rarely
-    // match, and the table is far larger than an XCD's L2 while the filter is not)
-    uint32_t* filter = nullptr;         // [(filter_mask + 1) / 32]
-    uint32_t filter_mask = 0;
+    // membership filter of the keys, blocked by (l, i) group: group g = key >> 40 owns the
+    // words [filter_dir[g], filter_dir[g + 1]) (a power of two of them), in which each of its
+    // keys sets two bits; a clear bit proves a key absent without reading the table (long,
+    // hashed segments rarely match).  nullptr when every segment is keyed exactly.
+    uint32_t* filter = nullptr;
+    uint32_t* filter_dir = nullptr;     // [(lmax - tau) * (tau + 1) + 1]
     // inline copies of the members' strings in index order (strings of at most kInlineMaxLen
     // bytes; nullptr otherwise): entry j of length l at inl + inl_base[l] + j * stride_of(l)
     uint8_t* inl = nullptr;
@@ -88,8 +89,8 @@ struct IndexRef {
     uint64_t mask;
     uint32_t div_m;     // ceil(2^21 / (tau + 1)), see Div
     uint32_t present;   // 1 if an index for this tau exists
-    const uint32_t* filter;   // DevIndex::filter / filter_mask
-    uint32_t filter_mask;
+    const uint32_t* filter;       // DevIndex::filter / filter_dir
+    const uint32_t* filter_dir;
 };
 
 // One selected substring that found a non-empty list: candidates (vals[start + m], x, i, p).
@@ -113,7 +114,7 @@ struct ProbeParams {
     // index side
     const int32_t* y_lenstart;  // to know which lengths are present
     const uint64_t* keys; const uint32_t* vals; const uint4* table; uint64_t mask;
-    const uint32_t* filter; uint32_t filter_mask;   // key filter (nullptr: none)
+    const uint32_t* filter; const uint32_t* filter_dir;   // key filter (nullptr: none)
     int tau;                    // uniform tau, or the largest tau of a mixed batch
     int ymin, ymax;             // indexed lengths present
     // output
@@ -178,10 +179,13 @@ hipError_t launch_scatter_runstart(const uint32_t* flags, const uint32_t* runid,
 hipError_t launch_clear_table(uint4* table, uint64_t slots, hipStream_t s);
 hipError_t launch_insert_runs(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
                               uint32_t E, uint4* table, uint64_t mask, hipStream_t s);
-// sets the filter bit of every list's key (filter zeroed by the caller)
-hipError_t launch_filter_keys(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
-                              uint32_t* filter, uint32_t filter_mask, hipStream_t s);
-hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
+// builds the (l, i)-blocked key filter of ngroups groups: filter_dir[0 .. ngroups] and the bits
+// of every list's key in filter (at most nruns + 2 * ngroups words, zeroed by the caller);
+// gfirst, gend, words: ngroups-entry scratch (gfirst and gend zeroed by the caller)
+hipError_t launch_filter_build(const uint64_t* keys, const uint32_t* runstart, uint32_t nruns,
+                               uint32_t ngroups, uint32_t* gfirst, uint32_t* gend, uint32_t* words,
+                               void* scan_tmp, size_t scan_bytes, uint32_t* filter_dir,
+                               uint32_t* filter, hipStream_t s);hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
 // batched path: bucket the hits by (list size class, slot) into out, bucket regions in order;
