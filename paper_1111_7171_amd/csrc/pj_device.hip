@@ -394,23 +394,40 @@ __global__ __launch_bounds__(kBlock) void k_pack_arena(const uint8_t* __restrict
 // One thread per (indexed string, slot): emits (key, g) at a position grouped by (l, i) and
 // ordered by g inside the group, so a stable sort by key keeps lists in ascending g.
 // bitmap of the bytes present in the strings of a set (one thread per string)
+// Byte values present in the arena: one thread per 16-byte chunk of the length-sorted arena
+// (coalesced wide loads); the chunk's length group l is found by binary search over the
+// groups' byte ranges [gbase[l], gbase[l + 1]) (an empty group's range is empty), and only the
+// bytes inside a string count, not the padding of its slot.
 __global__ __launch_bounds__(kBlock) void k_byte_presence(const uint8_t* __restrict__ sarena,
-                                                          const uint16_t* __restrict__ slen,
-                                                          const int32_t* __restrict__ lenstart,
                                                           const int64_t* __restrict__ gbase,
-                                                          int64_t n, uint32_t* __restrict__ bitmap)
+                                                          int64_t total,
+                                                          uint32_t* __restrict__ bitmap)
 {
     __shared__ uint32_t bm[8];
     if (threadIdx.x < 8) bm[threadIdx.x] = 0;
     __syncthreads();
-    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n;
-         g += (int64_t)gridDim.x * kBlock) {
-        const int l = slen[g];
-        const uint8_t* s = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
-        for (int k = 0; k < l; ++k) {
-            const uint32_t b = s[k];
-            const uint32_t bit = 1u << (b & 31u);
-            if (!(bm[b >> 5] & bit)) atomicOr(&bm[b >> 5], bit);
+    const int64_t nchunks = total >> 4;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks;
+         c += (int64_t)gridDim.x * kBlock) {
+        const int64_t o = c << 4;
+        int lo = 0, hi = kLenTab - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int64_t end = mid + 1 < kLenTab ? gbase[mid + 1] : total;
+            if (end > o) hi = mid; else lo = mid + 1;
+        }
+        const int l = lo;
+        const int within = (int)((o - gbase[l]) % stride_of(l));
+        const int valid = l - within < 16 ? l - within : 16;
+        const uint4 v = *reinterpret_cast<const uint4*>(sarena + o);
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < valid) {
+                const uint32_t byte = (wd[k >> 2] >> ((k & 3) * 8)) & 255u;
+                const uint32_t bit = 1u << (byte & 31u);
+                if (!(bm[byte >> 5] & bit)) atomicOr(&bm[byte >> 5], bit);
+            }
         }
     }
     __syncthreads();
@@ -2231,9 +2248,11 @@ hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const in
 hipError_t launch_byte_presence(const DevSet& S, uint32_t* bitmap, hipStream_t s)
 {
     if (S.n == 0) return hipSuccess;
-    const unsigned grid = (unsigned)std::min<uint64_t>(blocks_for((uint64_t)S.n), 1024);
-    hipLaunchKernelGGL(k_byte_presence, dim3(grid), dim3(kBlock), 0, s, S.sarena, S.slen,
-                       S.lenstart, S.gbase, S.n, bitmap);
+    const uint64_t nchunks = (uint64_t)S.arena_bytes >> 4;
+    if (nchunks == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<uint64_t>(blocks_for(nchunks), 2048);
+    hipLaunchKernelGGL(k_byte_presence, dim3(grid), dim3(kBlock), 0, s, S.sarena, S.gbase,
+                       (int64_t)S.arena_bytes, bitmap);
     return hipGetLastError();
 }
 
