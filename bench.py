@@ -62,16 +62,16 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, sha: str):
-    """HBM traffic per launch measured by rocprofv3 PMC runs (profiles/traffic.json), only if
-    the kernels have not changed since."""
+def load_traffic(kernel: str, sha: str, workload: str):
+    """HBM traffic per launch measured by rocprofv3 PMC runs (profiles/traffic.json) for this
+    kernel on this workload, only if the kernels have not changed since."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         d = json.load(f)
     e = d.get(kernel)
-    if not e or e.get("source_sha") != sha:
+    if not e or e.get("source_sha") != sha or e.get("workload_key") != workload:
         return None
     return e.get("bytes_per_launch")
 
@@ -449,7 +449,10 @@ def main():
     per_launch_s = k_ms / 1e3 / max(k_launches, 1)
     ops_per_launch = OPS_PER_CELL * k_cells / max(k_launches, 1)
     achieved = ops_per_launch / max(per_launch_s, 1e-12) / 1e12
-    traffic = load_traffic(rk, sha)
+    # the counters were taken on one configuration: the workload with its size, taus,
+    # selection and mode
+    traffic = load_traffic(rk, sha, f"{args.workload} n={args.n} taus={args.taus} "
+                                    f"selection={args.selection} mode={args.mode}")
     line = {
         "metric": "self-join wall time, candidates/s, GCUPS; serving p50/p99 latency at fixed QPS",
         "value": cand / elapsed,
