@@ -684,7 +684,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         uint64_t h = 0, top = 0;
         if (valid && lo <= hi) top = pow_hash(sg.len);   // HB^(len-1)
         // the (l, i) group's filter block
-        const bool use_filter = valid && lo <= hi && filter && sg.len > exact_len;
+        const bool use_filter = valid && lo <= hi && filter &&
+                                (sg.len > exact_len || sg.len * sym_bits >= kFilterMinBits);
         uint32_t fb = 0, fm = 0;
         if (use_filter) {
             const uint32_t g = (uint32_t)((l - (tau + 1)) * (tau + 1) + (i - 1));
@@ -711,9 +712,9 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
                                   exact_len);
                 }
                 const uint64_t key = make_key(l, i, tau, sg.len, h, exact_len);
-                // hashed (long) segments rarely match: the group's filter block (one cache line
-                // for a group of up to 64 lists, read again by the lane at every position of
-                // its window) turns most of those lookups away before the table read
+                // hashed segments and long exact codes rarely match: the group's filter block
+                // (one cache line for a group of up to 64 lists, read again by the lane at every
+                // position of its window) turns most of those lookups away before the table read
                 bool maybe = true;
                 if (use_filter) {
                     const uint64_t hs = table_slot(key);

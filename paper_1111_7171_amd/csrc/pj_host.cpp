@@ -454,8 +454,11 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     hip_check(launch_clear_table(X.table, slots, st), "clear_table");
     hip_check(launch_insert_runs(keys, runstart, nruns, (uint32_t)E, X.table, X.mask, st),
               "insert_runs");
-    if (X.sym.exact_len < kLenMax) {
-        // key filter for hashed segments, blocked by (l, i) group (16 bits per list)
+    // the longest segment (even partition: lengths floor(l / (tau+1)) or one more)
+    const int max_seg = (D.lmax + T1 - 1) / T1;
+    if (max_seg > X.sym.exact_len || max_seg * X.sym.bits >= kFilterMinBits) {
+        // key filter for hashed segments and long exact codes, blocked by (l, i) group (16 bits
+        // per list)
         const uint32_t ngroups = (uint32_t)((D.lmax - T1 + 1) * T1);
         const uint64_t fwords = (uint64_t)nruns + 2ull * ngroups;
         X.filter = (uint32_t*)A.get(nm("filter").c_str(), sizeof(uint32_t) * (size_t)fwords);

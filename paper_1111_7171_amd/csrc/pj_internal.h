@@ -33,6 +33,10 @@ constexpr int kInlineMaxLen = 64;       // longest string the list-segment kerne
 // floor(kHashBits / bits) bytes is keyed by its packed codes (exact: no byte guard); a longer
 // one by a hash of its bytes.  A probe segment with an absent byte packs a 0 code, which no
 // indexed key has.
+// Exact keys of at least this many code bits are also tested against the key filter: their
+// (l, i) groups hold few of the possible codes, so most lookups miss.
+constexpr int kFilterMinBits = 24;
+
 struct SymMap {
     const uint16_t* code = nullptr;   // device [256]
     int bits = 9;
@@ -67,7 +71,8 @@ struct DevIndex {
     // membership filter of the keys, blocked by (l, i) group: group g = key >> 40 owns the
     // words [filter_dir[g], filter_dir[g + 1]) (a power of two of them), in which each of its
     // keys sets two bits; a clear bit proves a key absent without reading the table (long,
-    // hashed segments rarely match).  nullptr when every segment is keyed exactly.
+    // hashed segments and long exact codes rarely match).  nullptr when every segment is
+    // keyed exactly in fewer than kFilterMinBits bits.
     uint32_t* filter = nullptr;
     uint32_t* filter_dir = nullptr;     // [(lmax - tau) * (tau + 1) + 1]
     // inline copies of the members' strings in index order (strings of at most kInlineMaxLen
