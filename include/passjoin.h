@@ -150,8 +150,11 @@ int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pai
  * one window.  Windows are cut greedily so that their strings hold at most window_bytes bytes
  * (at least one length per window).  S and the result are in host memory
  * (opt->inputs_on_device and opt->outputs_on_device must be 0); the result equals
- * pj_self_join's.  pj_last_stats sums the windows' counters.  Errors as pj_self_join, and
- * PJ_EINVAL for window_bytes <= 0. */
+ * pj_self_join's.  The windows' pairs are kept on the device and sorted there once; pairs beyond
+ * a 64th of the device memory free at the first window are sorted and moved to host memory in
+ * batches, which the host merges (the device then holds the current window and one batch).
+ * pj_last_stats sums the windows' counters.  Errors as pj_self_join, and PJ_EINVAL for
+ * window_bytes <= 0. */
 int pj_self_join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes,
                           const pj_options* opt, pj_pairs* out);
 

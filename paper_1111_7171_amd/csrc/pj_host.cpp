@@ -1096,8 +1096,10 @@ static void join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes
         }
         hip_check(hipMemsetAsync(batch.dropped, 0, sizeof(unsigned long long), st), "memset");
     };
-    // sorts the batch on the device; returns the sorted keys (valid ones first) and their count
-    Owned sorted_bufs;
+    // sorts the batch on the device; returns the sorted keys (valid ones first) and their count.
+    // Its buffers are reused by name from one batch to the next (no budget: the windows' own
+    // scratch is the call's budgeted part)
+    Workspace sorted_bufs;
     auto sort_batch = [&](uint64_t* valid_out) -> uint64_t* {
         const uint64_t m = batch.total;
         uint64_t* k0 = (uint64_t*)sorted_bufs.get("stream.k0", sizeof(uint64_t) * (size_t)m);
