@@ -4,6 +4,8 @@
 // phases are HBM/L2-bound streaming (arena packing, index build, radix sort), random-access
 // lookups (probe) and integer-VALU dynamic programming (verification).
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 #include <stdint.h>
 
 #include <algorithm>
@@ -2571,11 +2573,24 @@ hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_row
     const Div div = make_div(V.tau + 1);
     // three count buffers in rotation: pass j reads cnt[j % 3], writes cnt[(j + 1) % 3] and
     // clears cnt[(j + 2) % 3] (read by pass j - 1); the first two start cleared
+    // pass lengths: 16, 16, 32, 64, ..., 512 rows until every part's rows are covered;
+    // PJ_LONG_PASSES (a comma list, the last entry repeated) sets them (tests and tuning; it
+    // changes no result)
+    int sched[16], nsched = 0;
+    if (const char* e = getenv("PJ_LONG_PASSES")) {
+        for (const char* c = e; *c && nsched < 16;) {
+            const int v = atoi(c);
+            if (v < 1 || v > 4096) return hipErrorInvalidValue;
+            sched[nsched++] = v;
+            while (*c && *c != ',') ++c;
+            if (*c == ',') ++c;
+        }
+    }
     for (int side = 0; side < 2; ++side) {
-        // pass lengths 16, 16, 32, 64, ..., 512 rows until every part's rows are covered
         int done = 0, pass = 0;
         while (true) {
-            const int K = pass == 0 ? 16 : std::min(512, 16 << (pass - 1));
+            const int K = nsched ? sched[pass < nsched ? pass : nsched - 1]
+                                 : (pass == 0 ? 16 : std::min(512, 16 << (pass - 1)));
             const bool fresh = pass == 0;
             uint32_t* cin_cnt = cont_cnt[pass % 3];
             uint32_t* cout_cnt = cont_cnt[(pass + 1) % 3];

@@ -74,3 +74,18 @@ def test_long_strings_all_selection_methods(tau):
     jst = P.pj_last_stats()
     assert np.array_equal(jgot, jexp.pairs)
     assert (jst["selected"], jst["candidates"]) == (jexp.selected, jexp.candidates)
+
+
+@pytest.mark.parametrize("passes", ["8,4096", "1,2,3", "64", "16,16,32,64,128,4096"])
+def test_pass_schedules(passes, monkeypatch):
+    """Any schedule of pass lengths (PJ_LONG_PASSES: rows per pass, the last repeated) gives
+    the oracle's pairs, candidates and cells: a pass only decides where a task's rows are cut."""
+    monkeypatch.setenv("PJ_LONG_PASSES", passes)
+    for tau in (5, 24):
+        col = _long_set(900 + tau, 400, tau, lmin=140, lmax=700)
+        _say(f"long strings passes={passes} tau={tau}")
+        exp = O.self_join_pj(col, tau)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        assert np.array_equal(got, exp.pairs), (passes, tau)
+        assert st["candidates"] == exp.candidates and st["cells"] == exp.cells, (passes, tau)
