@@ -273,6 +273,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the timing of hipGraph-replayed self-joins (pj_plan_run)")
     ap.add_argument("--no-e2e", action="store_true",
                     help="skip the end-to-end (host arrays in, host pairs out) timings")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -433,6 +435,33 @@ def main():
                                   "device_resident_ms": per_tau[str(t)]["ms"]}
             log(f"end to end tau={t}: {end_to_end[str(t)]}")
 
+    # the same self-joins replayed from hipGraphs (pj_self_join_plan / pj_plan_run: each tau's
+    # launches captured once, then replayed after a device checksum of the strings), outside the
+    # timed region: median of the replays, beside the eager time of the timed steps
+    graph = {}
+    if not args.window_bytes and not args.no_graph:
+        step_ms = 0.0
+        for t in taus:
+            plan = P.Plan((chars, offs), t, mode=args.mode, stream=stream, tune_cache=cache,
+                          selection=args.selection)
+            plan.run().free()
+            runs = []
+            for _ in range(max(args.steps, 3)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = plan.run()
+                runs.append((time.perf_counter() - t0) * 1e3)
+                if P.pj_last_stats()["replayed"] != 1:
+                    raise RuntimeError("the plan did not replay")
+                r.free()
+            plan.free()
+            ms = float(np.median(runs))
+            graph[str(t)] = {"ms": round(ms, 3), "eager_ms": per_tau[str(t)]["ms"]}
+            step_ms += ms
+            log(f"graph replay tau={t}: {graph[str(t)]}")
+        graph["step_ms"] = round(step_ms, 3)
+        graph["host_syncs_per_call"] = 2
+
     sha = kernel_source_sha()
     # dominant verification kernel: the list-segment kernel (k_verify_segs) when it takes most
     # of the verification time, else candidate by candidate verification -- the long-string
@@ -474,6 +503,7 @@ def main():
         "self_join_ms": {k: v["ms"] for k, v in per_tau.items()},
         "end_to_end_ms": {k: v["ms"] for k, v in end_to_end.items()},
         "end_to_end": end_to_end,
+        "graph_replay": graph,
         "per_tau": per_tau,
         "probe_kernel_ms_per_step": probe_ms / args.steps,
         "verify_kernel_ms_per_step": verify_ms / args.steps,

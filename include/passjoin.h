@@ -136,6 +136,8 @@ typedef struct {
                                   of a content-ordered list instead of being computed (Sec. 5.3) */
     int64_t shared_cells;      /* the cells of those rows (included in cells, which counts every
                                   cell of the method's band; cells - shared_cells were computed) */
+    int64_t replayed;          /* pj_plan_run: 1 if the call replayed the plan's captured graph,
+                                  0 if it ran the self-join anew (the strings had changed) */
 } pj_stats;
 
 /* Self-join (Sec. 2, Algorithm 1): every pair of distinct ids a < b of S with
@@ -157,6 +159,27 @@ int pj_self_join(const pj_strings* S, int32_t tau, const pj_options* opt, pj_pai
  * window_bytes <= 0. */
 int pj_self_join_streamed(const pj_strings* S, int32_t tau, int64_t window_bytes,
                           const pj_options* opt, pj_pairs* out);
+
+/* A prepared self-join of one device-resident string set, for callers that join the same data
+ * repeatedly (the phases of Algorithm 1 as in pj_self_join): its launches are captured once in a
+ * hipGraph and replayed.  pj_self_join_plan runs the self-join of S once (S in device memory:
+ * opt->inputs_on_device = 1), recording the sizes each phase reads back, then captures the same
+ * launches on a stream of the plan's own with device buffers of the plan's own, and records a
+ * checksum of S.  The plan keeps S's pointers and the other options (mode, selection, tune
+ * cache, the stream whose earlier work a run waits for): the caller keeps S's memory valid while
+ * the plan exists.  Memory: the buffers of one self-join of S, held until pj_plan_free.  Errors
+ * as pj_self_join, and PJ_EINVAL for host strings. */
+typedef struct pj_plan pj_plan;
+int pj_self_join_plan(const pj_strings* S, int32_t tau, const pj_options* opt, pj_plan** out);
+
+/* Runs a plan: the result of pj_self_join on S as it is now, in new device arrays
+ * (out->on_device = 1).  First checks on the device that S's offsets and bytes are those the
+ * plan was made from (a checksum; the bytes read are bounded by the allocation measured at plan
+ * time); if so, replays the graph (pj_last_stats() holds the plan's counters, replayed = 1);
+ * otherwise runs the self-join of S anew (replayed = 0).  Two host synchronisations when
+ * replaying.  Calls on one plan must not overlap. */
+int pj_plan_run(pj_plan* plan, pj_pairs* out);
+void pj_plan_free(pj_plan* plan);
 
 /* Join of two sets (Definition 1, Sec. 3.2): every (r, s) with ED(R[r], S[s]) <= tau, sorted by
  * (r, s).  S is indexed and each r probes the lengths |r|-tau .. |r|+tau. */

@@ -23,7 +23,7 @@ __all__ = [
     "pj_index_info", "pj_index_free", "pj_last_error", "pj_last_stats", "pj_version",
     "MODE_AUTO", "MODE_PLAIN", "MODE_BATCHED", "MODE_SHARE_PREFIX", "PJ_TAU_MAX", "PJ_LEN_MAX",
     "Server", "Index",
-    "pj_tune", "pj_query_noalloc", "pj_self_join_host", "HostPairs",
+    "pj_tune", "pj_query_noalloc", "pj_self_join_host", "HostPairs", "Plan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,7 +67,7 @@ class PjStats(C.Structure):
                [("verify_launches", C.c_int64), ("ms_list_kernel", C.c_double),
                 ("list_cells", C.c_int64), ("list_launches", C.c_int64),
                 ("key_collisions", C.c_int64), ("shared_rows", C.c_int64),
-                ("shared_cells", C.c_int64)]
+                ("shared_cells", C.c_int64), ("replayed", C.c_int64)]
 
 
 class PjServerConfig(C.Structure):
@@ -146,6 +146,12 @@ def load():
         lib.pj_query_noalloc.restype = C.c_int
         lib.pj_tune.argtypes = [sp, C.c_int32, op, C.POINTER(PjTuneResult)]
         lib.pj_tune.restype = C.c_int
+        lib.pj_self_join_plan.argtypes = [sp, C.c_int32, op, C.POINTER(C.c_void_p)]
+        lib.pj_self_join_plan.restype = C.c_int
+        lib.pj_plan_run.argtypes = [C.c_void_p, pp]
+        lib.pj_plan_run.restype = C.c_int
+        lib.pj_plan_free.argtypes = [C.c_void_p]
+        lib.pj_plan_free.restype = None
         _lib = lib
     return _lib
 
@@ -310,6 +316,38 @@ def pj_self_join(strings, tau: int, *, mode: int = MODE_AUTO, outputs_on_device:
     raw = PjPairs()
     _check(lib.pj_self_join(C.byref(s.s), int(tau), C.byref(o), C.byref(raw)))
     return _take_pairs(raw, outputs_on_device)
+
+
+class Plan:
+    """pj_self_join_plan / pj_plan_run / pj_plan_free: the self-join of one device-resident
+    string set captured once in a hipGraph and replayed by run() (which checks first that the
+    strings are unchanged, else joins them anew).  The device tensors are kept alive here."""
+
+    def __init__(self, strings, tau: int, *, mode: int = MODE_AUTO, mem_budget: int = 0,
+                 stream=None, tune_cache: str | None = None, selection: int = 0):
+        lib = load()
+        self._s = _Marshalled(strings)
+        if not self._s.on_device:
+            raise PassJoinError(PJ_EINVAL, "a plan takes device strings")
+        o = _options(True, True, mode, mem_budget, stream, tune_cache, selection)
+        self._h = C.c_void_p()
+        _check(lib.pj_self_join_plan(C.byref(self._s.s), int(tau), C.byref(o), C.byref(self._h)))
+
+    def run(self) -> DevicePairs:
+        raw = PjPairs()
+        _check(load().pj_plan_run(self._h, C.byref(raw)))
+        return DevicePairs(raw)
+
+    def free(self):
+        if self._h:
+            load().pj_plan_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def pj_self_join_host(strings, tau: int, *, mode: int = MODE_AUTO, mem_budget: int = 0,

@@ -172,11 +172,21 @@ size_t scan_tmp_bytes(uint64_t n)
     return (size_t)(nb + 1) * sizeof(unsigned long long);
 }
 
+template <typename TO>
+__global__ void k_zero_one(TO* __restrict__ out)
+{
+    if (threadIdx.x == 0) *out = 0;
+}
+
 template <typename TI, typename TO>
 static hipError_t scan_impl(const TI* in, TO* out, uint64_t n, void* tmp, size_t tmp_bytes,
                             hipStream_t s)
 {
-    if (n == 0) return hipMemsetAsync(out, 0, sizeof(TO), s);
+    if (n == 0) {
+        // a kernel, not a memset, so that the call can be captured in a graph
+        hipLaunchKernelGGL((k_zero_one<TO>), dim3(1), dim3(64), 0, s, out);
+        return hipGetLastError();
+    }
     uint64_t nb = (n + kScanTile - 1) / kScanTile;
     if (tmp_bytes < (nb + 1) * sizeof(TO)) return hipErrorInvalidValue;
     TO* partial = (TO*)tmp;
@@ -2928,6 +2938,53 @@ hipError_t launch_split_keys(const uint64_t* keys, uint64_t m, int bbits, int32_
     if (m == 0) return hipSuccess;
     if (bbits < 1 || bbits > 31) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_split_keys, dim3(blocks_for(m)), dim3(kBlock), 0, s, keys, m, bbits, a, b);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_words(uint32_t* __restrict__ p, uint64_t n,
+                                                       uint32_t v)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
+         k += (uint64_t)gridDim.x * kBlock)
+        p[k] = v;
+}
+
+hipError_t launch_fill_words(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<uint64_t>(blocks_for(n), 4096);
+    hipLaunchKernelGGL(k_fill_words, dim3(grid), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Checksum of a device string set: offsets[0 .. n] and bytes[0 .. min(offsets[n], cap)), each
+// element mixed with its index (SplitMix64's finaliser) and summed.  A plan compares it with the
+// value taken when it was made; cap (the bytes allocation measured then) bounds the reads
+// whatever offsets[n] holds now.
+__global__ __launch_bounds__(kBlock) void k_set_checksum(const int32_t* __restrict__ offs, int64_t n,
+                                                         const uint8_t* __restrict__ bytes,
+                                                         int64_t cap,
+                                                         unsigned long long* __restrict__ sum)
+{
+    const int64_t last = offs[n];
+    const int64_t total = bytes ? (last < 0 ? 0 : (last < cap ? last : cap)) : 0;
+    uint64_t acc = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k <= n; k += stride)
+        acc += mix64((uint64_t)(uint32_t)offs[k] ^ ((uint64_t)k << 32) ^ 0x243F6A8885A308D3ull);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += stride)
+        acc += mix64((uint64_t)bytes[k] ^ ((uint64_t)k << 8) ^ 0x13198A2E03707344ull);
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(sum, (unsigned long long)acc);
+}
+
+hipError_t launch_set_checksum(const int32_t* offs, int64_t n, const uint8_t* bytes, int64_t cap,
+                               unsigned long long* sum, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(kBlock), 0, s, (uint32_t*)sum, (uint64_t)2, 0u);
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>(blocks_for((uint64_t)n + 1), 2048));
+    hipLaunchKernelGGL(k_set_checksum, dim3(grid), dim3(kBlock), 0, s, offs, n, bytes, cap, sum);
     return hipGetLastError();
 }
 

@@ -161,6 +161,49 @@ static int bitlen(uint64_t v)
 }
 
 // ------------------------------------------------------------------------------------------
+// Read-backs (recorded by a plan's first run, served from the record while it captures)
+// ------------------------------------------------------------------------------------------
+
+thread_local ReadTape* t_tape = nullptr;
+
+void readback(void* host, const void* dev, size_t bytes, hipStream_t st)
+{
+    if (t_tape && t_tape->replay) {
+        if (t_tape->pos + bytes > t_tape->bytes.size())
+            throw Error(PJ_EDEVICE, "plan record exhausted (the join took another path)");
+        memcpy(host, t_tape->bytes.data() + t_tape->pos, bytes);
+        t_tape->pos += bytes;
+        return;
+    }
+    hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st), "read back");
+    if (t_tape) t_tape->pending.emplace_back(host, bytes);
+}
+
+void sync_readback(hipStream_t st)
+{
+    if (t_tape && t_tape->replay) return;
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (t_tape) {
+        for (const auto& p : t_tape->pending) {
+            const uint8_t* b = (const uint8_t*)p.first;
+            t_tape->bytes.insert(t_tape->bytes.end(), b, b + p.second);
+        }
+        t_tape->pending.clear();
+    }
+}
+
+void upload(void* dev, const void* host, size_t bytes, hipStream_t st)
+{
+    if (t_tape && t_tape->replay) return;
+    hip_check(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st), "upload");
+}
+
+void zero_words(void* dev, size_t bytes, hipStream_t st)
+{
+    hip_check(launch_fill_words((uint32_t*)dev, (uint64_t)(bytes / 4), 0u, st), "fill");
+}
+
+// ------------------------------------------------------------------------------------------
 // Timing
 // ------------------------------------------------------------------------------------------
 
@@ -173,6 +216,7 @@ Timer::~Timer()
 
 int Timer::mark()
 {
+    if (t_tape && t_tape->replay) return -1;
     hipEvent_t e;
     hip_check(hipEventCreate(&e), "hipEventCreate");
     hip_check(hipEventRecord(e, st), "hipEventRecord");
@@ -182,6 +226,7 @@ int Timer::mark()
 
 double Timer::ms(int a, int b)
 {
+    if (a < 0 || b < 0) return 0.0;
     float v = 0.f;
     hip_check(hipEventSynchronize(evs[b]), "hipEventSynchronize");
     hip_check(hipEventElapsedTime(&v, evs[a], evs[b]), "hipEventElapsedTime");
@@ -269,16 +314,13 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
 
     // length histogram (+ validation of device inputs)
     int32_t* lcount = (int32_t*)A.get(nm("lcount").c_str(), sizeof(int32_t) * (kLenTab + 1));
-    hip_check(hipMemsetAsync(lcount, 0, sizeof(int32_t) * (kLenTab + 1), st), "memset");
+    zero_words(lcount, sizeof(int32_t) * (kLenTab + 1), st);
     hip_check(launch_length_hist(d_offs, n, lcount, lcount + kLenTab, st), "length_hist");
     std::vector<int32_t> h(kLenTab + 1);
     int32_t dev_total = 0;
-    hip_check(hipMemcpyAsync(h.data(), lcount, sizeof(int32_t) * (kLenTab + 1),
-                             hipMemcpyDeviceToHost, st), "download lcount");
-    if (on_device && n > 0)
-        hip_check(hipMemcpyAsync(&dev_total, d_offs + n, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                 st), "download offsets[n]");
-    hip_check(hipStreamSynchronize(st), "sync");
+    readback(h.data(), lcount, sizeof(int32_t) * (kLenTab + 1), st);
+    if (on_device && n > 0) readback(&dev_total, d_offs + n, sizeof(int32_t), st);
+    sync_readback(st);
     int err = h[kLenTab];
     if (err & 1) throw Error(PJ_EINVAL, "%s: offsets[0] != 0", tag.c_str());
     if (err & 2) throw Error(PJ_EINVAL, "%s: offsets decrease", tag.c_str());
@@ -311,10 +353,8 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
 
     D.lenstart = (int32_t*)A.get(nm("lenstart").c_str(), sizeof(int32_t) * (kLenTab + 1));
     D.gbase = (int64_t*)A.get(nm("gbase").c_str(), sizeof(int64_t) * kLenTab);
-    hip_check(hipMemcpyAsync(D.lenstart, D.h_lenstart, sizeof(int32_t) * (kLenTab + 1),
-                             hipMemcpyHostToDevice, st), "upload lenstart");
-    hip_check(hipMemcpyAsync(D.gbase, D.h_gbase, sizeof(int64_t) * kLenTab,
-                             hipMemcpyHostToDevice, st), "upload gbase");
+    upload(D.lenstart, D.h_lenstart, sizeof(int32_t) * (kLenTab + 1), st);
+    upload(D.gbase, D.h_gbase, sizeof(int64_t) * kLenTab, st);
 
     D.perm = (int32_t*)A.get(nm("perm").c_str(), sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     D.slen = (uint16_t*)A.get(nm("slen").c_str(), sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1));
@@ -359,19 +399,19 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
         // symbol map of the bytes the set contains: codes 1..sigma, 0 for absent bytes
         Workspace& WS = thread_workspace();
         uint32_t* bm = (uint32_t*)WS.get("index.bytemap", 8 * sizeof(uint32_t));
-        hip_check(hipMemsetAsync(bm, 0, 8 * sizeof(uint32_t), st), "memset");
+        zero_words(bm, 8 * sizeof(uint32_t), st);
         hip_check(launch_byte_presence(D, bm, st), "byte_presence");
         uint32_t hb[8];
-        hip_check(hipMemcpyAsync(hb, bm, sizeof hb, hipMemcpyDeviceToHost, st), "bytemap");
-        hip_check(hipStreamSynchronize(st), "sync");
+        readback(hb, bm, sizeof hb, st);
+        sync_readback(st);
         uint16_t code[256];
         int sigma = 0;
         for (int b = 0; b < 256; ++b)
             code[b] = (hb[b >> 5] >> (b & 31)) & 1u ? (uint16_t)(++sigma) : (uint16_t)0;
         const int sbits = std::max(1, bitlen((uint64_t)sigma));
         uint16_t* dcode = (uint16_t*)A.get(nm("sym").c_str(), sizeof code);
-        hip_check(hipMemcpyAsync(dcode, code, sizeof code, hipMemcpyHostToDevice, st), "upload sym");
-        hip_check(hipStreamSynchronize(st), "sync");
+        upload(dcode, code, sizeof code, st);
+        sync_readback(st);                  // code[] is on this stack frame
         X.sym = SymMap{dcode, sbits, kHashBits / sbits};
     }
     if (E == 0) {
@@ -391,8 +431,7 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     }
     Workspace& W = thread_workspace();
     int64_t* d_ebase = (int64_t*)W.get("index.ebase", sizeof(int64_t) * kLenTab);
-    hip_check(hipMemcpyAsync(d_ebase, ebase.data(), sizeof(int64_t) * kLenTab,
-                             hipMemcpyHostToDevice, st), "upload ebase");
+    upload(d_ebase, ebase.data(), sizeof(int64_t) * kLenTab, st);
     uint64_t* keys = (uint64_t*)A.get(nm("keys").c_str(), sizeof(uint64_t) * (size_t)E);
     uint32_t* vals = (uint32_t*)A.get(nm("vals").c_str(), sizeof(uint32_t) * (size_t)E);
     uint64_t* keys2 = (uint64_t*)W.get("index.keys2", sizeof(uint64_t) * (size_t)E);
@@ -427,8 +466,7 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
         if (A.budget == 0 || (long long)(A.used + need) <= A.budget) {
             X.inl = (uint8_t*)A.get(nm("inl").c_str(), (size_t)std::max<int64_t>(bytes, 16));
             X.inl_base = (int64_t*)A.get(nm("inl_base").c_str(), sizeof(int64_t) * kLenTab);
-            hip_check(hipMemcpyAsync(X.inl_base, inl_base.data(), sizeof(int64_t) * kLenTab,
-                                     hipMemcpyHostToDevice, st), "upload inl_base");
+            upload(X.inl_base, inl_base.data(), sizeof(int64_t) * kLenTab, st);
             hip_check(launch_gather_inline(D, keys, vals, E, tau, X.inl_base, X.inl, st),
                       "gather_inline");
         }
@@ -441,9 +479,8 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
     void* stmp = W.get("scan.tmp", sb);
     hip_check(scan_u32_to_u32(flags, runid, (uint64_t)E, stmp, sb, st), "scan(runs)");
     uint32_t nruns = 0;
-    hip_check(hipMemcpyAsync(&nruns, runid + E, sizeof(uint32_t), hipMemcpyDeviceToHost, st),
-              "download nruns");
-    hip_check(hipStreamSynchronize(st), "sync");
+    readback(&nruns, runid + E, sizeof(uint32_t), st);
+    sync_readback(st);
     X.lists = nruns;
     uint32_t* runstart = (uint32_t*)W.get("index.runstart", sizeof(uint32_t) * (size_t)(nruns + 1));
     hip_check(launch_scatter_runstart(flags, runid, E, runstart, st), "runstart");
@@ -467,9 +504,9 @@ void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, Dev
         uint32_t* gfirst = (uint32_t*)W.get("index.gfirst", sizeof(uint32_t) * (size_t)ngroups);
         uint32_t* gend = (uint32_t*)W.get("index.gend", sizeof(uint32_t) * (size_t)ngroups);
         uint32_t* words = (uint32_t*)W.get("index.fwords", sizeof(uint32_t) * (size_t)ngroups);
-        hip_check(hipMemsetAsync(gfirst, 0, sizeof(uint32_t) * (size_t)ngroups, st), "memset");
-        hip_check(hipMemsetAsync(gend, 0, sizeof(uint32_t) * (size_t)ngroups, st), "memset");
-        hip_check(hipMemsetAsync(X.filter, 0, sizeof(uint32_t) * (size_t)fwords, st), "memset");
+        zero_words(gfirst, sizeof(uint32_t) * (size_t)ngroups, st);
+        zero_words(gend, sizeof(uint32_t) * (size_t)ngroups, st);
+        zero_words(X.filter, sizeof(uint32_t) * (size_t)fwords, st);
         const size_t fsb = scan_tmp_bytes(ngroups);
         void* fst = W.get("scan.tmp", std::max(fsb, sb));
         hip_check(launch_filter_build(keys, runstart, nruns, ngroups, gfirst, gend, words, fst, fsb,
@@ -538,8 +575,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     const int T1 = tau + 1;
     J.counters = (unsigned long long*)W.get("join.counters",
                                             kJoinCounters * sizeof(unsigned long long));
-    hip_check(hipMemsetAsync(J.counters, 0, kJoinCounters * sizeof(unsigned long long), st),
-              "memset");
+    zero_words(J.counters, kJoinCounters * sizeof(unsigned long long), st);
     int64_t probe_first = 0;
     uint64_t bound = spec.q_tau ? spec.bound
                                 : selection_bound(P, Y, tau, self, &probe_first,
@@ -557,8 +593,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     for (int attempt = 0; attempt < 2; ++attempt) {
     J.hits = (Hit*)W.get("join.hits", sizeof(Hit) * (size_t)hit_cap);
     if (attempt > 0)
-        hip_check(hipMemsetAsync(J.counters, 0, kJoinCounters * sizeof(unsigned long long), st),
-                  "memset");
+        zero_words(J.counters, kJoinCounters * sizeof(unsigned long long), st);
     if (nprobe > 0 && bound > 0 && entries) {
         ProbeParams pp{};
         pp.x_arena = P.sarena; pp.x_slen = P.slen; pp.x_lenstart = P.lenstart; pp.x_gbase = P.gbase;
@@ -586,8 +621,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         int k1 = tm.mark();
         J.kernel_marks.push_back({k0, k1, 0});
     }
-    hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
-    hip_check(hipStreamSynchronize(st), "sync");
+    readback(c, J.counters, sizeof c, st);
+    sync_readback(st);
     if (c[0] <= hit_cap) break;
     hit_cap = c[0];
     J.kernel_marks.clear();
@@ -622,9 +657,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                                      bb_off, stmp, sb, sorted, st), "slot_bucket");
         J.hits = sorted;
         uint32_t ns = 0;
-        hip_check(hipMemcpyAsync(&ns, bb_off + (size_t)g * 64, sizeof ns, hipMemcpyDeviceToHost,
-                                 st), "small-list hits");
-        hip_check(hipStreamSynchronize(st), "sync");
+        readback(&ns, bb_off + (size_t)g * 64, sizeof ns, st);
+        sync_readback(st);
         nsmall = ns;
         nbig = J.nhits - nsmall;
     }
@@ -655,12 +689,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         void* stmp = W.get("scan.tmp2", sb);
         hip_check(scan_u32_to_u64(chains, cprefix, nbig, stmp, sb, st), "scan(chains)");
         unsigned long long cs = 0, nc = 0;
-        hip_check(hipMemcpyAsync(&nc, cprefix + nbig, sizeof nc, hipMemcpyDeviceToHost, st),
-                  "nchains");
-        if (nsmall > 0)
-            hip_check(hipMemcpyAsync(&cs, J.prefix + nsmall, sizeof cs, hipMemcpyDeviceToHost, st),
-                      "ncand small");
-        hip_check(hipStreamSynchronize(st), "sync");
+        readback(&nc, cprefix + nbig, sizeof nc, st);
+        if (nsmall > 0) readback(&cs, J.prefix + nsmall, sizeof cs, st);
+        sync_readback(st);
         nchains = nc;
         ncand_small = cs;
     } else if (nbig > 0) {
@@ -674,11 +705,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         hip_check(scan_u32_to_u32(segs, segp, nbig, stmp, sb, st), "scan(segs)");
         uint32_t ns = 0;
         unsigned long long cs = 0;
-        hip_check(hipMemcpyAsync(&ns, segp + nbig, sizeof ns, hipMemcpyDeviceToHost, st), "nseg");
-        if (nsmall > 0)
-            hip_check(hipMemcpyAsync(&cs, J.prefix + nsmall, sizeof cs, hipMemcpyDeviceToHost, st),
-                      "ncand small");
-        hip_check(hipStreamSynchronize(st), "sync");
+        readback(&ns, segp + nbig, sizeof ns, st);
+        if (nsmall > 0) readback(&cs, J.prefix + nsmall, sizeof cs, st);
+        sync_readback(st);
         nseg = ns;
         ncand_small = cs;
     }
@@ -687,8 +716,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
     uint64_t cap = std::min<uint64_t>(J.ncand + 4096, 1ull << 28);
     for (int attempt = 0; attempt < 2; ++attempt) {
         J.out = (uint64_t*)W.get("join.out", sizeof(uint64_t) * (size_t)cap);
-        hip_check(hipMemsetAsync(J.counters + 3, 0, (kJoinCounters - 3) * sizeof(unsigned long long),
-                                 st), "memset");
+        zero_words(J.counters + 3, (kJoinCounters - 3) * sizeof(unsigned long long), st);
         J.kernel_marks.erase(std::remove_if(J.kernel_marks.begin(), J.kernel_marks.end(),
                                             [](const JoinScratch::Mark& m) { return m.kind != 0; }),
                              J.kernel_marks.end());
@@ -785,8 +813,8 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         }
         hip_check(launch_short_path(P, Y, tau, self ? 1 : 0, spec.q_tau, J.out, cap, J.counters,
                                     st), "short_path");
-        hip_check(hipMemcpyAsync(c, J.counters, sizeof c, hipMemcpyDeviceToHost, st), "counters");
-        hip_check(hipStreamSynchronize(st), "sync");
+        readback(c, J.counters, sizeof c, st);
+        sync_readback(st);
         if (c[3] <= cap) break;
         cap = c[3];
     }
@@ -844,8 +872,8 @@ uint64_t finish_pairs(const DevSet& P, const DevSet& Y, bool self, const uint64_
     hip_check(scan_u32_to_u32(flags, pos, m, stmp, sb, st), "scan(unique)");
     hip_check(launch_compact_pairs(ks, flags, pos, m, bbits, a, b, st), "compact");
     uint32_t M = 0;
-    hip_check(hipMemcpyAsync(&M, pos + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st), "count");
-    hip_check(hipStreamSynchronize(st), "sync");
+    readback(&M, pos + m, sizeof(uint32_t), st);
+    sync_readback(st);
     return M;
 }
 
@@ -965,9 +993,17 @@ static double mean_length(const DevSet& D)
     return sum / (double)D.n;
 }
 
+// A plan's run of the join stops before the result is copied out: the sorted pairs stay in the
+// workspace (the plan's own) and their count is returned here.
+struct PlanOut {
+    int32_t* a = nullptr;
+    int32_t* b = nullptr;
+    uint64_t M = 0;
+};
+
 static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_options* opt,
                       pj_pairs* out, bool self, const TuneParams* force = nullptr,
-                      int probe_min_len = 0)
+                      int probe_min_len = 0, PlanOut* po = nullptr)
 {
     if (!out) throw Error(PJ_EINVAL, "null output");
     zero_pairs(out);
@@ -1014,7 +1050,13 @@ static void join_impl(const pj_strings* R, const pj_strings* S, int32_t tau, con
     int e3 = tm.mark();
     int32_t *da = nullptr, *db = nullptr;
     uint64_t M = finish_pairs(P, YY, self, J.out, J.naccepted, &da, &db, st);
-    emit_output(da, db, M, opt && opt->outputs_on_device, out, st);
+    if (po) {
+        po->a = da;
+        po->b = db;
+        po->M = M;
+    } else {
+        emit_output(da, db, M, opt && opt->outputs_on_device, out, st);
+    }
     int e4 = tm.mark();
     t_stats.pairs = (int64_t)M;
     t_stats.ms_upload = tm.ms(e0, e1);
@@ -1292,6 +1334,176 @@ int self_join_with(const pj_strings* S, int32_t tau, const pj_options* opt, pj_p
     return guarded(out, [&] { join_impl(nullptr, S, tau, opt, out, true, force); });
 }
 
+// ------------------------------------------------------------------------------------------
+// Plans: a self-join's launches captured once in a hipGraph and replayed
+// ------------------------------------------------------------------------------------------
+
+// Makes w the calling thread's workspace for the scope (a plan's buffers are its own).
+struct WorkspaceScope {
+    Workspace* saved;
+    explicit WorkspaceScope(Workspace* w) : saved(t_ws) { t_ws = w; }
+    ~WorkspaceScope() { t_ws = saved; }
+};
+
+struct TapeScope {
+    ReadTape* saved;
+    explicit TapeScope(ReadTape* t) : saved(t_tape) { t_tape = t; }
+    ~TapeScope() { t_tape = saved; }
+};
+
+}  // namespace pj
+
+struct pj_plan {
+    pj::Workspace ws;                   // destroyed last: the graph refers to its buffers
+    hipStream_t st = nullptr;           // the plan's stream (captured, replayed)
+    hipEvent_t ev = nullptr;            // orders the plan's stream after the caller's
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long* d_sum = nullptr;
+    pj_strings S{};
+    int32_t tau = 0;
+    pj_options opt{};                   // the caller's options, outputs in device memory
+    std::string tune_cache;             // the caller's tune cache path (opt points here)
+    hipStream_t user_st = nullptr;
+    int64_t bytes_cap = 0;              // the bytes allocation of S, measured at plan time
+    unsigned long long sum = 0;         // checksum of S at plan time
+    int32_t* da = nullptr;              // the captured join's sorted pairs (in ws)
+    int32_t* db = nullptr;
+    uint64_t M = 0;
+    pj_stats stats{};                   // counters of the recorded run
+    ~pj_plan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_sum) (void)hipFree(d_sum);
+        if (ev) (void)hipEventDestroy(ev);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+namespace pj {
+
+static unsigned long long plan_checksum(pj_plan* p)
+{
+    hip_check(launch_set_checksum(p->S.offsets, p->S.n, p->S.bytes, p->bytes_cap, p->d_sum, p->st),
+              "checksum");
+    unsigned long long v = 0;
+    hip_check(hipMemcpyAsync(&v, p->d_sum, sizeof v, hipMemcpyDeviceToHost, p->st), "checksum");
+    hip_check(hipStreamSynchronize(p->st), "sync");
+    return v;
+}
+
+static void plan_make(const pj_strings* S, int32_t tau, const pj_options* opt, pj_plan* p)
+{
+    if (!S) throw Error(PJ_EINVAL, "null pj_strings");
+    if (!opt || !opt->inputs_on_device)
+        throw Error(PJ_EINVAL, "a plan takes device strings (opt->inputs_on_device = 1)");
+    check_tau(tau);
+    p->S = *S;
+    p->tau = tau;
+    p->opt = *opt;
+    p->opt.outputs_on_device = 1;
+    if (opt->tune_cache) {
+        p->tune_cache = opt->tune_cache;
+        p->opt.tune_cache = p->tune_cache.c_str();
+    }
+    p->user_st = stream_of(opt);
+    hip_check(hipStreamCreateWithFlags(&p->st, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming), "hipEventCreate");
+    if (hipMalloc((void**)&p->d_sum, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        p->d_sum = nullptr;
+        throw Error(PJ_ENOMEM, "plan: checksum buffer");
+    }
+    hip_check(hipEventRecord(p->ev, p->user_st), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(p->st, p->ev, 0), "hipStreamWaitEvent");
+    pj_options o = p->opt;
+    o.hip_stream = p->st;
+    WorkspaceScope ws(&p->ws);
+    ReadTape tape;
+    TapeScope ts(&tape);
+    // 1. the self-join, recording what each phase reads back (it validates S)
+    pj_pairs unused{};
+    PlanOut rec;
+    join_impl(nullptr, S, tau, &o, &unused, true, nullptr, 0, &rec);
+    p->stats = t_stats;
+    p->da = rec.a;
+    p->db = rec.b;
+    p->M = rec.M;
+    // 2. the same launches captured: every read-back is served from the record
+    tape.replay = true;
+    tape.pos = 0;
+    hip_check(hipStreamBeginCapture(p->st, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    PlanOut cap;
+    try {
+        join_impl(nullptr, S, tau, &o, &unused, true, nullptr, 0, &cap);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(p->st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        throw;
+    }
+    hip_check(hipStreamEndCapture(p->st, &p->graph), "hipStreamEndCapture");
+    t_stats = p->stats;                 // the captured run added its (equal) counts again
+    if (cap.a != rec.a || cap.b != rec.b || cap.M != rec.M || tape.pos != tape.bytes.size())
+        throw Error(PJ_EDEVICE, "plan: the captured join differs from the recorded one");
+    hip_check(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    // 3. the checksum of S the runs compare with (its bytes bounded by their allocation)
+    p->bytes_cap = 0;
+    if (S->bytes) {
+        hipPointerAttribute_t attr{};
+        void* base = nullptr;
+        size_t size = 0;
+        if (hipPointerGetAttributes(&attr, S->bytes) == hipSuccess &&
+            hipMemGetAddressRange(&base, &size, const_cast<uint8_t*>(S->bytes)) == hipSuccess &&
+            base)
+            p->bytes_cap = (int64_t)(size - (size_t)((const uint8_t*)S->bytes - (const uint8_t*)base));
+        (void)hipGetLastError();
+    }
+    p->sum = plan_checksum(p);
+}
+
+static void plan_run(pj_plan* p, pj_pairs* out)
+{
+    if (!p) throw Error(PJ_EINVAL, "null plan");
+    if (!out) throw Error(PJ_EINVAL, "null output");
+    zero_pairs(out);
+    const auto t0 = std::chrono::steady_clock::now();
+    hip_check(hipEventRecord(p->ev, p->user_st), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(p->st, p->ev, 0), "hipStreamWaitEvent");
+    if (plan_checksum(p) != p->sum) {
+        // S changed since the plan was made: the self-join of S as it is now
+        join_impl(nullptr, &p->S, p->tau, &p->opt, out, true);
+        t_stats.replayed = 0;
+        return;
+    }
+    hip_check(hipGraphLaunch(p->exec, p->st), "hipGraphLaunch");
+    const size_t bytes = sizeof(int32_t) * (size_t)std::max<uint64_t>(p->M, 1);
+    void *pa = nullptr, *pb = nullptr;
+    if (hipMalloc(&pa, bytes) != hipSuccess || hipMalloc(&pb, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (pa) (void)hipFree(pa);
+        (void)hipStreamSynchronize(p->st);
+        throw Error(PJ_ENOMEM, "output allocation failed");
+    }
+    out->on_device = 1;
+    out->a = (int32_t*)pa;
+    out->b = (int32_t*)pb;
+    out->count = (int64_t)p->M;
+    if (p->M) {
+        hip_check(hipMemcpyAsync(pa, p->da, sizeof(int32_t) * p->M, hipMemcpyDeviceToDevice, p->st),
+                  "out");
+        hip_check(hipMemcpyAsync(pb, p->db, sizeof(int32_t) * p->M, hipMemcpyDeviceToDevice, p->st),
+                  "out");
+    }
+    hip_check(hipStreamSynchronize(p->st), "sync");
+    t_stats = p->stats;
+    t_stats.replayed = 1;
+    t_stats.ms_total = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+}
+
 }  // namespace pj
 
 using namespace pj;
@@ -1319,6 +1531,38 @@ int pj_join(const pj_strings* R, const pj_strings* S, int32_t tau, const pj_opti
         if (!R || !S) throw Error(PJ_EINVAL, "null pj_strings");
         join_impl(R, S, tau, opt, out, false);
     });
+}
+
+int pj_self_join_plan(const pj_strings* S, int32_t tau, const pj_options* opt, pj_plan** out)
+{
+    if (!out) {
+        t_last_error = "null plan output";
+        return PJ_EINVAL;
+    }
+    *out = nullptr;
+    auto* p = new (std::nothrow) pj_plan();
+    if (!p) {
+        t_last_error = "host allocation failed";
+        return PJ_ENOMEM;
+    }
+    const int rc = guarded(nullptr, [&] { plan_make(S, tau, opt, p); });
+    if (rc != PJ_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return PJ_OK;
+}
+
+int pj_plan_run(pj_plan* plan, pj_pairs* out)
+{
+    return guarded(out, [&] { plan_run(plan, out); });
+}
+
+void pj_plan_free(pj_plan* plan)
+{
+    if (plan) (void)hipStreamSynchronize(plan->st);
+    delete plan;
 }
 
 void pj_pairs_free(pj_pairs* p)

@@ -52,7 +52,26 @@ struct Owned : Alloc {
 Workspace& thread_workspace();
 int device_cus();
 
-// hipEvent marks on one stream.
+// Values the host reads back from the device to size the next phase.  A self-join plan
+// (pj_plan.cpp) runs the join once recording them in order, then captures the same sequence of
+// launches in a graph: while it captures, every read is served from the record, and nothing is
+// read back, uploaded or synchronised (the plan's own buffers already hold the uploaded tables).
+struct ReadTape {
+    bool replay = false;
+    std::vector<uint8_t> bytes;
+    size_t pos = 0;
+    std::vector<std::pair<void*, size_t>> pending;   // reads enqueued before the next sync
+};
+extern thread_local ReadTape* t_tape;
+// device -> host read, complete after the next sync_readback
+void readback(void* host, const void* dev, size_t bytes, hipStream_t st);
+void sync_readback(hipStream_t st);
+// host table -> device
+void upload(void* dev, const void* host, size_t bytes, hipStream_t st);
+// device memory = 0 with a kernel (bytes a multiple of 4)
+void zero_words(void* dev, size_t bytes, hipStream_t st);
+
+// hipEvent marks on one stream (none while a plan's graph is captured).
 struct Timer {
     hipStream_t st;
     std::vector<hipEvent_t> evs;

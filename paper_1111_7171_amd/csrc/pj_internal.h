@@ -285,6 +285,11 @@ hipError_t launch_window_keys(const int32_t* a, const int32_t* b, uint64_t m, co
                               unsigned long long* dropped, hipStream_t s);
 hipError_t launch_split_keys(const uint64_t* keys, uint64_t m, int bbits, int32_t* a, int32_t* b,
                              hipStream_t s);
+// p[0 .. n) = v (a kernel: capturable in a graph, unlike a memset node)
+hipError_t launch_fill_words(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// *sum = checksum of the device string set (offsets[0..n], bytes[0..min(offsets[n], cap)))
+hipError_t launch_set_checksum(const int32_t* offs, int64_t n, const uint8_t* bytes, int64_t cap,
+                               unsigned long long* sum, hipStream_t s);
 hipError_t launch_gather_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
                              hipStream_t s);
 

@@ -131,3 +131,25 @@ def test_binding_rejects_mixed_host_and_device_arrays():
     chars = torch.from_numpy(np.frombuffer(b"abcabc", np.uint8).copy())
     offs = torch.tensor([0, 3, 6], dtype=torch.int32)
     assert _err(P.pj_self_join, (chars, FakeDev(offs)), 1) == P.PJ_EINVAL
+
+
+def test_plan_rejects_host_strings_and_null_arguments():
+    """pj_self_join_plan takes device strings only (refused before any device work) and checks
+    its pointer arguments; pj_plan_run and pj_plan_free accept no plan / a null plan."""
+    lib = P.load()
+    chars = np.frombuffer(b"abcabc", np.uint8).copy()
+    offs = np.array([0, 3, 6], np.int32)
+    s = P.PjStrings(2, chars.ctypes.data, offs.ctypes.data)
+    h = C.c_void_p()
+    assert lib.pj_self_join_plan(C.byref(s), 1, None, C.byref(h)) == P.PJ_EINVAL
+    assert not h.value
+    o = P.PjOptions()
+    assert lib.pj_self_join_plan(C.byref(s), 1, C.byref(o), C.byref(h)) == P.PJ_EINVAL
+    assert "device" in P.pj_last_error() and not h.value
+    assert lib.pj_self_join_plan(C.byref(s), 1, C.byref(o), None) == P.PJ_EINVAL
+    assert lib.pj_self_join_plan(None, 1, C.byref(o), C.byref(h)) == P.PJ_EINVAL
+    raw = P.PjPairs()
+    assert lib.pj_plan_run(None, C.byref(raw)) == P.PJ_EINVAL and raw.count == 0
+    lib.pj_plan_free(None)
+    with pytest.raises(P.PassJoinError):
+        P.Plan((chars, offs), 1)
