@@ -879,13 +879,20 @@ constexpr uint64_t kWaveChunk = 64ull * kWaveRounds;
 
 // Bucket of a hit: lists with at least `big` candidates after all smaller ones, each part in
 // slot order.
+// Bucket of a hit: small lists by slot (0..63); big lists by the length class of their strings
+// (at most kLenClass0, at most kLenClass1, longer; so that each class is verified by the
+// list-segment kernel with the lane-slot class its strings fit), then by slot (64..255).
 __device__ inline uint32_t hit_bucket(const Hit& v, uint32_t big)
 {
-    return ((v.count >= big) ? 64u : 0u) + ((v.meta >> 11) & 63u);
+    const uint32_t slot = (v.meta >> 11) & 63u;
+    if (v.count < big) return slot;
+    const uint32_t l = v.meta >> 17;
+    const uint32_t lc = l <= (uint32_t)kLenClass0 ? 0u : (l <= (uint32_t)kLenClass1 ? 1u : 2u);
+    return 64u + lc * 64u + slot;
 }
 
 // Bucketing of the hits in two passes without global atomics: bb[b * G + blk] = hits of
-// bucket b that block blk meets in its grid-stride walk (G blocks, 128 buckets); after an
+// bucket b that block blk meets in its grid-stride walk (G blocks, kBuckets buckets); after an
 // exclusive scan of bb (bucket-major), the scatter pass walks the same hits in the same order
 // and places each at its block's offset in its bucket plus a rank from LDS counters.  The
 // regions come out in bucket order; order inside a region changes nothing downstream (the
@@ -894,15 +901,16 @@ __global__ __launch_bounds__(kBlock) void k_slot_hist(const Hit* __restrict__ hi
                                                       const unsigned long long* __restrict__ nh_dev,
                                                       uint32_t big, uint32_t* __restrict__ bb)
 {
-    __shared__ uint32_t h[128];
-    if (threadIdx.x < 128) h[threadIdx.x] = 0;
+    __shared__ uint32_t h[kHitBuckets];
+    for (int b = threadIdx.x; b < kHitBuckets; b += kBlock) h[b] = 0;
     __syncthreads();
     const uint64_t nh = *nh_dev;
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < nh;
          k += (uint64_t)gridDim.x * kBlock)
         atomicAdd(&h[hit_bucket(hits[k], big)], 1u);
     __syncthreads();
-    if (threadIdx.x < 128) bb[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    for (int b = threadIdx.x; b < kHitBuckets; b += kBlock)
+        bb[(uint64_t)b * gridDim.x + blockIdx.x] = h[b];
 }
 
 __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__ hits,
@@ -911,11 +919,12 @@ __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__
                                                          const uint32_t* __restrict__ bb_off,
                                                          Hit* __restrict__ out)
 {
-    __shared__ uint32_t run[128], cnt[128];
-    if (threadIdx.x < 128) run[threadIdx.x] = bb_off[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    __shared__ uint32_t run[kHitBuckets], cnt[kHitBuckets];
+    for (int b = threadIdx.x; b < kHitBuckets; b += kBlock)
+        run[b] = bb_off[(uint64_t)b * gridDim.x + blockIdx.x];
     const uint64_t nh = *nh_dev;
     for (uint64_t k0 = (uint64_t)blockIdx.x * kBlock; k0 < nh; k0 += (uint64_t)gridDim.x * kBlock) {
-        if (threadIdx.x < 128) cnt[threadIdx.x] = 0;
+        for (int b = threadIdx.x; b < kHitBuckets; b += kBlock) cnt[b] = 0;
         __syncthreads();
         const uint64_t k = k0 + threadIdx.x;
         Hit v{};
@@ -928,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void k_slot_scatter(const Hit* __restrict__
         __syncthreads();
         if (k < nh) out[run[sl] + rank] = v;
         __syncthreads();
-        if (threadIdx.x < 128) run[threadIdx.x] += cnt[threadIdx.x];
+        for (int b = threadIdx.x; b < kHitBuckets; b += kBlock) run[b] += cnt[b];
     }
 }
 
@@ -2402,7 +2411,8 @@ hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev,
     if (nh_cap == 0) return hipSuccess;
     const unsigned grid = slot_bucket_grid(nh_cap);
     hipLaunchKernelGGL(k_slot_hist, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, bb);
-    hipError_t e = scan_u32_to_u32(bb, bb_off, (uint64_t)grid * 128, scan_tmp, scan_bytes, s);
+    hipError_t e = scan_u32_to_u32(bb, bb_off, (uint64_t)grid * kHitBuckets, scan_tmp, scan_bytes,
+                                   s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_slot_scatter, dim3(grid), dim3(kBlock), 0, s, hits, nh_dev, big, bb_off,
                        out);

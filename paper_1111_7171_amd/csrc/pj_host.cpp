@@ -637,17 +637,20 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                                        (unsigned long long)J.nhits, (unsigned long long)hit_cap);
 
     const bool batched = J.mode != PJ_MODE_PLAIN;
-    // batched: hits bucketed into [lists with < big_list candidates | the others], each part
-    // in slot order; small lists are verified candidate by candidate, big ones a 64-member
-    // segment per wave
-    uint64_t nsmall = J.nhits, nbig = 0, ncand_small = J.ncand, nseg = 0;
-    uint32_t* segp = nullptr;
+    // batched: hits bucketed into [lists with < big_list candidates | the others by the length
+    // class of their strings], each part in slot order; small lists are verified candidate by
+    // candidate, big ones a 64-member segment per wave, one launch per length class (so that
+    // lists of short strings take the lane-slot kernels even when the set has long strings)
+    uint64_t nsmall = J.nhits, nbig = 0, ncand_small = J.ncand;
+    uint64_t cls_off[kLenClasses + 1] = {};    // big hits of class c: [cls_off[c], cls_off[c+1])
+    uint64_t cls_nseg[kLenClasses] = {};
+    uint32_t* segp = nullptr;                  // class c's scan at segp + cls_off[c] + c
     // few candidates (a serving batch): the bucketing round trips would cost more than they save
     uint64_t bucket_min = kBucketMinCandidates;
     if (const char* e = getenv("PJ_BUCKET_MIN_CANDIDATES")) bucket_min = strtoull(e, nullptr, 10);
     if (batched && J.nhits > 0 && J.ncand >= bucket_min) {
         const unsigned g = slot_bucket_grid(J.nhits);
-        const size_t nbb = (size_t)g * 128;
+        const size_t nbb = (size_t)g * kHitBuckets;
         uint32_t* bb = (uint32_t*)W.get("join.bb", sizeof(uint32_t) * nbb);
         uint32_t* bb_off = (uint32_t*)W.get("join.bb_off", sizeof(uint32_t) * (nbb + 1));
         const size_t sb = scan_tmp_bytes(nbb);
@@ -656,11 +659,17 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, (uint32_t)J.tp.big_list, bb,
                                      bb_off, stmp, sb, sorted, st), "slot_bucket");
         J.hits = sorted;
-        uint32_t ns = 0;
-        readback(&ns, bb_off + (size_t)g * 64, sizeof ns, st);
+        // bucket 64 * (c + 1) opens length class c of the big lists
+        uint32_t start[kLenClasses] = {};
+        for (int c = 0; c < kLenClasses; ++c)
+            readback(&start[c], bb_off + (size_t)g * 64 * (c + 1), sizeof(uint32_t), st);
         sync_readback(st);
-        nsmall = ns;
+        nsmall = start[0];
         nbig = J.nhits - nsmall;
+        for (int c = 0; c < kLenClasses; ++c) cls_off[c] = start[c] - nsmall;
+        cls_off[kLenClasses] = nbig;
+    } else {
+        cls_off[kLenClasses] = 0;
     }
 
     const Hit* bigp = J.hits + nsmall;
@@ -696,19 +705,25 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         ncand_small = cs;
     } else if (nbig > 0) {
         uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
-        segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + 1));
-        hip_check(launch_seg_counts(bigp, nbig,
-                                    seg_members(Y.lmax, tau, J.tp.lane_cands), segs, st),
-                  "seg_counts");
+        segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + kLenClasses));
         size_t sb = scan_tmp_bytes(nbig);
         void* stmp = W.get("scan.tmp2", sb);
-        hip_check(scan_u32_to_u32(segs, segp, nbig, stmp, sb, st), "scan(segs)");
-        uint32_t ns = 0;
+        uint32_t ns[kLenClasses] = {};
+        for (int c = 0; c < kLenClasses; ++c) {
+            const uint64_t o = cls_off[c], nb = cls_off[c + 1] - o;
+            if (nb == 0) continue;
+            hip_check(launch_seg_counts(bigp + o, nb,
+                                        seg_members(class_maxlen(c, Y.lmax), tau,
+                                                    J.tp.lane_cands),
+                                        segs + o, st),
+                      "seg_counts");
+            hip_check(scan_u32_to_u32(segs + o, segp + o + c, nb, stmp, sb, st), "scan(segs)");
+            readback(&ns[c], segp + o + c + nb, sizeof(uint32_t), st);
+        }
         unsigned long long cs = 0;
-        readback(&ns, segp + nbig, sizeof ns, st);
         if (nsmall > 0) readback(&cs, J.prefix + nsmall, sizeof cs, st);
         sync_readback(st);
-        nseg = ns;
+        for (int c = 0; c < kLenClasses; ++c) cls_nseg[c] = ns[c];
         ncand_small = cs;
     }
 
@@ -787,13 +802,24 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     stats.verify_launches += 1;
                     stats.list_launches += 1;
                 }
-                if (nseg > 0) {
+                uint64_t max_chunks = 0;
+                for (int c = 0; c < kLenClasses; ++c)
+                    max_chunks = std::max<uint64_t>(max_chunks,
+                                                    seg_chunks(cls_nseg[c], J.tp.seg_chunk));
+                uint32_t* first = max_chunks
+                    ? (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)max_chunks)
+                    : nullptr;
+                for (int c = 0; c < kLenClasses; ++c) {
+                    const uint64_t nseg = cls_nseg[c];
+                    if (nseg == 0) continue;
+                    const uint64_t o = cls_off[c], nb = cls_off[c + 1] - o;
                     const uint64_t nchunks = seg_chunks(nseg, J.tp.seg_chunk);
-                    uint32_t* first = (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)nchunks);
                     const uint64_t waves = std::min<uint64_t>(
                         nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
+                    VerifyParams vc = vp;
+                    vc.y_maxlen = class_maxlen(c, Y.lmax);
                     const int s0 = tm.mark();
-                    hip_check(launch_verify_segs(vp, bigp, segp, nbig, nseg, first,
+                    hip_check(launch_verify_segs(vc, bigp + o, segp + o + c, nb, nseg, first,
                                                  J.tp.seg_chunk, J.tp.lane_cands,
                                                  (int)((waves + 3) / 4), st),
                               "verify_segs");

@@ -33,6 +33,19 @@ constexpr int kInlineMaxLen = 64;       // longest string the list-segment kerne
 // floor(kHashBits / bits) bytes is keyed by its packed codes (exact: no byte guard); a longer
 // one by a hash of its bytes.  A probe segment with an absent byte packs a 0 code, which no
 // indexed key has.
+// Hit buckets of the batched path: small lists by slot (64), big lists by the length class of
+// their strings (<= kLenClass0, <= kLenClass1, longer) and slot (3 x 64).
+constexpr int kHitBuckets = 256;
+constexpr int kLenClasses = 3;
+constexpr int kLenClass0 = 40;
+constexpr int kLenClass1 = 64;
+// longest indexed string of length class c in a set whose longest string has ymax bytes
+inline int class_maxlen(int c, int ymax)
+{
+    const int cap = c == 0 ? kLenClass0 : c == 1 ? kLenClass1 : ymax;
+    return ymax < cap ? ymax : cap;
+}
+
 // Exact keys of at least this many code bits are also tested against the key filter: their
 // (l, i) groups hold few of the possible codes, so most lookups miss.
 constexpr int kFilterMinBits = 24;
@@ -193,9 +206,10 @@ hipError_t launch_filter_build(const uint64_t* keys, const uint32_t* runstart, u
                                uint32_t* filter, hipStream_t s);hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
-// batched path: bucket the hits by (list size class, slot) into out, bucket regions in order;
-// bb: 128 * slot_bucket_grid(nh_cap) u32, bb_off: one more (bb_off[64 * grid] = hits in the
-// small-list buckets), scan_tmp: scan_tmp_bytes(128 * grid).  Then verify with per-wave chunks
+// batched path: bucket the hits (small lists by slot; big lists by length class, then slot)
+// into out, bucket regions in order; bb: kHitBuckets * slot_bucket_grid(nh_cap) u32, bb_off:
+// one more (bb_off[64 * (c + 1) * grid] = first hit of the big lists of length class c),
+// scan_tmp: scan_tmp_bytes(kHitBuckets * grid).  Then verify with per-wave chunks
 // (first: batched_chunks(ncand) u32 of scratch)
 unsigned slot_bucket_grid(uint64_t nh_cap);
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,

@@ -306,11 +306,12 @@ def _clusters(seed, nbase, per, lmin, lmax, kmax):
 
 
 @pytest.mark.parametrize("lanes", [1, 2])
-@pytest.mark.parametrize("lmin,lmax", [(20, 40), (44, 64)])
+@pytest.mark.parametrize("lmin,lmax", [(20, 40), (44, 64), (10, 120)])
 def test_list_kernel_wide_bands(lanes, lmin, lmax, tmp_path, monkeypatch):
     # the list-segment kernel on every band class up to 9 wide (tau 1..8, parts with t up to
     # 8, the final diagonal a constant for t <= 4 and a runtime value above), indexed strings
-    # of up to 48 and of up to 64 bytes, one or two candidates per lane
+    # of up to 40, up to 64 and (10..120) of every length class in one set, each class with a
+    # launch of its own, one or two candidates per lane
     monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
     col = _clusters(5 + lmin, 40, 60, lmin, lmax, 8)
     cache = str(tmp_path / "tune.txt")
@@ -331,3 +332,5 @@ def test_list_kernel_wide_bands(lanes, lmin, lmax, tmp_path, monkeypatch):
         assert st["candidates"] == pj.candidates
         assert st["cells"] == pj.cells
         assert st["ms_list_kernel"] > 0          # the list-segment kernel ran
+        if lmax > 64 and tau >= 4:
+            assert st["list_launches"] >= 2      # lists of several length classes
