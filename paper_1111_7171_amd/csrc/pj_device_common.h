@@ -318,7 +318,10 @@ __device__ inline int vsp_fast(P r, int lr, P s, int ls, int t, int* cells)
         for (int k = 0; k < MAXW; ++k) {
             const int up = (k + 1 < MAXW) ? D[(k + 1) < MAXW ? k + 1 : k] : BIG;
             const int dg = D[k] + ((ai != w[k]) ? 1 : 0);
-            const int v = min(min(up + cu[k], left + cl[k]), dg);
+            // no left neighbour for the band's first cell, no upper one for its last
+            const int v = k == 0 ? (MAXW == 1 ? dg : min(up + cu[k], dg))
+                                 : (k + 1 == MAXW ? min(left + cl[k], dg)
+                                                  : min(min(up + cu[k], left + cl[k]), dg));
             D[k] = v;
             left = v;
         }
@@ -416,7 +419,11 @@ struct LdsChars {
 //    expected distance is at least (j - i) + |delta - (j - i)| >= t + 1, and any value that
 //    improves on the banded one through such a cell inherits that bound: every row's test,
 //    and the result once saturated at t+1, are those of the band of Lemma 4;
-//  * the outer neighbours (left of index 0, above index MAXW-1) read as BIG.
+//  * the outer neighbours (left of index 0, above index MAXW-1) read as BIG, or (vsp_lane,
+//    vsp_fast) are left out of the minimum: a value that starts at BIG or above grows by at
+//    most 2 per row (rows <= 2047), so it stays far below overflow and above every value
+//    reached from row 0, and whether it is BIG or a little more changes no minimum that has
+//    a value from row 0 among its inputs, no stop test and no result.
 // So the characters of columns outside 1..nc are never needed: a window slot there may hold any
 // byte (the probe string's LDS buffer is padded so that such reads stay inside it).
 // Values are not saturated at t+1: min(v, t+1) commutes with the recurrence, so stop rows
@@ -704,7 +711,10 @@ __device__ inline void vsp_lane(LdsChars U, int lu, LdsLaneChars V, int lv, int 
                         upa = up + cu[k];
                         lfa = left + cl[k];
                     }
-                    const int v = min(min(upa, lfa), dg);
+                    // the band's first cell has no left neighbour and its last no upper one
+                    // (both outside the band): those terms drop instead of entering as BIG
+                    const int v = k == 0 ? (MAXW == 1 ? dg : min(upa, dg))
+                                         : (k + 1 == MAXW ? min(lfa, dg) : min(min(upa, lfa), dg));
                     D[k] = v;
                     left = v;
                 }
