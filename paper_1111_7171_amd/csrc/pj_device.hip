@@ -879,16 +879,13 @@ constexpr uint64_t kWaveChunk = 64ull * kWaveRounds;
 
 // Bucket of a hit: lists with at least `big` candidates after all smaller ones, each part in
 // slot order.
-// Bucket of a hit: small lists by slot (0..63); big lists by the length class of their strings
-// (at most kLenClass0, at most kLenClass1, longer; so that each class is verified by the
-// list-segment kernel with the lane-slot class its strings fit), then by slot (64..255).
+// Bucket of a hit: small lists, then big ones (from 64 * kLenClasses on), each by the length
+// class of the list's strings and then by slot
 __device__ inline uint32_t hit_bucket(const Hit& v, uint32_t big)
 {
     const uint32_t slot = (v.meta >> 11) & 63u;
-    if (v.count < big) return slot;
-    const uint32_t l = v.meta >> 17;
-    const uint32_t lc = l <= (uint32_t)kLenClass0 ? 0u : (l <= (uint32_t)kLenClass1 ? 1u : 2u);
-    return 64u + lc * 64u + slot;
+    const uint32_t cls = (uint32_t)len_class((int)(v.meta >> 17));
+    return (v.count < big ? 0u : 64u * (uint32_t)kLenClasses) + 64u * cls + slot;
 }
 
 // Bucketing of the hits in two passes without global atomics: bb[b * G + blk] = hits of
@@ -1006,10 +1003,13 @@ __device__ inline int vsp_dispatch(P r, int lr, P s, int ls, int t, int* cells)
 constexpr int kStgX = 60, kStgY = 52;     // slot strides: odd word counts, conflict-free
 
 // With STG the LDS slots allow 4 blocks per CU; the register budget is held to match
-// (128 VGPRs, no spills), so 4 waves per SIMD hide the candidates' dependent loads.
+// (128 VGPRs, no spills), so 4 waves per SIMD hide the candidates' dependent loads.  The
+// unstaged 9-wide form is held to 128 VGPRs too (it would take 135, 3 waves per SIMD; the
+// budget costs an 8-byte spill and gains a wave: the self-join of 5x10^5 medium strings at
+// tau 2..8 measured 37.5 -> 36.0 ms); the wider bands keep their registers.
 template <int GMAXW, int STG>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(STG ? 4 : 1))) void k_verify_batched(VerifyParams V, Div div,
+__attribute__((amdgpu_waves_per_eu((STG || GMAXW <= 9) ? 4 : 1))) void k_verify_batched(VerifyParams V, Div div,
                                                            const uint32_t* __restrict__ first,
                                                            uint64_t nchunks)
 {

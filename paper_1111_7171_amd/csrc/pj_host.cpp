@@ -637,12 +637,15 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                                        (unsigned long long)J.nhits, (unsigned long long)hit_cap);
 
     const bool batched = J.mode != PJ_MODE_PLAIN;
-    // batched: hits bucketed into [lists with < big_list candidates | the others by the length
-    // class of their strings], each part in slot order; small lists are verified candidate by
-    // candidate, big ones a 64-member segment per wave, one launch per length class (so that
-    // lists of short strings take the lane-slot kernels even when the set has long strings)
-    uint64_t nsmall = J.nhits, nbig = 0, ncand_small = J.ncand;
+    // batched: hits bucketed into [lists with < big_list candidates | the others], each part by
+    // the length class of its lists' strings and then in slot order; small lists are verified
+    // candidate by candidate, big ones a 64-member segment per wave, one launch per part and
+    // length class (so that lists of short strings take the kernels that stage their strings
+    // in LDS even when the set has long strings)
+    uint64_t nsmall = J.nhits, nbig = 0;
+    uint64_t sm_off[kLenClasses + 1] = {};     // small hits of class c: [sm_off[c], sm_off[c+1])
     uint64_t cls_off[kLenClasses + 1] = {};    // big hits of class c: [cls_off[c], cls_off[c+1])
+    uint64_t sm_ncand[kLenClasses] = {};
     uint64_t cls_nseg[kLenClasses] = {};
     uint32_t* segp = nullptr;                  // class c's scan at segp + cls_off[c] + c
     // few candidates (a serving batch): the bucketing round trips would cost more than they save
@@ -659,30 +662,57 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         hip_check(launch_slot_bucket(J.hits, J.counters, J.nhits, (uint32_t)J.tp.big_list, bb,
                                      bb_off, stmp, sb, sorted, st), "slot_bucket");
         J.hits = sorted;
-        // bucket 64 * (c + 1) opens length class c of the big lists
-        uint32_t start[kLenClasses] = {};
-        for (int c = 0; c < kLenClasses; ++c)
-            readback(&start[c], bb_off + (size_t)g * 64 * (c + 1), sizeof(uint32_t), st);
+        // bucket 64 * c opens length class c of the small lists, 64 * (kLenClasses + c) that of
+        // the big ones
+        uint32_t start[2 * kLenClasses] = {};
+        for (int c = 1; c < 2 * kLenClasses; ++c)
+            readback(&start[c], bb_off + (size_t)g * 64 * c, sizeof(uint32_t), st);
         sync_readback(st);
-        nsmall = start[0];
+        nsmall = start[kLenClasses];
         nbig = J.nhits - nsmall;
-        for (int c = 0; c < kLenClasses; ++c) cls_off[c] = start[c] - nsmall;
+        for (int c = 0; c < kLenClasses; ++c) {
+            sm_off[c] = start[c];
+            cls_off[c] = start[kLenClasses + c] - nsmall;
+        }
+        sm_off[kLenClasses] = nsmall;
         cls_off[kLenClasses] = nbig;
     } else {
-        cls_off[kLenClasses] = 0;
+        // one range of small lists, of every length: the last class's bound is the set's
+        for (int c = 0; c <= kLenClasses; ++c) sm_off[c] = (c == kLenClasses) ? nsmall : 0;
     }
 
     const Hit* bigp = J.hits + nsmall;
 
-    // candidate prefix sums of the (small) lists, list segments of the big ones
-    J.prefix = (unsigned long long*)W.get("join.prefix",
-                                          sizeof(unsigned long long) * (size_t)(nsmall + 1));
+    // candidate prefix sums of the small lists, one scan per class (class c's at J.prefix +
+    // sm_off[c] + c), list segments of the big ones
+    J.prefix = (unsigned long long*)W.get(
+        "join.prefix", sizeof(unsigned long long) * (size_t)(nsmall + kLenClasses));
+    auto small_prefix = [&](int c) { return J.prefix + sm_off[c] + c; };
+    // a class's candidate total: read back with the big lists' totals (nbig > 0), or alone
+    // when several classes have small lists; with small lists of one class only and no big
+    // lists, it is every candidate
+    unsigned long long sm_total[kLenClasses] = {};
+    int sm_classes = 0, sm_last = 0;
+    for (int c = 0; c < kLenClasses; ++c)
+        if (sm_off[c + 1] > sm_off[c]) {
+            ++sm_classes;
+            sm_last = c;
+        }
+    const bool read_totals = nbig > 0 || sm_classes > 1;
     if (nsmall > 0) {
         uint32_t* counts = (uint32_t*)W.get("join.counts", sizeof(uint32_t) * (size_t)nsmall);
         hip_check(launch_hit_counts(J.hits, nsmall, counts, st), "hit_counts");
         size_t sb = scan_tmp_bytes(nsmall);
         void* stmp = W.get("scan.tmp", sb);
-        hip_check(scan_u32_to_u64(counts, J.prefix, nsmall, stmp, sb, st), "scan(prefix)");
+        for (int c = 0; c < kLenClasses; ++c) {
+            const uint64_t o = sm_off[c], nh = sm_off[c + 1] - o;
+            if (nh == 0) continue;
+            hip_check(scan_u32_to_u64(counts + o, small_prefix(c), nh, stmp, sb, st),
+                      "scan(prefix)");
+            if (read_totals)
+                readback(&sm_total[c], small_prefix(c) + nh, sizeof(unsigned long long), st);
+        }
+        if (!read_totals) sm_total[sm_last] = J.ncand;
     }
     // shared-prefix verification of the big lists (Sec. 5.3): chains of list members
     const bool share = J.mode == PJ_MODE_SHARE_PREFIX && spec.X && spec.X->svals && nbig > 0;
@@ -697,12 +727,10 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         size_t sb = scan_tmp_bytes(nbig);
         void* stmp = W.get("scan.tmp2", sb);
         hip_check(scan_u32_to_u64(chains, cprefix, nbig, stmp, sb, st), "scan(chains)");
-        unsigned long long cs = 0, nc = 0;
+        unsigned long long nc = 0;
         readback(&nc, cprefix + nbig, sizeof nc, st);
-        if (nsmall > 0) readback(&cs, J.prefix + nsmall, sizeof cs, st);
         sync_readback(st);
         nchains = nc;
-        ncand_small = cs;
     } else if (nbig > 0) {
         uint32_t* segs = (uint32_t*)W.get("join.segs", sizeof(uint32_t) * (size_t)nbig);
         segp = (uint32_t*)W.get("join.segp", sizeof(uint32_t) * (size_t)(nbig + kLenClasses));
@@ -720,11 +748,15 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             hip_check(scan_u32_to_u32(segs + o, segp + o + c, nb, stmp, sb, st), "scan(segs)");
             readback(&ns[c], segp + o + c + nb, sizeof(uint32_t), st);
         }
-        unsigned long long cs = 0;
-        if (nsmall > 0) readback(&cs, J.prefix + nsmall, sizeof cs, st);
         sync_readback(st);
         for (int c = 0; c < kLenClasses; ++c) cls_nseg[c] = ns[c];
-        ncand_small = cs;
+    } else if (nsmall > 0 && read_totals) {
+        sync_readback(st);
+    }
+    uint64_t ncand_small = 0;
+    for (int c = 0; c < kLenClasses; ++c) {
+        sm_ncand[c] = sm_total[c];
+        ncand_small += sm_total[c];
     }
 
     // verify (+ short path); rerun once with an exact buffer when the first guess overflows
@@ -745,7 +777,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.y_inl_base = spec.X ? spec.X->inl_base : nullptr;
             vp.q_tau = spec.q_tau;
             vp.refs = spec.refs;
-            vp.hits = J.hits; vp.prefix = J.prefix;
+            vp.hits = J.hits; vp.prefix = small_prefix(kLenClasses - 1);
             vp.nhits = nsmall; vp.ncand = ncand_small;
             vp.tau = tau;
             vp.y_maxlen = Y.lmax;
@@ -753,36 +785,60 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
             vp.out = J.out; vp.out_cap = cap;
             vp.counters = J.counters;
             int k0 = tm.mark();
-            // long strings: verification by row blocks with compacted continuation queues
-            bool long_path = batched && ncand_small > 0 && Y.lmax > kLongMinLen &&
-                             tau + 1 <= kLongMaxW && !spec.q_tau && ncand_small <= (1ull << 24);
-            // tests force either verification of long strings (it changes no result)
-            if (const char* e = getenv("PJ_LONG_VERIFY")) long_path = long_path && atoi(e) != 0;
-            if (long_path) {
-                void* lsc = W.get("join.long", long_scratch_bytes(ncand_small));
-                vp.nhits = nsmall;
-                hip_check(launch_verify_long(vp, ncand_small, std::max(P.lmax, Y.lmax), lsc,
-                                             device_cus() * 8, st), "verify_long");
-                stats.verify_launches += 1;
-            }
             if (batched) {
-                if (ncand_small > 0 && !long_path) {
+                // small lists, one launch per length class: long strings by row blocks with
+                // compacted continuation queues, the others a candidate per lane
+                bool long_c[kLenClasses] = {};
+                int rounds_c[kLenClasses] = {};
+                uint64_t max_chunks = 0, max_long = 0;
+                for (int c = 0; c < kLenClasses; ++c) {
+                    const uint64_t nc = sm_ncand[c];
+                    if (nc == 0) continue;
+                    long_c[c] = class_maxlen(c, Y.lmax) > kLongMinLen && tau + 1 <= kLongMaxW &&
+                                !spec.q_tau && nc <= (1ull << 24);
+                    // tests force either verification of long strings (it changes no result)
+                    if (const char* e = getenv("PJ_LONG_VERIFY"))
+                        long_c[c] = long_c[c] && atoi(e) != 0;
+                    if (long_c[c]) {
+                        max_long = std::max<uint64_t>(max_long, nc);
+                        continue;
+                    }
                     // at least ~32 wave chunks per CU before a wave takes more than one round
                     // of 64 candidates: a few long candidates (long strings, high tau) then
                     // still spread over the whole device
                     const uint64_t per = (uint64_t)device_cus() * 32ull * 64ull;
-                    vp.wave_rounds = (int)std::max<uint64_t>(
-                        1, std::min<uint64_t>((uint64_t)kBatchedRoundsMax, ncand_small / per));
+                    rounds_c[c] = (int)std::max<uint64_t>(
+                        1, std::min<uint64_t>((uint64_t)kBatchedRoundsMax, nc / per));
                     // tests force the chunk size (it changes no result)
                     if (const char* e = getenv("PJ_BATCHED_ROUNDS"))
-                        vp.wave_rounds = std::max(1, std::min(kBatchedRoundsMax, atoi(e)));
-                    const uint64_t nchunks = batched_chunks(ncand_small, vp.wave_rounds);
-                    uint32_t* first = (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)nchunks);
-                    // persistent: enough waves to fill the chip, each walking its chunks
-                    const uint64_t waves = std::min<uint64_t>(
-                        nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
-                    hip_check(launch_verify_batched(vp, first, (int)((waves + 3) / 4), st),
-                              "verify_batched");
+                        rounds_c[c] = std::max(1, std::min(kBatchedRoundsMax, atoi(e)));
+                    max_chunks = std::max<uint64_t>(max_chunks, batched_chunks(nc, rounds_c[c]));
+                }
+                void* lsc = max_long ? W.get("join.long", long_scratch_bytes(max_long)) : nullptr;
+                uint32_t* first = max_chunks
+                    ? (uint32_t*)W.get("join.first", sizeof(uint32_t) * (size_t)max_chunks)
+                    : nullptr;
+                for (int c = 0; c < kLenClasses; ++c) {
+                    const uint64_t nc = sm_ncand[c];
+                    if (nc == 0) continue;
+                    VerifyParams vs = vp;
+                    vs.hits = J.hits + sm_off[c];
+                    vs.prefix = small_prefix(c);
+                    vs.nhits = sm_off[c + 1] - sm_off[c];
+                    vs.ncand = nc;
+                    vs.y_maxlen = class_maxlen(c, Y.lmax);
+                    if (long_c[c]) {
+                        hip_check(launch_verify_long(vs, nc, std::max(P.lmax, Y.lmax), lsc,
+                                                     device_cus() * 8, st), "verify_long");
+                    } else {
+                        vs.wave_rounds = rounds_c[c];
+                        const uint64_t nchunks = batched_chunks(nc, vs.wave_rounds);
+                        // persistent: enough waves to fill the chip, each walking its chunks
+                        const uint64_t waves = std::min<uint64_t>(
+                            nchunks, (uint64_t)device_cus() * J.tp.verify_waves_per_cu);
+                        hip_check(launch_verify_batched(vs, first, (int)((waves + 3) / 4), st),
+                                  "verify_batched");
+                    }
                     stats.verify_launches += 1;
                 }
                 if (share && nchains > 0) {
@@ -802,12 +858,12 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     stats.verify_launches += 1;
                     stats.list_launches += 1;
                 }
-                uint64_t max_chunks = 0;
+                uint64_t max_seg_chunks = 0;
                 for (int c = 0; c < kLenClasses; ++c)
-                    max_chunks = std::max<uint64_t>(max_chunks,
-                                                    seg_chunks(cls_nseg[c], J.tp.seg_chunk));
-                uint32_t* first = max_chunks
-                    ? (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)max_chunks)
+                    max_seg_chunks = std::max<uint64_t>(max_seg_chunks,
+                                                        seg_chunks(cls_nseg[c], J.tp.seg_chunk));
+                uint32_t* first2 = max_seg_chunks
+                    ? (uint32_t*)W.get("join.first2", sizeof(uint32_t) * (size_t)max_seg_chunks)
                     : nullptr;
                 for (int c = 0; c < kLenClasses; ++c) {
                     const uint64_t nseg = cls_nseg[c];
@@ -819,7 +875,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
                     VerifyParams vc = vp;
                     vc.y_maxlen = class_maxlen(c, Y.lmax);
                     const int s0 = tm.mark();
-                    hip_check(launch_verify_segs(vc, bigp + o, segp + o + c, nb, nseg, first,
+                    hip_check(launch_verify_segs(vc, bigp + o, segp + o + c, nb, nseg, first2,
                                                  J.tp.seg_chunk, J.tp.lane_cands,
                                                  (int)((waves + 3) / 4), st),
                               "verify_segs");

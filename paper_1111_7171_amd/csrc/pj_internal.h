@@ -28,17 +28,18 @@ __host__ __device__ inline int64_t stride_of(int l) { return (int64_t)((l + 15) 
 constexpr int kBatchedRoundsMax = 16;   // rounds of 64 candidates per batched-verify wave chunk
 constexpr int kInlineMaxLen = 64;       // longest string the list-segment kernel keeps in registers
 
-// Symbol map of an indexed set: code[b] = 1 + rank of byte b among the bytes the set contains
-// (0: absent), bits = bit length of the largest code.  A segment of at most exact_len =
-// floor(kHashBits / bits) bytes is keyed by its packed codes (exact: no byte guard); a longer
-// one by a hash of its bytes.  A probe segment with an absent byte packs a 0 code, which no
-// indexed key has.
-// Hit buckets of the batched path: small lists by slot (64), big lists by the length class of
-// their strings (<= kLenClass0, <= kLenClass1, longer) and slot (3 x 64).
-constexpr int kHitBuckets = 256;
+// Length classes of the big lists in the batched path (strings of at most kLenClass0 bytes, at
+// most kLenClass1, longer): each class is verified by the list-segment kernel whose lane slots
+// its strings fit (a class split at 48 bytes measured no faster).  The small lists are split
+// the same way, for the batched kernel's LDS-staged form.  Hit buckets: small lists by class
+// and slot, then big lists by class and slot.
 constexpr int kLenClasses = 3;
-constexpr int kLenClass0 = 40;
-constexpr int kLenClass1 = 64;
+constexpr int kLenClass0 = 40, kLenClass1 = 64;
+constexpr int kHitBuckets = 128 * kLenClasses;
+__host__ __device__ inline int len_class(int l)
+{
+    return (l > kLenClass0 ? 1 : 0) + (l > kLenClass1 ? 1 : 0);
+}
 // longest indexed string of length class c in a set whose longest string has ymax bytes
 inline int class_maxlen(int c, int ymax)
 {
@@ -46,6 +47,11 @@ inline int class_maxlen(int c, int ymax)
     return ymax < cap ? ymax : cap;
 }
 
+// Symbol map of an indexed set: code[b] = 1 + rank of byte b among the bytes the set contains
+// (0: absent), bits = bit length of the largest code.  A segment of at most exact_len =
+// floor(kHashBits / bits) bytes is keyed by its packed codes (exact: no byte guard); a longer
+// one by a hash of its bytes.  A probe segment with an absent byte packs a 0 code, which no
+// indexed key has.
 // Exact keys of at least this many code bits are also tested against the key filter: their
 // (l, i) groups hold few of the possible codes, so most lookups miss.
 constexpr int kFilterMinBits = 24;
@@ -206,10 +212,11 @@ hipError_t launch_filter_build(const uint64_t* keys, const uint32_t* runstart, u
                                uint32_t* filter, hipStream_t s);hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
-// batched path: bucket the hits (small lists by slot; big lists by length class, then slot)
-// into out, bucket regions in order; bb: kHitBuckets * slot_bucket_grid(nh_cap) u32, bb_off:
-// one more (bb_off[64 * (c + 1) * grid] = first hit of the big lists of length class c),
-// scan_tmp: scan_tmp_bytes(kHitBuckets * grid).  Then verify with per-wave chunks
+// batched path: bucket the hits (small lists, then big ones, each by length class and then
+// slot) into out, bucket regions in order; bb: kHitBuckets * slot_bucket_grid(nh_cap) u32,
+// bb_off: one more (bb_off[64 * c * grid] = first hit of the small lists of length class c,
+// bb_off[64 * (kLenClasses + c) * grid] that of the big lists), scan_tmp:
+// scan_tmp_bytes(kHitBuckets * grid).  Then verify with per-wave chunks
 // (first: batched_chunks(ncand) u32 of scratch)
 unsigned slot_bucket_grid(uint64_t nh_cap);
 hipError_t launch_slot_bucket(const Hit* hits, const unsigned long long* nh_dev, uint64_t nh_cap,
