@@ -656,7 +656,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         const uint32_t* fdir = P.filter_dir;
         if (valid) {
             gx = P.g_begin + (uint32_t)(t / per);
-            const uint32_t rem = (uint32_t)(t % per);
+            const uint32_t r0 = (uint32_t)(t % per);
+            const uint32_t rem = P.order ? (uint32_t)P.order[r0] : r0;
             i = (int)(rem % T1) + 1;
             const int dl = (int)(rem / T1);
             n = P.x_slen[gx];
@@ -2363,6 +2364,57 @@ hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hip
 {
     if (nh == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hit_counts, dim3(blocks_for(nh)), dim3(kBlock), 0, s, hits, nh, counts);
+    return hipGetLastError();
+}
+
+// Multi-match window size of slot i for a length difference delta = n - l (Sec. 4.2: the
+// start positions p_i - (i-1) .. p_i + (i-1) intersected with p_i + delta - (tau+1-i) ..
+// p_i + delta + (tau+1-i)), 0 when empty
+__device__ inline int mm_window_size(int tau, int i, int delta)
+{
+    const int r = tau + 1 - i;
+    const int a = (i - 1) < delta + r ? (i - 1) : delta + r;
+    const int b = (i - 1) < r - delta ? (i - 1) : r - delta;
+    const int sz = a + b + 1;
+    return sz > 0 ? sz : 0;
+}
+
+// One block: the (length, slot) pairs of a probe string grouped by decreasing window size
+// (a counting sort on the size; the order within a size is whatever the atomics give).  Pairs
+// of one size take equally many steps of the probe's window walk, so a wave whose lanes hold
+// them keeps all its lanes busy.
+__global__ __launch_bounds__(kBlock) void k_probe_order(int tau, int nl, int self,
+                                                        uint16_t* __restrict__ order)
+{
+    constexpr int kSizes = 2 * kTauMax + 2;      // window sizes 0 .. 2 tau + 1
+    __shared__ uint32_t cnt[kSizes];
+    const int T1 = tau + 1, per = nl * T1;
+    auto size_of = [&](int r) {
+        const int dl = r / T1, i = r % T1 + 1;
+        return mm_window_size(tau, i, self ? dl : tau - dl);
+    };
+    for (int k = threadIdx.x; k < kSizes; k += kBlock) cnt[k] = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < per; r += kBlock) atomicAdd(&cnt[size_of(r)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = kSizes - 1; k >= 0; --k) {
+            const uint32_t c = cnt[k];
+            cnt[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < per; r += kBlock)
+        order[atomicAdd(&cnt[size_of(r)], 1u)] = (uint16_t)r;
+}
+
+hipError_t launch_probe_order(int tau, int nl, int self, uint16_t* order, hipStream_t s)
+{
+    if (tau < 0 || tau > kTauMax || nl < 1 || nl > 2 * kTauMax + 1 || !order)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_probe_order, dim3(1), dim3(kBlock), 0, s, tau, nl, self, order);
     return hipGetLastError();
 }
 

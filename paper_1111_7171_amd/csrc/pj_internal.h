@@ -148,6 +148,10 @@ struct ProbeParams {
     const uint32_t* nx_dev;
     SymMap sym;                 // the indexed set's symbol map (keys)
     int selection;              // PJ_SELECT_* window of start positions
+    // the (length, slot) pairs of a probe string in the order the threads take them: a
+    // permutation of 0 .. nl * (tau+1) - 1 grouped by window size, so that a wave's lanes walk
+    // windows of one size (launch_probe_order); nullptr: natural order
+    const uint16_t* order;
 };
 
 struct VerifyParams {
@@ -210,6 +214,9 @@ hipError_t launch_filter_build(const uint64_t* keys, const uint32_t* runstart, u
                                uint32_t ngroups, uint32_t* gfirst, uint32_t* gend, uint32_t* words,
                                void* scan_tmp, size_t scan_bytes, uint32_t* filter_dir,
                                uint32_t* filter, hipStream_t s);hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s);
+// order[0 .. nl * (tau+1)): the (length, slot) pairs r = dl * (tau+1) + (i-1) of a probe string
+// by decreasing multi-match window size (any order within a size)
+hipError_t launch_probe_order(int tau, int nl, int self, uint16_t* order, hipStream_t s);
 hipError_t launch_hit_counts(const Hit* hits, uint64_t nh, uint32_t* counts, hipStream_t s);
 hipError_t launch_verify(const VerifyParams& V, int grid, hipStream_t s);
 // batched path: bucket the hits (small lists, then big ones, each by length class and then
