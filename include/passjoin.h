@@ -290,13 +290,17 @@ int pj_server_stop(pj_server* srv);
  * spread over the GPU: the persistent verification grid (waves per compute unit), the list
  * segments (64 candidates per lane slot) a wave takes at a time, the candidate count from which
  * an inverted list is verified a wave at a time instead of candidate by candidate, the probe
- * grid (blocks per compute unit), and how many members of one list each lane verifies at once. */
+ * grid (blocks per compute unit) and its thread mapping, and how many members of one list each
+ * lane verifies at once. */
 typedef struct {
     int32_t verify_waves_per_cu;   /* 8, 16, 32, ..., 1024, powers of two (default 32) */
     int32_t seg_chunk;             /* 1, 2, 4, ..., 2048, powers of two (default 4) */
     int32_t big_list;              /* 16, 32, 64 or 128 (default 32) */
     int32_t probe_blocks_per_cu;   /* 4, 8 or 16 (default 8) */
     int32_t lane_cands;            /* list-segment candidates per lane: 1 or 2 (default 2) */
+    int32_t probe_map;             /* probe threads: 0 a wave over consecutive (length, slot)
+                                      pairs of a few probe strings, 1 a wave over 64 probe
+                                      strings with one pair (default 0) */
     int32_t len_bucket;            /* key: bit length of the rounded mean string length */
     int32_t trials;                /* settings measured */
     double ms_default;             /* probe + verification kernel time, built-in defaults */

@@ -79,7 +79,8 @@ class PjServerConfig(C.Structure):
 class PjTuneResult(C.Structure):
     _fields_ = [("verify_waves_per_cu", C.c_int32), ("seg_chunk", C.c_int32),
                 ("big_list", C.c_int32), ("probe_blocks_per_cu", C.c_int32),
-                ("lane_cands", C.c_int32), ("len_bucket", C.c_int32), ("trials", C.c_int32),
+                ("lane_cands", C.c_int32), ("probe_map", C.c_int32),
+                ("len_bucket", C.c_int32), ("trials", C.c_int32),
                 ("ms_default", C.c_double), ("ms_best", C.c_double)]
 
 

@@ -596,10 +596,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_keys(const uint64_t* __restri
 // One thread per (probe string x, probed length l, slot i).  The thread walks the window
 // [bot_i, top_i] with a rolling hash of x[p, l_i], looks each substring up, trims the list to
 // the members visited before x (self-join, l == |x|), and appends non-empty lookups as hits.
-constexpr int kProbeStage = 2048;    // bytes of probe strings a wave stages in LDS
-
+// Threads map to triples string-major (a wave covers consecutive (l, i) pairs of one or a few
+// probe strings) or, with XMAJ, pair-major over blocks of 64 probe strings (a wave's lanes are
+// 64 consecutive probe strings with one (l, i) pair: windows of one size when the strings have
+// a few pairs each).
+template <bool XMAJ>
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
 {
+    // bytes of probe strings a wave stages in LDS
+    constexpr int kProbeStage = XMAJ ? 4096 : 2048;
     __shared__ Hit s_hits[kWaves][kAppendCap];
     __shared__ uint4 s_xs[kWaves][kProbeStage / 16];
     __shared__ uint16_t s_sym[256];
@@ -627,10 +632,27 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         const uint64_t tw = t0 + (threadIdx.x & ~63u);
         uint32_t g_first = 0;
         bool staged = false;
+        // XMAJ: threads t = block * 64 * per + pair * 64 + lane, string g_begin + block*64 + lane
+        uint32_t gx_t = 0, r0 = 0;
+        if constexpr (XMAJ) {
+            const uint64_t b = t / (64 * per), q = t % (64 * per);
+            gx_t = P.g_begin + (uint32_t)(b * 64 + q % 64);
+            r0 = (uint32_t)(q / 64);
+            valid = valid && gx_t < P.g_begin + P.nx;
+        } else {
+            gx_t = P.g_begin + (uint32_t)(t / per);
+            r0 = (uint32_t)(t % per);
+        }
         if (tw < nthreads) {
-            const uint64_t tl = min(tw + 63, nthreads - 1);
-            g_first = P.g_begin + (uint32_t)(tw / per);
-            const uint32_t g_last = P.g_begin + (uint32_t)(tl / per);
+            uint32_t g_last;
+            if constexpr (XMAJ) {
+                g_first = P.g_begin + (uint32_t)(tw / (64 * per)) * 64u;
+                g_last = min(g_first + 63u, P.g_begin + P.nx - 1u);
+            } else {
+                const uint64_t tl = min(tw + 63, nthreads - 1);
+                g_first = P.g_begin + (uint32_t)(tw / per);
+                g_last = P.g_begin + (uint32_t)(tl / per);
+            }
             const int n0 = P.x_slen[g_first];
             const int64_t bytes = (int64_t)(g_last - g_first + 1) * stride_of(n0);
             if (P.x_slen[g_last] == n0 && bytes <= kProbeStage) {
@@ -655,8 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
         const uint32_t* filter = P.filter;
         const uint32_t* fdir = P.filter_dir;
         if (valid) {
-            gx = P.g_begin + (uint32_t)(t / per);
-            const uint32_t r0 = (uint32_t)(t % per);
+            gx = gx_t;
             const uint32_t rem = P.order ? (uint32_t)P.order[r0] : r0;
             i = (int)(rem % T1) + 1;
             const int dl = (int)(rem / T1);
@@ -2423,7 +2444,14 @@ hipError_t launch_probe(const ProbeParams& P, int max_blocks, hipStream_t s)
     if (P.threads == 0) return hipSuccess;
     if (!P.sym.code) return hipErrorInvalidValue;
     const uint64_t blocks = std::min<uint64_t>(blocks_for(P.threads), (uint64_t)max_blocks);
-    hipLaunchKernelGGL(k_probe, dim3((unsigned)blocks), dim3(kBlock), 0, s, P, make_div(P.tau + 1));
+    if (P.xmajor) {
+        if (P.q_tau || P.nx_dev || P.nx == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_probe<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, P,
+                           make_div(P.tau + 1));
+    } else {
+        hipLaunchKernelGGL(k_probe<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, P,
+                           make_div(P.tau + 1));
+    }
     return hipGetLastError();
 }
 
@@ -2898,7 +2926,7 @@ hipError_t launch_graph_batch(const GraphBatch& G, hipStream_t s)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, G.probe.counters, 8, 0ull);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, G.bcounts, 4, 0ull);
-    hipLaunchKernelGGL(k_probe, dim3(G.probe_grid), dim3(kBlock), 0, s, G.probe,
+    hipLaunchKernelGGL(k_probe<false>, dim3(G.probe_grid), dim3(kBlock), 0, s, G.probe,
                        make_div(G.probe.tau + 1));
     hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(kBlock), 0, s, G.probe.hits,
                        G.probe.counters, G.probe.hit_cap,

@@ -600,6 +600,24 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.g_begin = (uint32_t)probe_first;
         pp.nl = self ? T1 : 2 * tau + 1;
         pp.threads = (uint64_t)nprobe * (uint64_t)pp.nl * (uint64_t)T1;
+        // the thread mapping the tuner chose (pair-major keeps a wave's lanes on windows of
+        // one size when probe strings have few (length, slot) pairs)
+        if (!spec.q_tau && J.tp.probe_map == 1) {
+            pp.xmajor = 1;
+            pp.nx = (uint32_t)nprobe;
+            pp.threads = ((uint64_t)nprobe + 63) / 64 * 64 * (uint64_t)pp.nl * (uint64_t)T1;
+        }
+        // tests force either thread mapping (it changes no result)
+        if (const char* e = getenv("PJ_PROBE_XMAJOR")) {
+            if (atoi(e) == 0 || spec.q_tau) {
+                pp.xmajor = 0;
+                pp.threads = (uint64_t)nprobe * (uint64_t)pp.nl * (uint64_t)T1;
+            } else {
+                pp.xmajor = 1;
+                pp.nx = (uint32_t)nprobe;
+                pp.threads = ((uint64_t)nprobe + 63) / 64 * 64 * (uint64_t)pp.nl * (uint64_t)T1;
+            }
+        }
         pp.self = self ? 1 : 0;
         pp.q_tau = spec.q_tau;
         pp.refs = spec.refs;

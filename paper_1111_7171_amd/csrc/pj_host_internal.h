@@ -89,6 +89,7 @@ struct TuneParams {
     int big_list = 32;              // lists with at least this many candidates: list-segment kernel
     int probe_blocks_per_cu = 8;    // grid of the probe kernel
     int lane_cands = 2;             // list-segment candidates per lane (1 or 2)
+    int probe_map = 0;              // probe threads: 0 string-major, 1 pair-major (64 strings)
 };
 
 bool tune_params_valid(const TuneParams& p);

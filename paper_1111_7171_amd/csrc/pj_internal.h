@@ -152,6 +152,10 @@ struct ProbeParams {
     // permutation of 0 .. nl * (tau+1) - 1 grouped by window size, so that a wave's lanes walk
     // windows of one size (launch_probe_order); nullptr: natural order
     const uint16_t* order;
+    // 1: threads pair-major over blocks of 64 probe strings (threads = nx rounded up to 64,
+    // times nl * (tau+1)); not with q_tau or nx_dev
+    int xmajor;
+    uint32_t nx;                // probe strings (xmajor)
 };
 
 struct VerifyParams {

@@ -1,5 +1,6 @@
 // Autotuner for the batched path's launch parameters (persistent verification grid, list
-// segments per wave chunk, the small/large inverted-list threshold, probe grid).  None of them
+// segments per wave chunk, the small/large inverted-list threshold, probe grid and thread
+// mapping).  None of them
 // changes a result: they decide only how the candidates of Algorithm 1 are spread over waves.
 //
 // Parameters are kept per (GPU architecture, tau, length bucket), the bucket being the bit
@@ -8,11 +9,12 @@
 // events; the result goes to an in-process table and, when pj_options.tune_cache names a file,
 // to that file, which later calls read back.  The file is plain text:
 //
-//   # passjoin tune cache v2: arch tau len_bucket verify_waves_per_cu seg_chunk big_list
-//   #   probe_blocks_per_cu lane_cands ms
-//   gfx950 4 4 32 4 32 8 2 112.300
+//   # passjoin tune cache v3: arch tau len_bucket verify_waves_per_cu seg_chunk big_list
+//   #   probe_blocks_per_cu lane_cands probe_map ms
+//   gfx950 4 4 32 4 32 8 2 0 112.300
 //
-// Unknown or out-of-range lines are ignored.  A file that changes on disk is read again.
+// Lines of the v2 format (without probe_map) read as probe_map 0.  Unknown or out-of-range
+// lines are ignored.  A file that changes on disk is read again.
 #include <sys/stat.h>
 
 #include <algorithm>
@@ -52,6 +54,7 @@ const int kChunkOpts[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048};
 const int kBigOpts[] = {16, 32, 64, 128};
 const int kProbeOpts[] = {4, 8, 16};
 const int kLaneOpts[] = {1, 2};
+const int kMapOpts[] = {0, 1};
 
 template <size_t N>
 bool in(const int (&opts)[N], int v)
@@ -103,10 +106,17 @@ void parse_file(const char* path, std::map<Key, Entry>& table)
         char arch[128];
         int tau, lb;
         Entry e;
-        if (sscanf(line, "%127s %d %d %d %d %d %d %d %lf", arch, &tau, &lb,
-                   &e.p.verify_waves_per_cu, &e.p.seg_chunk, &e.p.big_list,
-                   &e.p.probe_blocks_per_cu, &e.p.lane_cands, &e.ms) != 9)
-            continue;
+        const int got = sscanf(line, "%127s %d %d %d %d %d %d %d %d %lf", arch, &tau, &lb,
+                               &e.p.verify_waves_per_cu, &e.p.seg_chunk, &e.p.big_list,
+                               &e.p.probe_blocks_per_cu, &e.p.lane_cands, &e.p.probe_map, &e.ms);
+        if (got != 10) {
+            // v2: no probe_map column
+            e.p.probe_map = 0;
+            if (sscanf(line, "%127s %d %d %d %d %d %d %d %lf", arch, &tau, &lb,
+                       &e.p.verify_waves_per_cu, &e.p.seg_chunk, &e.p.big_list,
+                       &e.p.probe_blocks_per_cu, &e.p.lane_cands, &e.ms) != 9)
+                continue;
+        }
         if (tau < 0 || tau > kTauMax || lb < 0 || lb > 12 || !tune_params_valid(e.p)) continue;
         table[Key(arch, tau, lb)] = e;
     }
@@ -134,13 +144,14 @@ void write_file(const char* path, const std::map<Key, Entry>& table)
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = fopen(tmp.c_str(), "w");
     if (!f) throw Error(PJ_EINVAL, "cannot write tune cache %s", path);
-    fprintf(f, "# passjoin tune cache v2: arch tau len_bucket verify_waves_per_cu seg_chunk "
-               "big_list probe_blocks_per_cu lane_cands ms\n");
+    fprintf(f, "# passjoin tune cache v3: arch tau len_bucket verify_waves_per_cu seg_chunk "
+               "big_list probe_blocks_per_cu lane_cands probe_map ms\n");
     for (const auto& kv : table) {
         const Entry& e = kv.second;
-        fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", std::get<0>(kv.first).c_str(),
+        fprintf(f, "%s %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(kv.first).c_str(),
                 std::get<1>(kv.first), std::get<2>(kv.first), e.p.verify_waves_per_cu,
-                e.p.seg_chunk, e.p.big_list, e.p.probe_blocks_per_cu, e.p.lane_cands, e.ms);
+                e.p.seg_chunk, e.p.big_list, e.p.probe_blocks_per_cu, e.p.lane_cands,
+                e.p.probe_map, e.ms);
     }
     if (fclose(f) != 0 || rename(tmp.c_str(), path) != 0)
         throw Error(PJ_EINVAL, "cannot write tune cache %s", path);
@@ -157,7 +168,7 @@ bool tune_params_valid(const TuneParams& p)
 {
     return in(kWavesOpts, p.verify_waves_per_cu) && in(kChunkOpts, p.seg_chunk) &&
            in(kBigOpts, p.big_list) && in(kProbeOpts, p.probe_blocks_per_cu) &&
-           in(kLaneOpts, p.lane_cands);
+           in(kLaneOpts, p.lane_cands) && in(kMapOpts, p.probe_map);
 }
 
 TuneParams tune_lookup(const char* cache, int tau, double mean_len)
@@ -215,10 +226,10 @@ int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_res
         const double ms_default = measure(cur);
         double ms_best = ms_default;
         // measured settings, so a later pass does not time one again
-        std::map<std::tuple<int, int, int, int, int>, double> seen;
+        std::map<std::tuple<int, int, int, int, int, int>, double> seen;
         auto key_of = [](const TuneParams& p) {
             return std::make_tuple(p.verify_waves_per_cu, p.seg_chunk, p.big_list,
-                                   p.probe_blocks_per_cu, p.lane_cands);
+                                   p.probe_blocks_per_cu, p.lane_cands, p.probe_map);
         };
         seen[key_of(cur)] = ms_default;
         bool changed = false;
@@ -248,6 +259,7 @@ int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_res
             descend(&TuneParams::lane_cands, kLaneOpts, sizeof kLaneOpts / sizeof kLaneOpts[0]);
             descend(&TuneParams::probe_blocks_per_cu, kProbeOpts,
                     sizeof kProbeOpts / sizeof kProbeOpts[0]);
+            descend(&TuneParams::probe_map, kMapOpts, sizeof kMapOpts / sizeof kMapOpts[0]);
             if (!changed) break;
         }
 
@@ -267,6 +279,7 @@ int pj_tune(const pj_strings* S, int32_t tau, const pj_options* opt, pj_tune_res
         out->big_list = cur.big_list;
         out->probe_blocks_per_cu = cur.probe_blocks_per_cu;
         out->lane_cands = cur.lane_cands;
+        out->probe_map = cur.probe_map;
         out->len_bucket = std::get<2>(key);
         out->trials = trials;
         out->ms_default = ms_default;

@@ -279,6 +279,31 @@ def test_batched_chunk_sizes(rounds, monkeypatch):
         assert st["cells"] == pj.cells
 
 
+@pytest.mark.parametrize("xmajor", ["0", "1"])
+def test_probe_thread_mappings(xmajor, monkeypatch):
+    # the probe's two thread mappings (string-major; pair-major over blocks of 64 probe strings,
+    # with a partial last block, strings of several lengths per block and unstaged blocks of
+    # long strings) and the window-size order of the pairs change no result, for self-joins
+    # and joins of two sets
+    monkeypatch.setenv("PJ_PROBE_XMAJOR", xmajor)
+    col = W.cfg3(3_001, seed=72)
+    for tau in (1, 3, 8):
+        _say("probe mapping", xmajor, "tau", tau)
+        got = P.pj_self_join(col, tau)
+        st = P.pj_last_stats()
+        pj = O.self_join_pj(col, tau)
+        _same(got, pj.pairs, f"xmajor={xmajor} tau={tau}")
+        assert st["candidates"] == pj.candidates and st["selected"] == pj.selected
+    R = W.cfg2(1_500, seed=73)
+    S = W.cfg2(1_250, seed=74)
+    for tau in (2, 4):
+        got = P.pj_join(R, S, tau)
+        st = P.pj_last_stats()
+        pj = O.join_pj(R, S, tau)
+        _same(got, pj.pairs, f"join xmajor={xmajor} tau={tau}")
+        assert st["candidates"] == pj.candidates and st["selected"] == pj.selected
+
+
 def _clusters(seed, nbase, per, lmin, lmax, kmax):
     """nbase random base strings over a-z (lengths U{lmin..lmax}), each with per - 1 copies
     carrying U{0..kmax} random edits kept within [lmin, lmax]: the members of a cluster share

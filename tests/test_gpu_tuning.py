@@ -21,12 +21,14 @@ def _len_bucket(col):
 
 
 def _read_cache(path):
+    # v3 lines: arch tau len_bucket and six parameters (the last the probe's thread mapping), ms
     rows = []
     for line in open(path):
         if line.startswith("#"):
             continue
         f = line.split()
-        rows.append((f[0], int(f[1]), int(f[2]), tuple(int(v) for v in f[3:8]), float(f[8])))
+        assert len(f) == 10, line
+        rows.append((f[0], int(f[1]), int(f[2]), tuple(int(v) for v in f[3:9]), float(f[9])))
     return rows
 
 
@@ -48,6 +50,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert r["big_list"] in (16, 32, 64, 128)
     assert r["probe_blocks_per_cu"] in (4, 8, 16)
     assert r["lane_cands"] in (1, 2)
+    assert r["probe_map"] in (0, 1)
     assert r["len_bucket"] == _len_bucket(col)
     assert r["trials"] >= 10 and 0 < r["ms_best"] <= r["ms_default"]
     rows = _read_cache(cache)
@@ -55,7 +58,7 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     arch, tau, lb, params, ms = rows[0]
     assert arch.startswith("gfx") and tau == 3 and lb == r["len_bucket"]
     assert params == (r["verify_waves_per_cu"], r["seg_chunk"], r["big_list"],
-                      r["probe_blocks_per_cu"], r["lane_cands"])
+                      r["probe_blocks_per_cu"], r["lane_cands"], r["probe_map"])
     plain = P.pj_self_join(col, 3)
     st0 = P.pj_last_stats()
     tuned = P.pj_self_join(col, 3, tune_cache=cache)
@@ -68,8 +71,9 @@ def test_pj_tune_writes_cache_and_keeps_results(tmp_path):
     assert sorted(t for _, t, _, _, _ in _read_cache(cache)) == [2, 3]
 
 
-@pytest.mark.parametrize("params", [(8, 1, 16, 4, 1), (512, 512, 128, 16, 2), (16, 2, 64, 8, 2),
-                                    (32, 4, 32, 8, 1)])
+# six values: a v3 line (the last is the probe's thread mapping); five: a v2 line (mapping 0)
+@pytest.mark.parametrize("params", [(8, 1, 16, 4, 1, 1), (512, 512, 128, 16, 2, 0),
+                                    (16, 2, 64, 8, 2, 1), (32, 4, 32, 8, 1)])
 def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     # the list-segment kernel at these sizes needs the slot bucketing forced on
     monkeypatch.setenv("PJ_BUCKET_MIN_CANDIDATES", "0")
@@ -80,7 +84,7 @@ def test_forced_settings_match_oracle(tmp_path, monkeypatch, params):
     arch = _read_cache(cache)[0][0]
     lb = _len_bucket(col)
     with open(cache, "w") as f:
-        f.write("# passjoin tune cache v2\n")
+        f.write(f"# passjoin tune cache v{3 if len(params) == 6 else 2}\n")
         for tau in (1, 2, 3, 4):
             f.write(f"{arch} {tau} {lb} {' '.join(map(str, params))} 1.0\n")
     for tau in (1, 2, 3, 4):
