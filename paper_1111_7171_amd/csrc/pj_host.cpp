@@ -632,9 +632,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.ymin = Y.lmin; pp.ymax = Y.lmax;
         pp.sym = spec.sym;
         pp.selection = spec.selection;
-        if (!spec.q_tau && spec.selection == PJ_SELECT_MULTIMATCH) {
+        if (!spec.q_tau && spec.selection == PJ_SELECT_MULTIMATCH && J.mode != PJ_MODE_PLAIN) {
             // the (length, slot) pairs grouped by window size, so a wave's lanes walk windows of
-            // one size
+            // one size (the plain path keeps the natural order: it is the unscheduled baseline)
             uint16_t* order = (uint16_t*)W.get(
                 "probe.order", sizeof(uint16_t) * (size_t)pp.nl * (size_t)T1);
             hip_check(launch_probe_order(tau, pp.nl, pp.self, order, st), "probe_order");
