@@ -601,8 +601,9 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
         pp.nl = self ? T1 : 2 * tau + 1;
         pp.threads = (uint64_t)nprobe * (uint64_t)pp.nl * (uint64_t)T1;
         // the thread mapping the tuner chose (pair-major keeps a wave's lanes on windows of
-        // one size when probe strings have few (length, slot) pairs)
-        if (!spec.q_tau && J.tp.probe_map == 1) {
+        // one size when probe strings have few (length, slot) pairs); the plain path keeps the
+        // string-major one
+        if (!spec.q_tau && J.tp.probe_map == 1 && J.mode != PJ_MODE_PLAIN) {
             pp.xmajor = 1;
             pp.nx = (uint32_t)nprobe;
             pp.threads = ((uint64_t)nprobe + 63) / 64 * 64 * (uint64_t)pp.nl * (uint64_t)T1;
