@@ -166,6 +166,63 @@ static int bitlen(uint64_t v)
 
 thread_local ReadTape* t_tape = nullptr;
 
+// Small read-backs land in a page-locked staging buffer of the calling thread, so that their
+// copies are asynchronous: a copy into pageable memory makes the host wait for the stream, and
+// the device then idles until the host launches the next kernel, once per read-back instead of
+// once per sync_readback.  The values move to their destinations at the next sync_readback on
+// the stream.  Buffers go back to a process-wide pool when their thread ends (no HIP call at
+// thread exit).
+namespace {
+
+constexpr size_t kStageBytes = 64 << 10;     // per thread
+constexpr size_t kStageMaxRead = 16 << 10;   // larger read-backs copy straight to their target
+
+std::mutex g_stage_mu;
+std::vector<uint8_t*> g_stage_pool;
+
+struct ThreadStage {
+    uint8_t* buf = nullptr;
+    size_t used = 0;
+    struct Pending {
+        void* host;
+        size_t off, bytes;
+        hipStream_t st;
+    };
+    std::vector<Pending> pend;
+    bool failed = false;                     // page-locked allocation refused: pageable copies
+
+    uint8_t* get()
+    {
+        if (!buf && !failed) {
+            {
+                std::lock_guard<std::mutex> lk(g_stage_mu);
+                if (!g_stage_pool.empty()) {
+                    buf = g_stage_pool.back();
+                    g_stage_pool.pop_back();
+                }
+            }
+            if (!buf && hipHostMalloc((void**)&buf, kStageBytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                buf = nullptr;
+                failed = true;
+            }
+        }
+        return buf;
+    }
+
+    ~ThreadStage()
+    {
+        if (buf) {
+            std::lock_guard<std::mutex> lk(g_stage_mu);
+            g_stage_pool.push_back(buf);
+        }
+    }
+};
+
+thread_local ThreadStage t_stage;
+
+}  // namespace
+
 void readback(void* host, const void* dev, size_t bytes, hipStream_t st)
 {
     if (t_tape && t_tape->replay) {
@@ -175,14 +232,44 @@ void readback(void* host, const void* dev, size_t bytes, hipStream_t st)
         t_tape->pos += bytes;
         return;
     }
-    hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st), "read back");
+    ThreadStage& S = t_stage;
+    const size_t need = (bytes + 15) & ~(size_t)15;
+    uint8_t* buf = bytes <= kStageMaxRead ? S.get() : nullptr;
+    if (buf && S.used + need <= kStageBytes) {
+        hip_check(hipMemcpyAsync(buf + S.used, dev, bytes, hipMemcpyDeviceToHost, st),
+                  "read back");
+        S.pend.push_back({host, S.used, bytes, st});
+        S.used += need;
+    } else {
+        hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st), "read back");
+    }
     if (t_tape) t_tape->pending.emplace_back(host, bytes);
+}
+
+void drop_readbacks()
+{
+    ThreadStage& S = t_stage;
+    for (const auto& p : S.pend) (void)hipStreamSynchronize(p.st);
+    (void)hipGetLastError();
+    S.pend.clear();
+    S.used = 0;
 }
 
 void sync_readback(hipStream_t st)
 {
     if (t_tape && t_tape->replay) return;
     hip_check(hipStreamSynchronize(st), "sync");
+    ThreadStage& S = t_stage;
+    if (!S.pend.empty()) {
+        size_t keep = 0;
+        for (size_t k = 0; k < S.pend.size(); ++k) {
+            const auto& p = S.pend[k];
+            if (p.st == st) memcpy(p.host, S.buf + p.off, p.bytes);
+            else S.pend[keep++] = p;        // another stream's read: still in flight
+        }
+        S.pend.resize(keep);
+        if (keep == 0) S.used = 0;
+    }
     if (t_tape) {
         for (const auto& p : t_tape->pending) {
             const uint8_t* b = (const uint8_t*)p.first;
@@ -276,6 +363,7 @@ static size_t device_extent(const void* p, const std::string& what)
 void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string& tag, DevSet& D,
                hipStream_t st)
 {
+    ReadbackScope rb_scope;
     if (!S) throw Error(PJ_EINVAL, "%s: null pj_strings", tag.c_str());
     size_t bytes_extent = 0;
     if (!on_device) validate_host_strings(S, tag.c_str());
@@ -387,6 +475,7 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
 void build_index(const DevSet& D, int tau, Alloc& A, const std::string& tag, DevIndex& X,
                  hipStream_t st, bool with_inline, bool with_share)
 {
+    ReadbackScope rb_scope;
     const int T1 = tau + 1;
     X.tau = tau;
     auto nm = [&](const char* s) { return tag + "." + s; };
@@ -569,6 +658,7 @@ static uint64_t selection_bound(const DevSet& P, const DevSet& Y, int tau, bool 
 void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, JoinScratch& J,
                     pj_stats& stats, Timer& tm, hipStream_t st)
 {
+    ReadbackScope rb_scope;
     Workspace& W = thread_workspace();
     const int tau = spec.tau;
     const bool self = spec.self;
@@ -956,6 +1046,7 @@ void run_candidates(const DevSet& P, const DevSet& Y, const ProbeSpec& spec, Joi
 uint64_t finish_pairs(const DevSet& P, const DevSet& Y, bool self, const uint64_t* acc,
                       uint64_t m, int32_t** a_out, int32_t** b_out, hipStream_t st)
 {
+    ReadbackScope rb_scope;
     Workspace& W = thread_workspace();
     if (m >= (uint64_t)UINT32_MAX) throw Error(PJ_ERANGE, "too many accepted candidates");
     int bbits = std::max(1, bitlen((uint64_t)std::max<int64_t>(std::max(P.n, Y.n) - 1, 1)));

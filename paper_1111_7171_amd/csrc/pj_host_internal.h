@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <exception>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -63,9 +64,21 @@ struct ReadTape {
     std::vector<std::pair<void*, size_t>> pending;   // reads enqueued before the next sync
 };
 extern thread_local ReadTape* t_tape;
-// device -> host read, complete after the next sync_readback
+// device -> host read, complete after the next sync_readback on the stream
 void readback(void* host, const void* dev, size_t bytes, hipStream_t st);
 void sync_readback(hipStream_t st);
+// forgets this thread's read-backs that no sync_readback completed (after waiting for their
+// streams): their targets belong to a scope an exception is leaving
+void drop_readbacks();
+// declared in a function that issues read-backs into its own variables: when an exception
+// leaves the function between a read-back and its sync, the read-back is dropped
+struct ReadbackScope {
+    int uncaught = std::uncaught_exceptions();
+    ~ReadbackScope()
+    {
+        if (std::uncaught_exceptions() > uncaught) drop_readbacks();
+    }
+};
 // host table -> device
 void upload(void* dev, const void* host, size_t bytes, hipStream_t st);
 // device memory = 0 with a kernel (bytes a multiple of 4)
