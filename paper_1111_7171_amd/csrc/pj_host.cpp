@@ -212,7 +212,8 @@ struct ThreadStage {
 
     ~ThreadStage()
     {
-        if (buf) {
+        // a buffer with copies that no sync completed is not handed on (kept until exit)
+        if (buf && pend.empty()) {
             std::lock_guard<std::mutex> lk(g_stage_mu);
             g_stage_pool.push_back(buf);
         }
