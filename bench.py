@@ -261,7 +261,7 @@ def serving_bench(P, W, n_index: int, seconds: float, slots: int, compare_eager:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--taus", default=None, help="default: 1,2,3,4 (cfg2)")
     ap.add_argument("--n", type=int, default=None, help="default: 1,000,000 (cfg2)")
@@ -402,10 +402,14 @@ def main():
     list_ms = sum(s["ms_list_kernel"] for _, s in stats)
     list_cells = sum(s["list_cells"] for _, s in stats)
     list_launches = sum(s["list_launches"] for _, s in stats)
+    # per tau: the median wall time over the timed steps, the counts and phase times of the
+    # last step
     per_tau = {}
     for t, s in stats[-len(taus):]:
+        med = float(np.median([x["ms_total"] for tt, x in stats if tt == t]))
         per_tau[str(t)] = {
-            "ms": round(s["ms_total"], 3), "candidates": s["candidates"], "cells": s["cells"],
+            "ms": round(med, 3), "ms_last": round(s["ms_total"], 3),
+            "candidates": s["candidates"], "cells": s["cells"],
             "pairs": s["pairs"], "selected": s["selected"], "hits": s["hits"],
             "index_entries": s["index_entries"],
             "ms_index": round(s["ms_index"], 3), "ms_probe": round(s["ms_probe"], 3),
@@ -413,18 +417,18 @@ def main():
             "ms_verify_kernel": round(s["ms_verify_kernel"], 3),
             "shared_rows": s["shared_rows"], "shared_cells": s["shared_cells"],
             "key_collisions": s["key_collisions"],
-            "candidates_per_s": s["candidates"] / max(s["ms_total"], 1e-9) * 1e3,
+            "candidates_per_s": s["candidates"] / max(med, 1e-9) * 1e3,
             "gcups": s["cells"] / max(s["ms_verify_kernel"], 1e-9) / 1e6,
         }
 
     # end to end (host arrays in -> sorted host pairs out, as the C ABI returns them; PCIe
-    # copies included), outside the timed region: median of 3 per tau, beside the
+    # copies included), outside the timed region: median of 5 per tau, beside the
     # device-resident time of the timed steps
     end_to_end = {}
     if not args.window_bytes and not args.no_e2e:
         for t in taus:
             runs, m = [], 0
-            for _ in range(3):
+            for _ in range(5):
                 t0 = time.perf_counter()
                 hp = P.pj_self_join_host(col, t, mode=args.mode, tune_cache=cache,
                                          selection=args.selection)
