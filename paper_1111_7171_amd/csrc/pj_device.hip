@@ -377,25 +377,29 @@ __global__ __launch_bounds__(kBlock) void k_len_keys(const int32_t* __restrict__
 }
 
 // One wave per sorted position: copies the string into its padded slot of the sorted arena.
+// 2^lps_shift lanes per string, at least a quarter of the widest slot (16 when every slot is at
+// most 64 bytes: a wave packs 4 strings at once, so their dependent loads of position, offsets
+// and group base overlap; 32 up to 128 bytes; else 64)
 __global__ __launch_bounds__(kBlock) void k_pack_arena(const uint8_t* __restrict__ bytes,
                                                        const int32_t* __restrict__ offs,
                                                        const int32_t* __restrict__ perm, int64_t n,
                                                        const int32_t* __restrict__ lenstart,
                                                        const int64_t* __restrict__ gbase,
                                                        uint8_t* __restrict__ sarena,
-                                                       uint16_t* __restrict__ slen)
+                                                       uint16_t* __restrict__ slen, int lps_shift)
 {
-    const int lane = threadIdx.x & 63;
-    int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const int64_t gstep = ((int64_t)gridDim.x * kBlock) >> 6;
+    const int lps = 1 << lps_shift;
+    const int sub = threadIdx.x & (lps - 1);
+    int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> lps_shift;
+    const int64_t gstep = ((int64_t)gridDim.x * kBlock) >> lps_shift;
     for (; g < n; g += gstep) {
         int32_t id = perm[g];
         int32_t a = offs[id];
         int32_t l = offs[id + 1] - a;
         uint8_t* dst = sarena + gbase[l] + (g - lenstart[l]) * stride_of(l);
         int32_t st = (int32_t)stride_of(l);
-        for (int32_t k = lane; k < st; k += 64) dst[k] = (k < l) ? bytes[a + k] : (uint8_t)0;
-        if (lane == 0) slen[g] = (uint16_t)l;
+        for (int32_t k = sub; k < st; k += lps) dst[k] = (k < l) ? bytes[a + k] : (uint8_t)0;
+        if (sub == 0) slen[g] = (uint16_t)l;
     }
 }
 
@@ -2278,14 +2282,16 @@ hipError_t launch_iota_len_keys(const int32_t* offs, int64_t n, uint32_t* keys, 
 
 hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const int32_t* perm,
                              int64_t n, const int32_t* lenstart, const int64_t* gbase,
-                             uint8_t* sarena, uint16_t* slen, hipStream_t s)
+                             uint8_t* sarena, uint16_t* slen, int lmax, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    uint64_t waves = (uint64_t)n;
-    uint64_t blocks = (waves * 64 + kBlock - 1) / kBlock;
+    const int64_t widest = stride_of(std::max(lmax, 0));
+    const int lps_shift = widest <= 64 ? 4 : widest <= 128 ? 5 : 6;
+    const uint64_t threads = (uint64_t)n << lps_shift;
+    uint64_t blocks = (threads + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_pack_arena, dim3((unsigned)blocks), dim3(kBlock), 0, s, bytes, offs, perm,
-                       n, lenstart, gbase, sarena, slen);
+                       n, lenstart, gbase, sarena, slen, lps_shift);
     return hipGetLastError();
 }
 

@@ -466,7 +466,7 @@ void build_set(const pj_strings* S, bool on_device, Alloc& A, const std::string&
         hip_check(hipMemcpyAsync(D.perm, v1, sizeof(uint32_t) * (size_t)n,
                                  hipMemcpyDeviceToDevice, st), "perm copy");
     hip_check(launch_pack_arena(d_bytes, d_offs, D.perm, n, D.lenstart, D.gbase, D.sarena, D.slen,
-                                st), "pack_arena");
+                                D.lmax, st), "pack_arena");
 }
 
 // ------------------------------------------------------------------------------------------

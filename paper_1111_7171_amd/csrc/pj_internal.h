@@ -196,7 +196,7 @@ hipError_t launch_iota_len_keys(const int32_t* offs, int64_t n, uint32_t* keys, 
                                 hipStream_t s);
 hipError_t launch_pack_arena(const uint8_t* bytes, const int32_t* offs, const int32_t* perm,
                              int64_t n, const int32_t* lenstart, const int64_t* gbase,
-                             uint8_t* sarena, uint16_t* slen, hipStream_t s);
+                             uint8_t* sarena, uint16_t* slen, int lmax, hipStream_t s);
 // bytes present in a set's strings: bitmap (8 u32, zeroed by the caller)
 hipError_t launch_byte_presence(const DevSet& S, uint32_t* bitmap, hipStream_t s);
 hipError_t launch_emit_segments(const DevSet& S, int tau, const int64_t* ebase_dev,
