@@ -1025,7 +1025,11 @@ __device__ inline int vsp_dispatch(P r, int lr, P s, int ls, int t, int* cells)
 // STG: every lane copies its candidate's two strings into LDS slots of its own first (probe
 // string x up to kStgX - 4 bytes, indexed string y up to kStgY - 4), so the band DP reads LDS
 // instead of global memory byte by byte.  Launched for indexed strings of at most 48 bytes and
-// tau <= 8: a hit pairs x with lists of lengths within tau of |x|, so |x| <= 56.
+// tau <= 8: a hit pairs x with lists of lengths within tau of |x|, so |x| <= 56.  STG 2 is the
+// form for indexed strings of at most 40 bytes (|x| <= 48) with 52- and 44-byte slots and a
+// 128-pair buffer: 28 KB per block, 5 blocks per CU, registers held to 96 (a 104-byte spill);
+// it is taken for tau 6..8, where the fifth wave paid (the self-join of 5x10^5 medium strings:
+// 22.1 -> 21.5 ms at tau = 8), not below (2% slower at tau 2 and 4 on short strings).
 constexpr int kStgX = 60, kStgY = 52;     // slot strides: odd word counts, conflict-free
 
 // With STG the LDS slots allow 4 blocks per CU; the register budget is held to match
@@ -1035,20 +1039,23 @@ constexpr int kStgX = 60, kStgY = 52;     // slot strides: odd word counts, conf
 // tau 2..8 measured 37.5 -> 36.0 ms); the wider bands keep their registers.
 template <int GMAXW, int STG>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((STG || GMAXW <= 9) ? 4 : 1))) void k_verify_batched(VerifyParams V, Div div,
+__attribute__((amdgpu_waves_per_eu(STG == 2 ? 5 : (STG || GMAXW <= 9) ? 4 : 1))) void k_verify_batched(VerifyParams V, Div div,
                                                            const uint32_t* __restrict__ first,
                                                            uint64_t nchunks)
 {
-    __shared__ uint64_t s_acc[kWaves][kAppendCap];
-    __shared__ uint32_t s_str[kWaves][STG ? 64 * (kStgX + kStgY) / 4 : 1];
-    WaveAppender<uint64_t, kAppendCap> acc{s_acc[threadIdx.x >> 6], 0};
+    // slot strides and pair buffer: STG 2 the smaller ones (5 blocks per CU in LDS)
+    constexpr int SX = STG == 2 ? 52 : kStgX, SY = STG == 2 ? 44 : kStgY;
+    constexpr int ACAP = STG == 2 ? 128 : kAppendCap;
+    __shared__ uint64_t s_acc[kWaves][ACAP];
+    __shared__ uint32_t s_str[kWaves][STG ? 64 * (SX + SY) / 4 : 1];
+    WaveAppender<uint64_t, ACAP> acc{s_acc[threadIdx.x >> 6], 0};
     const int lane = threadIdx.x & 63;
     using LdsBytes = const __attribute__((address_space(3))) uint8_t*;
     __attribute__((address_space(3))) uint32_t* xsw =
-        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + lane * (kStgX / 4);
+        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + lane * (SX / 4);
     __attribute__((address_space(3))) uint32_t* ysw =
-        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + 64 * (kStgX / 4) +
-        lane * (kStgY / 4);
+        (__attribute__((address_space(3))) uint32_t*)(s_str[threadIdx.x >> 6]) + 64 * (SX / 4) +
+        lane * (SY / 4);
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
     uint64_t my_cells = 0, my_miss = 0;
@@ -1123,23 +1130,23 @@ __attribute__((amdgpu_waves_per_eu((STG || GMAXW <= 9) ? 4 : 1))) void k_verify_
                     const uint4* xq = reinterpret_cast<const uint4*>(x);
                     const uint4* yq = reinterpret_cast<const uint4*>(y);
 #pragma unroll
-                    for (int q = 0; q < (kStgX + 15) / 16; ++q) {
+                    for (int q = 0; q < (SX + 15) / 16; ++q) {
                         if (q * 16 < n) {
                             const uint4 v = xq[q];
-                            if (4 * q < kStgX / 4) xsw[4 * q] = v.x;
-                            if (4 * q + 1 < kStgX / 4) xsw[4 * q + 1] = v.y;
-                            if (4 * q + 2 < kStgX / 4) xsw[4 * q + 2] = v.z;
-                            if (4 * q + 3 < kStgX / 4) xsw[4 * q + 3] = v.w;
+                            if (4 * q < SX / 4) xsw[4 * q] = v.x;
+                            if (4 * q + 1 < SX / 4) xsw[4 * q + 1] = v.y;
+                            if (4 * q + 2 < SX / 4) xsw[4 * q + 2] = v.z;
+                            if (4 * q + 3 < SX / 4) xsw[4 * q + 3] = v.w;
                         }
                     }
 #pragma unroll
-                    for (int q = 0; q < (kStgY + 15) / 16; ++q) {
+                    for (int q = 0; q < (SY + 15) / 16; ++q) {
                         if (q * 16 < l) {
                             const uint4 v = yq[q];
-                            if (4 * q < kStgY / 4) ysw[4 * q] = v.x;
-                            if (4 * q + 1 < kStgY / 4) ysw[4 * q + 1] = v.y;
-                            if (4 * q + 2 < kStgY / 4) ysw[4 * q + 2] = v.z;
-                            if (4 * q + 3 < kStgY / 4) ysw[4 * q + 3] = v.w;
+                            if (4 * q < SY / 4) ysw[4 * q] = v.x;
+                            if (4 * q + 1 < SY / 4) ysw[4 * q + 1] = v.y;
+                            if (4 * q + 2 < SY / 4) ysw[4 * q + 2] = v.z;
+                            if (4 * q + 3 < SY / 4) ysw[4 * q + 3] = v.w;
                         }
                     }
                     verify((LdsBytes)(xsw), (LdsBytes)(ysw));
@@ -2471,7 +2478,10 @@ template <int W>
 static void verify_batched_w(const VerifyParams& V, const uint32_t* first, uint64_t nchunks,
                              int grid, hipStream_t s)
 {
-    if (W == 9 && V.tau <= 8 && V.y_maxlen <= kStgY - 4)
+    if (W == 9 && V.tau >= 6 && V.tau <= 8 && V.y_maxlen <= 40)
+        hipLaunchKernelGGL((k_verify_batched<W, (W == 9 ? 2 : 0)>), dim3(grid), dim3(kBlock), 0,
+                           s, V, make_div(V.tau + 1), first, nchunks);
+    else if (W == 9 && V.tau <= 8 && V.y_maxlen <= kStgY - 4)
         hipLaunchKernelGGL((k_verify_batched<W, (W == 9 ? 1 : 0)>), dim3(grid), dim3(kBlock), 0,
                            s, V, make_div(V.tau + 1), first, nchunks);
     else
