@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pj_internal.h"
 #include "pj_device_common.h"
@@ -1915,7 +1916,9 @@ __device__ inline void cont_chunk(const VerifyParams& V, const Div& div, int sid
     LongRec rec;
     rec.a = make_uint4(0u, 0u, 0u, 0u);
     rec.b = rec.a;
-    int M[MAXW];
+    int M[MAXW];                                          // every lane runs the row loop
+#pragma unroll
+    for (int q = 0; q < MAXW; ++q) M[q] = BIG;
     int row = 0, nr = 0, nc = 0, a = 0, b = 0, st = 0;    // st: 0 running, 1 pass, 2 fail, 3 none
     const uint8_t* A = nullptr;
     const uint8_t* B = nullptr;
@@ -2007,43 +2010,67 @@ __device__ inline void cont_chunk(const VerifyParams& V, const Div& div, int sid
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (running) {
+        {
+            // every lane runs the rows of the sub-block, so the loop's control flow stays
+            // wave-uniform (a lane's own exit would make the compiler copy the band and the
+            // window at every row); a lane that is not running, or stops, computes rows whose
+            // values are never used, and its reads stay inside its stage (ncs = 0: no column
+            // byte is read)
+            const int ncs = running ? nc : 0;
             // byte q of the lane's A blocks / B blocks (lane-interleaved 16-byte blocks)
             auto sa = [&](int q) -> int { return (int)stage8[((q >> 4) * 64) * 16 + (q & 15)]; };
             auto sb = [&](int ib) -> int {             // B[ib], 256 outside B
                 const int q = oB + ib - ib0;
-                return ((unsigned)ib < (unsigned)nc)
+                return ((unsigned)ib < (unsigned)ncs)
                            ? (int)stage8[((kStageA + (q >> 4)) * 64) * 16 + (q & 15)] : 256;
             };
-            int w[MAXW];
+            // the window of rows r and r + 1: w[q] = B[rowstart + r - a + q], q <= MAXW (rows
+            // taken in pairs, so the window shifts by two every second row)
+            int w[MAXW + 1];
 #pragma unroll
-            for (int q = 0; q < MAXW; ++q) w[q] = sb(row - a + q);
+            for (int q = 0; q <= MAXW; ++q) w[q] = sb(row - a + q);
             const int rowstart = row;
-            for (int r = 0; r < Ks && row < nr; ++r) {
+            bool live = running;                       // the lane's rows still count
+            // row r of the sub-block on the window w[O .. O + MAXW); false once no lane counts
+            auto step = [&](int r, auto o) -> bool {
+                constexpr int O = decltype(o)::value;
                 const int ai = sa(oA + r);
                 int left = BIG, emin = BIG;
 #pragma unroll
                 for (int q = 0; q < MAXW; ++q) {
                     const int up = (q + 1 < MAXW) ? M[(q + 1) < MAXW ? q + 1 : q] : BIG;
-                    const int dg = M[q] + ((ai != w[q]) ? 1 : 0);
-                    const int v = min(min(up, left) + 1, dg);
+                    // min(up + 1, left + 1, diagonal + [mismatch]) as one three-way min of
+                    // up, left and diagonal - [match], plus one
+                    const int dm = M[q] - ((ai == w[q + O]) ? 1 : 0);
+                    const int v = min(min(up, left), dm) + 1;
                     M[q] = v;
                     left = v;
                     const uint32_t ub = (uint32_t)b, uq = (uint32_t)q;
                     emin = min(emin, (int)(max(ub, uq) - min(ub, uq) + (uint32_t)v));
                 }
-                row = rowstart + r + 1;
-                if (emin > t) { st = 2; break; }
-                if (row == nr) {
-                    int out = BIG;
+                const int nrow = rowstart + r + 1;
+                const bool fail = emin > t;            // Lemma 4: stop, return t + 1
+                const bool last = nrow == nr;
+                row = live ? nrow : row;
+                // the final cell (band index b) only on a row where some lane ends
+                int out = BIG;
+                if (__ballot(live && !fail && last)) {
 #pragma unroll
                     for (int q = 0; q < MAXW; ++q) out = (q == b) ? M[q] : out;
-                    st = out <= t ? 1 : 2;
-                    break;
                 }
+                const int nst = fail ? 2 : last ? (out <= t ? 1 : 2) : 0;
+                st = live ? nst : st;
+                live = live && nst == 0;
+                return __ballot(live) != 0;
+            };
+            for (int r = 0; r < Ks; r += 2) {
+                if (!step(r, std::integral_constant<int, 0>{})) break;
+                if (r + 1 >= Ks || !step(r + 1, std::integral_constant<int, 1>{})) break;
+                if (r + 2 >= Ks) break;
 #pragma unroll
-                for (int q = 0; q + 1 < MAXW; ++q) w[q] = w[q + 1];
-                w[MAXW - 1] = sb(rowstart - a + MAXW + r);
+                for (int q = 0; q + 1 < MAXW; ++q) w[q] = w[q + 2];
+                w[MAXW - 1] = sb(rowstart - a + MAXW + r + 1);
+                w[MAXW] = sb(rowstart - a + MAXW + r + 2);
             }
             running = st == 0;
         }
