@@ -2118,22 +2118,42 @@ __device__ inline void cont_chunk(const VerifyParams& V, const Div& div, int sid
     }
 }
 
-// One pass over the tasks of every slot: fresh tasks (fin, counts cnt) or continuing ones (cin,
-// counts cnt); continuing tasks go to cout (counts cout_cnt); side 0's passing tasks to rout
-// (counts rout_cnt).  Regions of every queue start at off[slot].
-__global__ __launch_bounds__(64) void k_verify_cont(VerifyParams V, Div div, int side, int fresh,
-                                                    int K, const LongRec* __restrict__ fin,
-                                                    const ContRec* __restrict__ cin,
-                                                    const uint32_t* __restrict__ cnt,
-                                                    const uint32_t* __restrict__ off,
-                                                    ContRec* __restrict__ cout,
-                                                    uint32_t* __restrict__ cout_cnt,
-                                                    LongRec* __restrict__ rout,
-                                                    uint32_t* __restrict__ rout_cnt,
-                                                    uint32_t* __restrict__ zero_cnt)
+// One pass over the tasks of both sides, so that a candidate's right part starts in the pass
+// after its left part passes and runs beside the other candidates' left parts.  Three groups of
+// tasks, each in per-slot regions that start at off[slot]:
+//  0: left parts (side 0), fresh from fin_l (counts cnt_l; the first pass) or continuing from
+//     cin_l (counts cnt_l); cnt_l null when no left part is left;
+//  1: right parts new in this pass: fin_r[lo_r[slot], hi_r[slot]) (lo_r null: none);
+//  2: right parts continuing from cin_r (counts cnt_r; null: none).
+// Continuing tasks go to cout_l / cout_r (counts cout_l_cnt / cout_r_cnt); left parts that pass
+// are appended to rout (counts rout_cnt), right parts that pass to the pair buffer.
+struct ContPass {
+    const LongRec* fin_l;
+    const ContRec* cin_l;
+    const uint32_t* cnt_l;
+    const LongRec* fin_r;
+    const uint32_t* lo_r;
+    const uint32_t* hi_r;
+    const ContRec* cin_r;
+    const uint32_t* cnt_r;
+    const uint32_t* off;
+    ContRec* cout_l;
+    uint32_t* cout_l_cnt;
+    ContRec* cout_r;
+    uint32_t* cout_r_cnt;
+    LongRec* rout;
+    uint32_t* rout_cnt;
+    uint32_t* zero_l;        // count buffers the next pass writes (read by the previous pass
+    uint32_t* zero_r;        // only): cleared here
+    int K;
+};
+
+__global__ __launch_bounds__(64) void k_verify_cont(VerifyParams V, Div div, ContPass P)
 {
-    // the counts the next pass writes: read by the previous pass only, so clear now
-    if (blockIdx.x == 0 && zero_cnt) zero_cnt[threadIdx.x] = 0u;
+    if (blockIdx.x == 0) {
+        if (P.zero_l) P.zero_l[threadIdx.x] = 0u;
+        if (P.zero_r) P.zero_r[threadIdx.x] = 0u;
+    }
     __shared__ uint64_t s_acc[kAppendCap];
     __shared__ uint4 s_stage[(kStageA + kStageB) * 64];
     WaveAppender<uint64_t, kAppendCap> acc{s_acc, 0};
@@ -2141,22 +2161,38 @@ __global__ __launch_bounds__(64) void k_verify_cont(VerifyParams V, Div div, int
     __attribute__((address_space(3))) uint32_t* stage =
         (__attribute__((address_space(3))) uint32_t*)s_stage + 4 * lane;
     uint64_t my_cells = 0, my_miss = 0;
-    const uint32_t c = lane <= V.tau ? cnt[lane] : 0u;
-    const uint32_t nch = (c + 63u) / 64u;
-    const uint32_t incl = wave_incl_scan(nch);
-    const uint32_t total = __shfl(incl, 63, 64);
+    // chunks of 64 tasks: group 0's slots, then group 1's, then group 2's (lane = slot)
+    const bool sl = lane <= V.tau;
+    const uint32_t c0 = (sl && P.cnt_l) ? P.cnt_l[lane] : 0u;
+    const uint32_t c1 = (sl && P.lo_r) ? P.hi_r[lane] - P.lo_r[lane] : 0u;
+    const uint32_t c2 = (sl && P.cnt_r) ? P.cnt_r[lane] : 0u;
+    const uint32_t n0 = (c0 + 63u) / 64u, n1 = (c1 + 63u) / 64u, n2 = (c2 + 63u) / 64u;
+    const uint32_t i0 = wave_incl_scan(n0), i1 = wave_incl_scan(n1), i2 = wave_incl_scan(n2);
+    const uint32_t T0 = __shfl(i0, 63, 64), T1 = __shfl(i1, 63, 64), T2 = __shfl(i2, 63, 64);
+    const uint32_t total = T0 + T1 + T2;
     for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
-        const int slot = __popcll(__ballot(incl <= ch));
+        const int g = ch < T0 ? 0 : (ch < T0 + T1 ? 1 : 2);
+        const uint32_t loc = g == 0 ? ch : (g == 1 ? ch - T0 : ch - T0 - T1);
+        const uint32_t incl = g == 0 ? i0 : (g == 1 ? i1 : i2);
+        const uint32_t nch = g == 0 ? n0 : (g == 1 ? n1 : n2);
+        const uint32_t cc = g == 0 ? c0 : (g == 1 ? c1 : c2);
+        const int slot = __popcll(__ballot(incl <= loc));
         const uint32_t first = __shfl(incl - nch, slot, 64);
-        const uint32_t cs = __shfl(c, slot, 64);
-        const uint32_t base = off[slot];
-        const uint32_t b0 = (ch - first) * 64u;
+        const uint32_t cs = __shfl(cc, slot, 64);
+        const uint32_t base = P.off[slot];
+        const uint32_t b0 = (loc - first) * 64u;
         const uint32_t b1 = min(b0 + 64u, cs);
+        const int side = g == 0 ? 0 : 1;
+        const bool fresh = g == 0 ? P.cin_l == nullptr : g == 1;
+        const LongRec* fi = g == 0 ? (fresh ? P.fin_l + base : nullptr)
+                                   : (g == 1 ? P.fin_r + base + P.lo_r[slot] : nullptr);
+        const ContRec* ci = g == 0 ? (fresh ? nullptr : P.cin_l + base)
+                                   : (g == 2 ? P.cin_r + base : nullptr);
+        ContRec* cout = side == 0 ? P.cout_l : P.cout_r;
+        uint32_t* cout_cnt = side == 0 ? P.cout_l_cnt : P.cout_r_cnt;
         const int t = side == 0 ? slot : V.tau - slot;
-        const LongRec* fi = fin ? fin + base : nullptr;
-        const ContRec* ci = cin ? cin + base : nullptr;
-#define PJ_CONT(W) cont_chunk<W>(V, div, side, slot, fresh != 0, fi, ci, b0, b1, K, cout,        \
-                                 cout_cnt, rout, rout_cnt, base, stage, acc, my_cells, my_miss)
+#define PJ_CONT(W) cont_chunk<W>(V, div, side, slot, fresh, fi, ci, b0, b1, P.K, cout, cout_cnt,  \
+                                 P.rout, P.rout_cnt, base, stage, acc, my_cells, my_miss)
         if (t + 1 <= 5) PJ_CONT(5);
         else if (t + 1 <= 9) PJ_CONT(9);
         else if (t + 1 <= 13) PJ_CONT(13);
@@ -2167,7 +2203,7 @@ __global__ __launch_bounds__(64) void k_verify_cont(VerifyParams V, Div div, int
         else PJ_CONT(33);
 #undef PJ_CONT
     }
-    if (side == 1) acc.flush(V.out, V.out_cap, &V.counters[3]);
+    acc.flush(V.out, V.out_cap, &V.counters[3]);
     my_cells = wave_sum(my_cells);
     my_miss = wave_sum(my_miss);
     if (lane == 0) {
@@ -2680,13 +2716,21 @@ hipError_t launch_run_lengths(const uint32_t* runstart, uint32_t nruns, uint32_t
     return hipGetLastError();
 }
 
+// count arrays of 256 u32: slot counts, offsets, cursors, right tasks, three left and three right
+// continuation counts, two snapshots of the right-task counts
+constexpr int kLongCounts = 12;
+
 size_t long_scratch_bytes(uint64_t ncand)
 {
     const uint64_t rc = (ncand * sizeof(LongRec) + 255) & ~(uint64_t)255;
     const uint64_t cc = (ncand * sizeof(ContRec) + 255) & ~(uint64_t)255;
-    // counts: slot, offsets, cursor, right, three continuation counts (256 u32 each);
-    // candidates, right tasks, two continuation queues
-    return 7 * 256 * sizeof(uint32_t) + 2 * rc + 2 * cc;
+    // candidates, right tasks, two left and two right continuation queues
+    return kLongCounts * 256 * sizeof(uint32_t) + 2 * rc + 4 * cc;
+}
+
+__global__ void k_copy_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, int n)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
 hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_rows, void* scratch,
@@ -2699,14 +2743,17 @@ hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_row
     uint32_t* off = slot_cnt + 256;
     uint32_t* cursor = off + 256;
     uint32_t* right_cnt = cursor + 256;
-    uint32_t* cont_cnt[3] = {right_cnt + 256, right_cnt + 512, right_cnt + 768};
+    uint32_t* cl[3] = {right_cnt + 256, right_cnt + 512, right_cnt + 768};
+    uint32_t* cr[3] = {right_cnt + 1024, right_cnt + 1280, right_cnt + 1536};
+    uint32_t* snap[2] = {right_cnt + 1792, right_cnt + 2048};
     const uint64_t rc = (ncand * sizeof(LongRec) + 255) & ~(uint64_t)255;
     const uint64_t cc = (ncand * sizeof(ContRec) + 255) & ~(uint64_t)255;
-    uint8_t* q = p + 7 * 256 * sizeof(uint32_t);
+    uint8_t* q = p + kLongCounts * 256 * sizeof(uint32_t);
     LongRec* cands = (LongRec*)q;
     LongRec* right = (LongRec*)(q + rc);
-    ContRec* cont[2] = {(ContRec*)(q + 2 * rc), (ContRec*)(q + 2 * rc + cc)};
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, slot_cnt, 7 * 256, 0u);
+    ContRec* cont_l[2] = {(ContRec*)(q + 2 * rc), (ContRec*)(q + 2 * rc + cc)};
+    ContRec* cont_r[2] = {(ContRec*)(q + 2 * rc + 2 * cc), (ContRec*)(q + 2 * rc + 3 * cc)};
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, slot_cnt, kLongCounts * 256, 0u);
     const unsigned hb = (unsigned)std::min<uint64_t>(blocks_for(V.nhits), 4096);
     hipLaunchKernelGGL(k_long_slot_counts, dim3(hb), dim3(kBlock), 0, s, V.hits, V.nhits, slot_cnt);
     hipLaunchKernelGGL(k_long_slot_offsets, dim3(1), dim3(64), 0, s, slot_cnt, off, cursor);
@@ -2714,11 +2761,8 @@ hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_row
                        V.nhits, V.vals, V.x_slen, V.x_lenstart, V.x_gbase, V.y_lenstart,
                        V.y_gbase, cursor, cands);
     const Div div = make_div(V.tau + 1);
-    // three count buffers in rotation: pass j reads cnt[j % 3], writes cnt[(j + 1) % 3] and
-    // clears cnt[(j + 2) % 3] (read by pass j - 1); the first two start cleared
-    // pass lengths: 16, 16, 32, 64, ..., 512 rows until every part's rows are covered;
-    // PJ_LONG_PASSES (a comma list, the last entry repeated) sets them (tests and tuning; it
-    // changes no result)
+    // pass lengths: 16, 16, 32, 64, ..., 512 rows; PJ_LONG_PASSES (a comma list, the last entry
+    // repeated) sets them (tests and tuning; it changes no result)
     int sched[16], nsched = 0;
     if (const char* e = getenv("PJ_LONG_PASSES")) {
         for (const char* c = e; *c && nsched < 16;) {
@@ -2729,31 +2773,50 @@ hipError_t launch_verify_long(const VerifyParams& V, uint64_t ncand, int max_row
             if (*c == ',') ++c;
         }
     }
-    for (int side = 0; side < 2; ++side) {
-        int done = 0, pass = 0;
-        while (true) {
-            const int K = nsched ? sched[pass < nsched ? pass : nsched - 1]
-                                 : (pass == 0 ? 16 : std::min(512, 16 << (pass - 1)));
-            const bool fresh = pass == 0;
-            uint32_t* cin_cnt = cont_cnt[pass % 3];
-            uint32_t* cout_cnt = cont_cnt[(pass + 1) % 3];
-            uint32_t* zero = cont_cnt[(pass + 2) % 3];
-            hipLaunchKernelGGL(k_verify_cont, dim3(grid), dim3(64), 0, s, V, div, side,
-                               fresh ? 1 : 0, K,
-                               fresh ? (side == 0 ? (const LongRec*)cands : (const LongRec*)right)
-                                     : (const LongRec*)nullptr,
-                               fresh ? (const ContRec*)nullptr : (const ContRec*)cont[pass % 2],
-                               (const uint32_t*)(fresh ? (side == 0 ? slot_cnt : right_cnt)
-                                                       : cin_cnt),
-                               (const uint32_t*)off, cont[(pass + 1) % 2], cout_cnt, right,
-                               right_cnt, zero);
-            done += K;
-            ++pass;
-            if (done >= max_rows) break;
+    // Pass j runs the left parts (until every left part has had max_rows rows), the right parts
+    // appended by passes before j (the range between the snapshots of the right-task counts taken
+    // before passes j - 1 and j) and the right parts continuing from pass j - 1; it ends when the
+    // right parts appended by the last left pass have had max_rows rows.  Continuation counts
+    // rotate over three buffers per side: pass j reads c[j % 3], writes c[(j + 1) % 3] (cleared
+    // by pass j - 1, or at the start) and clears c[(j + 2) % 3] (read by pass j - 1).
+    bool left = true;
+    int done_l = 0, done_r = 0;
+    for (int pass = 0;; ++pass) {
+        const int K = nsched ? sched[pass < nsched ? pass : nsched - 1]
+                             : (pass == 0 ? 16 : std::min(512, 16 << (pass - 1)));
+        if (pass > 0)
+            hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(256), 0, s, snap[pass % 2], right_cnt, 256);
+        ContPass P{};
+        if (left) {
+            P.fin_l = pass == 0 ? cands : nullptr;
+            P.cin_l = pass == 0 ? nullptr : cont_l[pass % 2];
+            P.cnt_l = pass == 0 ? slot_cnt : cl[pass % 3];
+            P.cout_l = cont_l[(pass + 1) % 2];
+            P.cout_l_cnt = cl[(pass + 1) % 3];
+            P.zero_l = cl[(pass + 2) % 3];
+            P.rout = right;
+            P.rout_cnt = right_cnt;
         }
-        // the next side starts with its first two count buffers cleared: the last pass left
-        // cnt[pass % 3] (written, now drained to zero tasks) and cleared cnt[(pass + 1) % 3]
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, cont_cnt[0], 3 * 256, 0u);
+        if (pass > 0) {
+            P.fin_r = right;
+            P.lo_r = snap[(pass + 1) % 2];      // snap[0] is zero before pass 2
+            P.hi_r = snap[pass % 2];
+            P.cin_r = cont_r[pass % 2];
+            P.cnt_r = cr[pass % 3];
+        }
+        P.cout_r = cont_r[(pass + 1) % 2];
+        P.cout_r_cnt = cr[(pass + 1) % 3];
+        P.zero_r = cr[(pass + 2) % 3];
+        P.off = off;
+        P.K = K;
+        hipLaunchKernelGGL(k_verify_cont, dim3(grid), dim3(64), 0, s, V, div, P);
+        if (left) {
+            done_l += K;
+            if (done_l >= max_rows) left = false;
+        } else {
+            done_r += K;
+            if (done_r >= max_rows) break;
+        }
     }
     return hipGetLastError();
 }
