@@ -605,6 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_keys(const uint64_t* __restri
 // probe strings) or, with XMAJ, pair-major over blocks of 64 probe strings (a wave's lanes are
 // 64 consecutive probe strings with one (l, i) pair: windows of one size when the strings have
 // a few pairs each).
+constexpr int kProbeStep = 2;      // window positions a probe thread takes per step
+
 template <bool XMAJ>
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
 {
@@ -732,36 +734,80 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
             fm = fdir[g + 1] - fb - 1u;
         }
         // the window has at most tau+1 positions for multi-match, more for the other methods;
-        // the loop ends when no lane of the wave has a position left
-        for (int s = 0;; ++s) {
-            const int p = lo + s;
-            const bool active = valid && p <= hi;
-            if (__ballot(active) == 0) break;
-            uint32_t start = 0, count = 0;
-            if (active) {
-                const int w0 = p - 1;
-                if (s == 0) {
-                    h = 0;
-                    if (sg.len <= exact_len)
-                        for (int k = 0; k < sg.len; ++k) h = (h << sym_bits) | (uint64_t)s_sym[rd(w0 + k)];
-                    else
-                        for (int k = 0; k < sg.len; ++k) h = h * kHashBase + (uint64_t)rd(w0 + k) + 1ull;
-                } else {
-                    h = roll_code(h, sg.len, rd(w0 - 1), rd(w0 + sg.len - 1), top, s_sym, sym_bits,
-                                  exact_len);
+        // the loop ends when no lane of the wave has a position left.  kProbeStep positions per
+        // step: their bytes are read first, then their keys computed, then their filter words
+        // (or, without a filter, their first table slots) read together, so a step waits on one
+        // round trip per kind of read instead of one per position; hits are appended in position
+        // order as before.
+        for (int s0 = 0;; s0 += kProbeStep) {
+            if (__ballot(valid && lo + s0 <= hi) == 0) break;
+            bool act[kProbeStep];
+            int outb[kProbeStep], inb[kProbeStep];
+#pragma unroll
+            for (int u = 0; u < kProbeStep; ++u) {
+                const int p = lo + s0 + u;
+                act[u] = valid && p <= hi;
+                outb[u] = 0;
+                inb[u] = 0;
+                if (act[u] && s0 + u > 0) {              // the bytes leaving and entering x[p, l_i]
+                    outb[u] = rd(p - 2);
+                    inb[u] = rd(p - 2 + sg.len);
                 }
-                const uint64_t key = make_key(l, i, tau, sg.len, h, exact_len);
-                // hashed segments and long exact codes rarely match: the group's filter block
-                // (one cache line for a group of up to 64 lists, read again by the lane at every
-                // position of its window) turns most of those lookups away before the table read
-                bool maybe = true;
-                if (use_filter) {
-                    const uint64_t hs = table_slot(key);
-                    const uint32_t fbits = filter_bits(hs);
-                    maybe = (filter[fb + filter_word_in(hs, fm)] & fbits) == fbits;
+            }
+            uint64_t key[kProbeStep], hs[kProbeStep];
+#pragma unroll
+            for (int u = 0; u < kProbeStep; ++u) {
+                key[u] = 0;
+                hs[u] = 0;
+                if (act[u]) {
+                    if (s0 + u == 0) {
+                        const int w0 = lo - 1;
+                        h = 0;
+                        if (sg.len <= exact_len)
+                            for (int k = 0; k < sg.len; ++k) h = (h << sym_bits) | (uint64_t)s_sym[rd(w0 + k)];
+                        else
+                            for (int k = 0; k < sg.len; ++k) h = h * kHashBase + (uint64_t)rd(w0 + k) + 1ull;
+                    } else {
+                        h = roll_code(h, sg.len, (uint8_t)outb[u], (uint8_t)inb[u], top, s_sym,
+                                      sym_bits, exact_len);
+                    }
+                    key[u] = make_key(l, i, tau, sg.len, h, exact_len);
+                    hs[u] = table_slot(key[u]);
                 }
-                if (maybe && table_lookup(table, mask, key, &start, &count)) {
-                    if (P.self && l == n) {
+            }
+            // hashed segments and long exact codes rarely match: the group's filter block (one
+            // cache line for a group of up to 64 lists, read again by the lane at every position
+            // of its window) turns most of those lookups away before the table read
+            uint32_t fw[kProbeStep];
+#pragma unroll
+            for (int u = 0; u < kProbeStep; ++u) {
+                fw[u] = 0;
+                if (act[u] && use_filter) fw[u] = filter[fb + filter_word_in(hs[u], fm)];
+            }
+            bool maybe[kProbeStep];
+            uint4 tv[kProbeStep];
+#pragma unroll
+            for (int u = 0; u < kProbeStep; ++u) {
+                const uint32_t fbits = filter_bits(hs[u]);
+                maybe[u] = act[u] && (!use_filter || (fw[u] & fbits) == fbits);
+                tv[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (maybe[u]) tv[u] = table[hs[u] & mask];
+            }
+#pragma unroll
+            for (int u = 0; u < kProbeStep; ++u) {
+                uint32_t start = 0, count = 0;
+                if (maybe[u]) {
+                    const uint64_t k = (uint64_t)tv[u].x | ((uint64_t)tv[u].y << 32);
+                    bool hit = false;
+                    if (k == key[u]) {
+                        start = tv[u].z;
+                        count = tv[u].w;
+                        hit = true;
+                    } else if (k != kEmptyKey) {
+                        hit = table_lookup_from(table, mask, key[u], ((hs[u] & mask) + 1) & mask,
+                                                &start, &count);
+                    }
+                    if (hit && P.self && l == n) {
                         // keep members with g < gx (lists are ascending in g)
                         uint32_t a = 0, b = count;
                         while (a < b) {
@@ -770,16 +816,16 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams P, Div div)
                         }
                         count = a;
                     }
-                } else {
-                    count = 0;
+                    if (!hit) count = 0;
                 }
+                const int p = lo + s0 + u;
+                const bool found = act[u] && count > 0;
+                Hit hh;
+                hh.gx = gx; hh.start = start; hh.count = count;
+                hh.meta = (uint32_t)(p - 1) | ((uint32_t)(i - 1) << 11) | ((uint32_t)l << 17);
+                app.push(found, hh, P.hits, P.hit_cap, &P.counters[0]);
+                if (found) my_cand += count;
             }
-            const bool found = active && count > 0;
-            Hit hh;
-            hh.gx = gx; hh.start = start; hh.count = count;
-            hh.meta = (uint32_t)(p - 1) | ((uint32_t)(i - 1) << 11) | ((uint32_t)l << 17);
-            app.push(found, hh, P.hits, P.hit_cap, &P.counters[0]);
-            if (found) my_cand += count;
         }
     }
     app.flush(P.hits, P.hit_cap, &P.counters[0]);

@@ -175,6 +175,24 @@ __device__ inline uint32_t filter_word_in(uint64_t h, uint32_t block_mask)
     return (uint32_t)(h >> 45) & block_mask;
 }
 
+// The open-addressing lookup from a given slot on (linear probing).
+__device__ inline bool table_lookup_from(const uint4* __restrict__ table, uint64_t mask,
+                                         uint64_t key, uint64_t slot, uint32_t* start,
+                                         uint32_t* count)
+{
+    while (true) {
+        const uint4 v = table[slot];
+        const uint64_t k = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        if (k == key) {
+            *start = v.z;
+            *count = v.w;
+            return true;
+        }
+        if (k == kEmptyKey) return false;
+        slot = (slot + 1) & mask;
+    }
+}
+
 __device__ inline bool table_lookup(const uint4* __restrict__ table, uint64_t mask, uint64_t key,
                                     uint32_t* start, uint32_t* count)
 {
