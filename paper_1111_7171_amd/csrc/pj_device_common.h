@@ -137,7 +137,16 @@ __device__ inline uint64_t seg_code(const uint8_t* w, int len, const uint16_t* s
     if (len <= exact_len) {
         for (int k = 0; k < len; ++k) h = (h << bits) | (uint64_t)sym[w[k]];
     } else {
-        for (int k = 0; k < len; ++k) h = h * kHashBase + (uint64_t)w[k] + 1ull;
+        // eight bytes read before they enter the hash, so a segment waits on len / 8 reads
+        int k = 0;
+        for (; k + 8 <= len; k += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = w[k + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) h = h * kHashBase + (uint64_t)c[u] + 1ull;
+        }
+        for (; k < len; ++k) h = h * kHashBase + (uint64_t)w[k] + 1ull;
     }
     return h;
 }
